@@ -1,0 +1,227 @@
+"""Benchmark of the Zoom-SVD hot path on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input:
+  storage phase  zs_store_blocks  on A (1,000,000 x 128 float64, b = 1000, k = 20)
+  query phase    zs_query_batch   on 1,024 ranges of exactly 320,000 rows, k_q = 20.
+Inputs are resident in HBM before the timed region starts.
+
+Printed as one JSON line:
+  value       range-query SVDs/s of the batched query phase (1,024 / query time)
+  p50/p99     latency of single queries (zs_query, one at a time) of 320,000 rows
+  store_gbps  storage-phase throughput, t * c * 8 bytes / store time
+  roofline    the dominant kernel against its roofline (HIP events on the
+              library's stream, over the timed steps)
+  cpu_baseline the CPU oracle timed on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "sinmix_1m_x128_f64"
+QUERY_LEN = 320_000
+N_QUERIES = 1024
+HBM_PEAK_GBPS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--queries", type=int, default=N_QUERIES)
+    ap.add_argument("--latency-samples", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-queries", type=int, default=32)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1805_00754_amd import synth
+    from paper_1805_00754_amd import zoomsvd as zs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    zs.load()
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+
+    log("generating %s" % WORKLOAD)
+    ser, cfg = synth.workload(WORKLOAD)
+    A_host = ser.A
+    t, c = A_host.shape
+    b, k = cfg["b"], cfg["k"]
+    ts, te = synth.queries_fixed(ser.rng, t, args.queries, QUERY_LEN)
+    kq = np.full(args.queries, k, np.int32)
+    A = torch.from_numpy(A_host).to(dev)
+    torch.cuda.synchronize()
+
+    # Output buffers of the batch are allocated once, outside the timed region.
+    st0 = zs.zs_store_blocks(A, b, k)
+    out = zs.Batch(st0, ts, te, kq, dev)
+    st0.free()
+
+    def step(timing_events=None):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st = zs.zs_store_blocks(A, b, k)        # synchronises the stream at its end
+        e1.record(stream)
+        zs.zs_query_batch(st, ts, te, kq, out=out)
+        e2.record(stream)
+        e2.synchronize()
+        return st, e0.elapsed_time(e1), e1.elapsed_time(e2)
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        st, _, _ = step()
+        zs.zs_sync_status(st)
+        st.free()
+
+    zs.zs_timing_reset()
+    zs.zs_timing_enable(True)
+    torch.cuda.synchronize()
+    store_ms, query_ms = [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        st, sm, qm = step()
+        store_ms.append(sm)
+        query_ms.append(qm)
+        if i + 1 < args.steps:
+            st.free()
+        log("step %d: store %.2f ms  query batch %.2f ms" % (i, sm, qm))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    zs.zs_timing_enable(False)
+    kernels = {}
+    for name in ("gram", "eig", "project", "finalize", "utransform", "partial", "gather", "coef",
+                 "blockprod"):
+        n, ms = zs.zs_timing_get(name)
+        if n:
+            kernels[name] = {"launches": n, "total_ms": ms, "avg_ms": ms / n}
+    zs.zs_sync_status(st)
+
+    # Single-query latency (queries issued one at a time).
+    lat = []
+    U1 = torch.empty((QUERY_LEN, k), dtype=torch.float64, device=dev)
+    S1 = torch.empty(k, dtype=torch.float64, device=dev)
+    V1 = torch.empty((c, k), dtype=torch.float64, device=dev)
+    ko = torch.empty(1, dtype=torch.int32, device=dev)
+    for q in range(min(args.latency_samples + 4, args.queries)):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        zs.zs_query(st, int(ts[q]), int(te[q]), k, U1, S1, V1, ko)
+        torch.cuda.synchronize()
+        if q >= 4:
+            lat.append((time.perf_counter() - a) * 1e3)
+    st.free()
+
+    q_ms = float(np.mean(query_ms))
+    s_ms = float(np.mean(store_ms))
+    value = args.queries / (q_ms / 1e3)
+    store_gbps = t * c * 8 / (s_ms / 1e3) / 1e9
+
+    # Roofline of the dominant kernel (largest share of the timed region).
+    n_rows = int((te - ts).sum())
+    pieces = int(sum((int(e) - 1) // b - int(s) // b + 1 for s, e in zip(ts, te)))
+    algo = {
+        # U rows read (k) + output rows written (k_q) + coefficient blocks read
+        "blockprod": ("hbm", 8.0 * (n_rows * k + n_rows * k + pieces * k * k), "GB/s"),
+        # A read once
+        "gram": ("hbm", 8.0 * t * c, "GB/s"),
+        "project": ("hbm", 8.0 * (t * c + t * k), "GB/s"),
+    }
+    dom = max(kernels, key=lambda n: kernels[n]["total_ms"])
+    roof = None
+    if dom in algo:
+        bound, amount, unit = algo[dom]
+        avg_s = kernels[dom]["avg_ms"] / 1e3
+        achieved = amount / avg_s / 1e9
+        roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                "unit": unit, "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                "algorithmic_bytes_per_launch": amount}
+    else:
+        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": None, "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(A_host, b, k, ts, te, args.cpu_queries)
+
+    res = {
+        "metric": "range-query SVDs/s + p50/p99 latency at 3.2e5-row ranges; store-phase GB/s",
+        "value": value,
+        "unit": "SVDs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "t": t, "c": c, "b": b, "k": k,
+                   "queries": args.queries, "query_rows": QUERY_LEN, "k_q": k,
+                   "parallelism": "single-gpu"},
+        "query_batch_ms": q_ms,
+        "store_ms": s_ms,
+        "store_gbps": store_gbps,
+        "store_frac_hbm": store_gbps / HBM_PEAK_GBPS,
+        "p50_ms": float(np.percentile(lat, 50)) if lat else None,
+        "p99_ms": float(np.percentile(lat, 99)) if lat else None,
+        "single_query_svds_per_s": 1e3 / float(np.mean(lat)) if lat else None,
+        "kernels_ms_per_step": {n: v["total_ms"] / args.steps for n, v in kernels.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(A, b, k, ts, te, nq):
+    """The oracle as it stands, on a bounded sample: store the blocks that a
+    sample of the benchmark's queries touch, then answer those queries."""
+    import numpy as np
+
+    import oracle
+
+    oracle.load()
+    cores = oracle.max_threads()
+    # Sample: the first nq queries, re-based onto the span of rows they cover.
+    ts = np.asarray(ts[:nq], np.int64)
+    te = np.asarray(te[:nq], np.int64)
+    lo_blk = int(ts.min()) // b
+    hi_blk = (int(te.max()) - 1) // b + 1
+    Asub = np.ascontiguousarray(A[lo_blk * b:min(hi_blk * b, A.shape[0])])
+    a = time.perf_counter()
+    st = oracle.store(Asub, b, k)
+    store_s = time.perf_counter() - a
+    a = time.perf_counter()
+    oracle.query_batch(st, ts - lo_blk * b, te - lo_blk * b, k)
+    query_s = time.perf_counter() - a
+    return {"value": nq / query_s, "unit": "SVDs/s", "cores": cores, "kind": "oracle",
+            "sample": "%d queries of %d rows over %d stored blocks (%d x %d f64); store %.2f s "
+                      "(%.3f GB/s), queries %.2f s" % (nq, int(te[0] - ts[0]), st.nb,
+                                                        Asub.shape[0], Asub.shape[1], store_s,
+                                                        Asub.nbytes / store_s / 1e9, query_s),
+            "store_gbps": Asub.nbytes / store_s / 1e9}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,151 @@
+/*
+ * zoomsvd.h -- C ABI of the MI355X (gfx950) Zoom-SVD library.
+ *
+ * Zoom-SVD (Jang, Choi, Jung, Kang; arXiv 1805.00754) answers "what is the SVD
+ * of the rows [t_s, t_e) of a t x c multivariate time series A?" without
+ * keeping A.  The storage phase (Sec. 3.2, Alg. 1, Def. 1-2) compresses every
+ * b-row block A_(i) into its rank-k SVD U_(i) Sigma_(i) V_(i)^T.  The query
+ * phase (Sec. 3.3, Alg. 2) runs a Partial-SVD of the two boundary blocks
+ * (Alg. 3, Eqs. (5)-(6)), an SVD of the vertically stacked Sigma_i V_i^T rows
+ * (Eqs. (7)-(8)) and the block-diagonal product diag(U_i) U_r of Eq. (9).
+ *
+ * Conventions shared by every entry point:
+ *   - Row-major storage.  A is t x c, row tau = time tick tau (Def. 1).
+ *   - Time ranges are 0-based and half-open: [t_s, t_e), n = t_e - t_s rows.
+ *     The paper's inclusive [t_s, t_e] is (t_s, t_e + 1) here.
+ *   - Block i holds rows [i*b, min((i+1)*b, t)); the last block may be short.
+ *   - Singular values are FP64, descending.  A value <= 1e-11 * sigma_1 (FP64
+ *     mode; 1e-5 in the FP32/BF16 modes) is numerically zero: its triplet is
+ *     zeroed and it does not count in k_out / k_i.
+ *   - Sign rule: every returned pair (u_j, v_j) is flipped so that the entry
+ *     of v_j with the largest magnitude is positive.
+ *   - Device pointers are HIP device memory; host pointers are ordinary host
+ *     memory that is read during the call only.
+ *   - Every call enqueues its GPU work on `stream` and returns without waiting
+ *     for it, except where noted.  Outputs are valid once the stream has
+ *     reached that point.  The store is immutable after zs_store_blocks, so
+ *     queries on different streams may run concurrently.
+ *   - Calls return a zs_status and never throw or abort.  On error nothing is
+ *     written to the outputs; zs_last_error() gives a message for the calling
+ *     thread.
+ */
+#ifndef ZOOMSVD_H
+#define ZOOMSVD_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ZS_OK = 0,
+    ZS_EINVAL = -1,    /* bad argument: null pointer, b < 1, k < 1, k > c, lda < c, ...   */
+    ZS_ERANGE = -2,    /* bad query: t_s < 0, t_e > t, t_s >= t_e, k_q < 1 or k_q > k       */
+    ZS_ENOMEM = -3,    /* device allocation failed                                          */
+    ZS_ENOCONV = -4,   /* a Jacobi eigen-solve hit its sweep cap (reported by zs_sync_status) */
+    ZS_EDEVICE = -5,   /* a HIP runtime call failed                                         */
+    ZS_EUNSUPPORTED = -6 /* a size this build does not handle (c or k above the limits)    */
+} zs_status;
+
+typedef enum { ZS_F64 = 0, ZS_F32 = 1, ZS_BF16 = 2 } zs_dtype;          /* element type of A */
+typedef enum { ZS_MODE_FP64 = 0, ZS_MODE_FP32 = 1, ZS_MODE_BF16 = 2 } zs_mode; /* bulk arithmetic */
+
+typedef struct zs_store zs_store;   /* opaque; owns the device-resident U_(i), Sigma_(i), V_(i) */
+
+/* Limits of this build: c <= ZS_MAX_C columns and k <= ZS_MAX_K. */
+#define ZS_MAX_C 128
+#define ZS_MAX_K 64
+
+/*
+ * zs_store_blocks -- storage phase in batch form (Alg. 1 with the rank-k SVD of
+ * each complete block; Def. 1 block partition; Def. 2 sets U, S, V).
+ *   A      device pointer, t x c row-major with leading dimension lda >= c,
+ *          element type a_type.  Read only.  The caller may free it once the
+ *          stream has passed this call (the method discards raw data).
+ *   t, c   rows (time ticks) and columns (series); t >= 1, 1 <= c <= ZS_MAX_C.
+ *   b      block size >= 1.  k: stored rank, 1 <= k <= min(c, ZS_MAX_K).
+ *          Block i keeps k_i = min(k, rows_i, numerical rank) triplets.
+ *   mode   ZS_MODE_FP64 (only mode of this build; FP64 A required).
+ *   out    receives the new store.  The library owns its device memory until
+ *          zs_store_free.  The call synchronises `stream` once at the end to
+ *          check the per-block Jacobi status; on ZS_ENOCONV the store is still
+ *          returned (a block used its last sweep) and *out is set.
+ */
+zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_dtype a_type,
+                          int64_t b, int32_t k, zs_mode mode, hipStream_t stream, zs_store **out);
+
+/*
+ * zs_query -- query phase for one range (Alg. 2 with Alg. 3).
+ *   [t_s, t_e)  0 <= t_s < t_e <= t.   k_q: requested rank, 1 <= k_q <= k.
+ *   U       device, n x k_q row-major, leading dimension ldu >= k_q (n = t_e - t_s).
+ *   S       device, k_q doubles.
+ *   V       device, c x k_q row-major, leading dimension ldv >= k_q; column j = v_j.
+ *   k_out   device int32: the numerical rank kept (<= k_q).  Columns j >= k_out
+ *           of U and V and entries of S are zero.
+ *   U and V are double in FP64 mode.  Asynchronous on `stream`.
+ */
+zs_status zs_query(const zs_store *st, int64_t t_s, int64_t t_e, int32_t k_q, void *U, int64_t ldu,
+                   double *S, void *V, int64_t ldv, int32_t *k_out, hipStream_t stream);
+
+/*
+ * zs_query_batch -- nq independent queries in one set of launches.
+ *   t_s, t_e, k_q   host arrays of nq ranges and ranks (same rules as zs_query).
+ *   U, S, V         device base pointers; query q writes
+ *                     U + u_off[q]  (n_q x k_q[q], leading dimension k_q[q]),
+ *                     S + s_off[q]  (k_q[q] doubles),
+ *                     V + v_off[q]  (c x k_q[q], leading dimension k_q[q]),
+ *                   offsets in elements, host arrays.
+ *   k_out           device, nq int32.
+ *   Each query's result does not depend on the other queries in the batch.
+ */
+zs_status zs_query_batch(const zs_store *st, int32_t nq, const int64_t *t_s, const int64_t *t_e,
+                         const int32_t *k_q, void *U, const int64_t *u_off, double *S,
+                         const int64_t *s_off, void *V, const int64_t *v_off, int32_t *k_out,
+                         hipStream_t stream);
+
+/* Releases the store's device memory (synchronises the device first). */
+void zs_store_free(zs_store *st);
+
+/* Device bytes held by the store (factors only, not scratch). */
+int64_t zs_store_bytes(const zs_store *st);
+
+/* Shape of a store: any pointer may be null. */
+zs_status zs_store_info(const zs_store *st, int64_t *t, int64_t *c, int64_t *b, int32_t *k,
+                        int64_t *nb, int32_t *mode);
+
+/*
+ * zs_store_get_block -- copies block i's factors (Def. 2) to device buffers:
+ *   U  rows_i x k (ld k), S k doubles, V c x k (ld k, column j = v_j),
+ *   k_i device int32.  Element type of U and V as in zs_query.  Asynchronous.
+ */
+zs_status zs_store_get_block(const zs_store *st, int64_t i, void *U, double *S, void *V,
+                             int32_t *k_i, hipStream_t stream);
+
+/*
+ * zs_sync_status -- waits for `stream` and reports ZS_ENOCONV if any Jacobi
+ * eigen-solve enqueued by this store since the last call hit its sweep cap.
+ */
+zs_status zs_sync_status(const zs_store *st, hipStream_t stream);
+
+/* Thread-local message describing the last error of the calling thread. */
+const char *zs_last_error(void);
+
+/* Library version string. */
+const char *zs_version(void);
+
+/*
+ * Per-kernel timing (diagnostics).  When enabled, every kernel launch of the
+ * library is bracketed by HIP events on its stream; zs_timing_get waits for
+ * the recorded events and returns, for kernel `name`, the number of launches
+ * and the summed duration in milliseconds since the last reset.
+ */
+void zs_timing_enable(int on);
+void zs_timing_reset(void);
+zs_status zs_timing_get(const char *name, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZOOMSVD_H */

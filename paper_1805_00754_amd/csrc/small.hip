@@ -1,0 +1,374 @@
+// Small symmetric eigen-solves (n <= 64) and the kernels built on them:
+//
+//  * finalize: second stage of every rank-k SVD.  With Y = X V_k (the data
+//    projected on the first-stage eigenvectors), G_Y = Y^T Y is nearly
+//    diagonal with scales sigma_j^2; two-sided Jacobi on it (Demmel-Veselic
+//    stopping rule) gives singular values with high relative accuracy
+//    (Rayleigh-Ritz on span V_k).  Outputs Sigma, V = V_k W (sign rule
+//    applied) and F = W Sigma^-1, so that U = Y F.
+//  * partial: Partial-SVD of a boundary block (Alg. 3, Eqs. (5)-(6)):
+//    P = X U_(i) Sigma_(i),  P^T P = V~ Sigma~^2 V~^T, the block's stack rows
+//    Sigma~ V~^T V_(i)^T, and T = Sigma_(i) V~ Sigma~^+ so that U' = X U_(i) T.
+#include "zs_internal.h"
+
+namespace zs {
+namespace {
+
+constexpr int LDS_N = kMaxK + 1;   // leading dimension of k x k LDS matrices
+
+__device__ __forceinline__ void rr_pair(int step, int pi, int N, int &p, int &q)
+{
+    const int m = N - 1;
+    if (pi == 0) {
+        p = 0;
+        q = 1 + (step % m);
+    } else {
+        p = 1 + ((pi + step) % m);
+        q = 1 + ((m - pi + step) % m);
+    }
+}
+
+// Two-sided cyclic Jacobi, parallel round-robin ordering, on the symmetric
+// n x n matrix G (row-major, ld LDS_N) accumulating W (ld LDS_N, identity on
+// entry).  A pair is rotated when |g_pq| > tol sqrt(g_pp g_qq), tol = n eps
+// (the relative stopping rule of Demmel & Veselic).  As in the classical
+// algorithm, the rotated 2 x 2 block is set exactly afterwards: g_pq = 0,
+// g_pp - t g_pq, g_qq + t g_pq, so no rounding residue is left in the
+// annihilated entry.  Diagonal entries at or below (n eps)^2 tr(G) are
+// numerically zero and are not rotated.
+// Returns the number of sweeps, or -1 if the cap was hit.  All threads of
+// the block must call it; cs/sn/dp/dq need n/2 entries.
+__device__ int sym_jacobi(double *G, double *W, int n, double *cs_sh, double *sn_sh, double *dp_sh,
+                          double *dq_sh, int *flag_sh, double *tr_sh)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        double tr = 0.0;
+        for (int i = 0; i < n; ++i) tr += fabs(G[i * LDS_N + i]);
+        *tr_sh = tr;
+    }
+    __syncthreads();
+    const double tol = (double)n * __DBL_EPSILON__;
+    const double floor = ((double)n * __DBL_EPSILON__) * ((double)n * __DBL_EPSILON__) * (*tr_sh);
+    const int N = (n + 1) & ~1;
+    const int np = N / 2;
+    for (int sweep = 1; sweep <= kMaxSweeps; ++sweep) {
+        if (tid == 0) *flag_sh = 0;
+        __syncthreads();
+        for (int step = 0; step < N - 1; ++step) {
+            for (int pi = tid; pi < np; pi += kThreads) {
+                int p, q;
+                rr_pair(step, pi, N, p, q);
+                double cs = 1.0, sn = 0.0, dp = 0.0, dq = 0.0;
+                if (p < n && q < n) {
+                    const double gpp = G[p * LDS_N + p], gqq = G[q * LDS_N + q];
+                    const double gpq = G[p * LDS_N + q];
+                    if (gpq != 0.0 && fabs(gpp) > floor && fabs(gqq) > floor &&
+                        fabs(gpq) > tol * sqrt(fabs(gpp)) * sqrt(fabs(gqq))) {
+                        const double zeta = (gqq - gpp) / (2.0 * gpq);
+                        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                        cs = 1.0 / sqrt(1.0 + t * t);
+                        sn = cs * t;
+                        dp = gpp - t * gpq;
+                        dq = gqq + t * gpq;
+                        *flag_sh = 1;
+                    }
+                }
+                cs_sh[pi] = cs;
+                sn_sh[pi] = sn;
+                dp_sh[pi] = dp;
+                dq_sh[pi] = dq;
+            }
+            __syncthreads();
+            // columns p, q of G and W: G <- G J, W <- W J
+            for (int e = tid; e < np * n; e += kThreads) {
+                const int pi = e / n, r = e % n;
+                const double sn = sn_sh[pi];
+                if (sn == 0.0) continue;
+                const double cs = cs_sh[pi];
+                int p, q;
+                rr_pair(step, pi, N, p, q);
+                double gp = G[r * LDS_N + p], gq = G[r * LDS_N + q];
+                G[r * LDS_N + p] = cs * gp - sn * gq;
+                G[r * LDS_N + q] = sn * gp + cs * gq;
+                gp = W[r * LDS_N + p];
+                gq = W[r * LDS_N + q];
+                W[r * LDS_N + p] = cs * gp - sn * gq;
+                W[r * LDS_N + q] = sn * gp + cs * gq;
+            }
+            __syncthreads();
+            // rows p, q of G: G <- J^T G
+            for (int e = tid; e < np * n; e += kThreads) {
+                const int pi = e / n, r = e % n;
+                const double sn = sn_sh[pi];
+                if (sn == 0.0) continue;
+                const double cs = cs_sh[pi];
+                int p, q;
+                rr_pair(step, pi, N, p, q);
+                const double gp = G[p * LDS_N + r], gq = G[q * LDS_N + r];
+                G[p * LDS_N + r] = cs * gp - sn * gq;
+                G[q * LDS_N + r] = sn * gp + cs * gq;
+            }
+            __syncthreads();
+            // the rotated 2 x 2 blocks, exactly
+            for (int pi = tid; pi < np; pi += kThreads) {
+                if (sn_sh[pi] == 0.0) continue;
+                int p, q;
+                rr_pair(step, pi, N, p, q);
+                G[p * LDS_N + p] = dp_sh[pi];
+                G[q * LDS_N + q] = dq_sh[pi];
+                G[p * LDS_N + q] = 0.0;
+                G[q * LDS_N + p] = 0.0;
+            }
+            __syncthreads();
+        }
+        const int f = *flag_sh;
+        __syncthreads();
+        if (!f) return sweep;
+    }
+    return -1;
+}
+
+__global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *__restrict__ probs,
+                                                            const double *__restrict__ GYpart,
+                                                            const double *__restrict__ Vk,
+                                                            double *__restrict__ F,
+                                                            double rank_tol,
+                                                            int *__restrict__ conv_flag)
+{
+    extern __shared__ __align__(16) double smem[];
+    double *G = smem;                         // kk x kk, ld LDS_N
+    double *W = G + kMaxK * LDS_N;            // kk x kk, ld LDS_N
+    double *Vn = W + kMaxK * LDS_N;           // c x kk (V_k W)
+    __shared__ double cs_sh[kMaxK / 2], sn_sh[kMaxK / 2], dp_sh[kMaxK / 2], dq_sh[kMaxK / 2];
+    __shared__ double sig[kMaxK], flip[kMaxK];
+    __shared__ int pos[kMaxK], inv[kMaxK], keep[kMaxK];
+    __shared__ int flag_sh;
+    __shared__ double tr_sh;
+
+    const Prob P = probs[blockIdx.x];
+    const int kk = P.kk;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kk * kk; e += kThreads) {
+        const int a = e / kk, b = e % kk;
+        double s = 0.0;
+        for (int sl = 0; sl < P.nslots; ++sl) s += GYpart[(int64_t)(P.slot0 + sl) * kSlotK + e];
+        G[a * LDS_N + b] = s;
+        W[a * LDS_N + b] = (a == b) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int sweeps = sym_jacobi(G, W, kk, cs_sh, sn_sh, dp_sh, dq_sh, &flag_sh, &tr_sh);
+    if (sweeps < 0 && tid == 0) atomicOr(conv_flag, 1);
+
+    for (int j = tid; j < kk; j += kThreads) sig[j] = sqrt(fmax(G[j * LDS_N + j], 0.0));
+    __syncthreads();
+    double smax = 0.0;
+    for (int j = 0; j < kk; ++j) smax = fmax(smax, sig[j]);
+    for (int j = tid; j < kk; j += kThreads) {
+        int p = 0;
+        for (int i = 0; i < kk; ++i) p += (sig[i] > sig[j]) || (sig[i] == sig[j] && i < j);
+        pos[j] = p;
+        inv[p] = j;
+        keep[j] = (sig[j] > rank_tol * smax) && (sig[j] > 0.0);
+    }
+    // Vn = V_k W
+    const double *vk = Vk + (int64_t)blockIdx.x * c * kMaxK;
+    for (int e = tid; e < c * kk; e += kThreads) {
+        const int a = e / kk, j = e % kk;
+        double s = 0.0;
+        for (int l = 0; l < kk; ++l) s = fma(vk[a * kk + l], W[l * LDS_N + j], s);
+        Vn[a * kk + j] = s;
+    }
+    __syncthreads();
+    // sign rule: largest |v| entry (lowest index on ties) made positive
+    for (int j = tid; j < kk; j += kThreads) {
+        int am = 0;
+        double vm = -1.0;
+        for (int a = 0; a < c; ++a) {
+            const double v = fabs(Vn[a * kk + j]);
+            if (v > vm) { vm = v; am = a; }
+        }
+        flip[j] = Vn[am * kk + j] < 0.0 ? -1.0 : 1.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < c * kk; e += kThreads) {
+        const int a = e / kk, pp = e % kk;
+        const int j = inv[pp];
+        const double v = keep[j] ? flip[j] * Vn[a * kk + j] : 0.0;
+        P.v_dst[a * P.v_rs + pp * P.v_cs] = v;
+    }
+    double *Fp = F + (int64_t)blockIdx.x * kSlotK;
+    for (int e = tid; e < kk * kk; e += kThreads) {
+        const int l = e / kk, pp = e % kk;
+        const int j = inv[pp];
+        Fp[l * kk + pp] = keep[j] ? flip[j] * W[l * LDS_N + j] / sig[j] : 0.0;
+    }
+    for (int pp = tid; pp < kk; pp += kThreads) {
+        const int j = inv[pp];
+        P.s_dst[pp] = keep[j] ? sig[j] : 0.0;
+    }
+    if (tid == 0) {
+        int n = 0;
+        for (int j = 0; j < kk; ++j) n += keep[j];
+        *P.k_dst = n;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
+                                                           const Piece *__restrict__ pieces,
+                                                           const int32_t *__restrict__ pidx,
+                                                           double *__restrict__ M,
+                                                           double *__restrict__ T, double rank_tol,
+                                                           int *__restrict__ conv_flag)
+{
+    constexpr int RB = 32;
+    extern __shared__ __align__(16) double smem[];
+    double *G = smem;                         // k x k, ld LDS_N (G_P, then G_Y)
+    double *W1 = G + kMaxK * LDS_N;           // first-stage eigenvectors
+    double *W2 = W1 + kMaxK * LDS_N;          // second-stage rotation
+    double *Us = W2 + kMaxK * LDS_N;          // RB x k staged rows of P = X U Sigma
+    double *Ys = Us + RB * kMaxK;             // RB x k rows of Y = P W1
+    __shared__ double cs_sh[kMaxK / 2], sn_sh[kMaxK / 2], dp_sh[kMaxK / 2], dq_sh[kMaxK / 2];
+    __shared__ double sig[kMaxK], sblk[kMaxK];
+    __shared__ int flag_sh;
+    __shared__ double tr_sh;
+
+    const Piece pc = pieces[pidx[blockIdx.x]];
+    const int k = st.k;
+    const int c = (int)st.c;
+    const int tid = threadIdx.x;
+    const double *Ub = st.U + (pc.blk * st.b + pc.r0) * k;
+    const int m = pc.r1 - pc.r0;
+    for (int j = tid; j < k; j += kThreads) sblk[j] = st.S[pc.blk * k + j];
+
+    constexpr int EPT = (kMaxK * kMaxK + kThreads - 1) / kThreads;
+    double acc[EPT];
+    // Two passes over the kept rows.  Pass 0: G_P = P^T P.  Pass 1, after the
+    // first eigen-solve: G_Y = Y^T Y with Y = P W1 recomputed from the rows,
+    // so the singular values of P come out with relative accuracy.
+    for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+        for (int x = 0; x < EPT; ++x) acc[x] = 0.0;
+        for (int r0 = 0; r0 < m; r0 += RB) {
+            const int nr = min(RB, m - r0);
+            __syncthreads();
+            for (int e = tid; e < nr * k; e += kThreads) {
+                const int a = e % k;
+                Us[e] = Ub[(int64_t)r0 * k + e] * sblk[a];
+            }
+            __syncthreads();
+            const double *R = Us;
+            if (pass == 1) {
+                for (int e = tid; e < nr * k; e += kThreads) {
+                    const int rr = e / k, j = e % k;
+                    double s = 0.0;
+                    for (int a = 0; a < k; ++a) s = fma(Us[rr * k + a], W1[a * LDS_N + j], s);
+                    Ys[e] = s;
+                }
+                __syncthreads();
+                R = Ys;
+            }
+#pragma unroll
+            for (int x = 0; x < EPT; ++x) {
+                const int e = tid + x * kThreads;
+                if (e < k * k) {
+                    const int a = e / k, b = e % k;
+                    double s = acc[x];
+                    for (int rr = 0; rr < nr; ++rr) s = fma(R[rr * k + a], R[rr * k + b], s);
+                    acc[x] = s;
+                }
+            }
+        }
+        __syncthreads();
+        double *Wp = pass == 0 ? W1 : W2;
+#pragma unroll
+        for (int x = 0; x < EPT; ++x) {
+            const int e = tid + x * kThreads;
+            if (e < k * k) {
+                const int a = e / k, b = e % k;
+                G[a * LDS_N + b] = acc[x];
+                Wp[a * LDS_N + b] = (a == b) ? 1.0 : 0.0;
+            }
+        }
+        __syncthreads();
+        const int sweeps = sym_jacobi(G, Wp, k, cs_sh, sn_sh, dp_sh, dq_sh, &flag_sh, &tr_sh);
+        if (sweeps < 0 && tid == 0) atomicOr(conv_flag, 1);
+    }
+    for (int j = tid; j < k; j += kThreads) sig[j] = sqrt(fmax(G[j * LDS_N + j], 0.0));
+    // V~ = W1 W2, kept in G (no longer needed)
+    for (int e = tid; e < k * k; e += kThreads) {
+        const int a = e / k, j = e % k;
+        double s = 0.0;
+        for (int l = 0; l < k; ++l) s = fma(W1[a * LDS_N + l], W2[l * LDS_N + j], s);
+        Ys[e] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < k * k; e += kThreads) {
+        const int a = e / k, j = e % k;
+        G[a * LDS_N + j] = Ys[e];
+    }
+    __syncthreads();
+    double smax = 0.0;
+    for (int j = 0; j < k; ++j) smax = fmax(smax, sig[j]);
+
+    // stack rows: M[m_row + j] = sigma~_j (V_(i) v~_j)^T = sigma~_j sum_l v~_lj V_(i)^T[l]
+    const double *Vt = st.Vt + pc.blk * k * st.c;
+    for (int e = tid; e < k * c; e += kThreads) {
+        const int j = e / c, col = e % c;
+        double s = 0.0;
+        for (int l = 0; l < k; ++l) s = fma(G[l * LDS_N + j], Vt[(int64_t)l * c + col], s);
+        M[(pc.m_row + j) * c + col] = sig[j] * s;
+    }
+    // T = Sigma_(i) V~ Sigma~^+  (k x k, row-major)
+    double *Tp = T + (int64_t)pc.t_idx * k * k;
+    for (int e = tid; e < k * k; e += kThreads) {
+        const int a = e / k, j = e % k;
+        const bool kp = sig[j] > rank_tol * smax && sig[j] > 0.0;
+        Tp[e] = kp ? sblk[a] * G[a * LDS_N + j] / sig[j] : 0.0;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_finalize(int c, const Prob *probs, int nprob, const double *GYpart,
+                           const double *Vk, double *F, double rank_tol, int *conv_flag,
+                           hipStream_t stream)
+{
+    if (nprob <= 0) return hipSuccess;
+    timing_begin("finalize", stream);
+    const size_t lds = (size_t)(2 * kMaxK * LDS_N + c * kMaxK) * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)finalize_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)((2 * kMaxK * LDS_N + kMaxC * kMaxK) * sizeof(double)));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    finalize_kernel<<<nprob, kThreads, lds, stream>>>(c, probs, GYpart, Vk, F, rank_tol, conv_flag);
+    hipError_t e = hipGetLastError();
+    timing_end("finalize", stream);
+    return e;
+}
+
+hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx, int npartial,
+                          double *M, double *T, double rank_tol, int *conv_flag,
+                          hipStream_t stream)
+{
+    if (npartial <= 0) return hipSuccess;
+    timing_begin("partial", stream);
+    const size_t lds = (size_t)(3 * kMaxK * LDS_N + 2 * 32 * kMaxK) * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)partial_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    partial_kernel<<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, M, T, rank_tol, conv_flag);
+    hipError_t e = hipGetLastError();
+    timing_end("partial", stream);
+    return e;
+}
+
+}  // namespace zs

@@ -1,0 +1,585 @@
+// Host runtime of the Zoom-SVD library: the store object, the query planner
+// (Alg. 3 index math and the ragged work lists), workspaces, kernel timing and
+// the C ABI declared in include/zoomsvd.h.
+#include "zoomsvd.h"
+#include "zs_internal.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace zs;
+
+namespace {
+
+thread_local std::string t_err;
+
+zs_status fail(zs_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                   \
+    } while (0)
+
+// ------------------------------------------------------------------ timing
+std::mutex g_tmu;
+bool g_timing = false;
+struct TimedLaunch {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::vector<TimedLaunch> g_pending;
+std::map<std::string, std::pair<int64_t, double>> g_acc;
+thread_local std::map<std::string, hipEvent_t> t_open;
+
+// ------------------------------------------------------------------ buffers
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t need)
+    {
+        if (need <= bytes) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+            p = nullptr;
+            bytes = 0;
+        }
+        size_t want = std::max(need, bytes + bytes / 2);
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            e = hipMalloc(&p, need);
+            if (e != hipSuccess) { p = nullptr; return e; }
+            want = need;
+        }
+        bytes = want;
+        return hipSuccess;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Scratch of the query pipeline for one stream (grow-only).
+struct Workspace {
+    DevBuf M, Gpart, Vk, Y, GY, F, T, C, desc;
+    void *host = nullptr;        // pinned staging of the descriptors
+    size_t host_bytes = 0;
+    hipEvent_t copied = nullptr; // the last upload from `host` has completed
+    void release()
+    {
+        M.release(); Gpart.release(); Vk.release(); Y.release(); GY.release();
+        F.release(); T.release(); C.release(); desc.release();
+        if (host) (void)hipHostFree(host);
+        if (copied) (void)hipEventDestroy(copied);
+        host = nullptr;
+        copied = nullptr;
+    }
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct zs_store {
+    int64_t t = 0, c = 0, b = 0, nb = 0;
+    int32_t k = 0;
+    zs_mode mode = ZS_MODE_FP64;
+    int device = 0;
+    double *U = nullptr, *Vt = nullptr, *S = nullptr;
+    int32_t *kvec = nullptr;
+    int *conv = nullptr;          // set by kernels when a Jacobi hits its cap
+    std::mutex mu;
+    std::map<hipStream_t, Workspace *> ws;
+
+    StoreView view() const
+    {
+        StoreView v;
+        v.U = U; v.Vt = Vt; v.S = S; v.t = t; v.c = c; v.b = b; v.k = k;
+        return v;
+    }
+    int64_t block_rows(int64_t i) const { return std::min(b, t - i * b); }
+};
+
+namespace zs {
+void timing_begin(const char *name, hipStream_t stream)
+{
+    if (!g_timing) return;
+    hipEvent_t a;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    (void)hipEventRecord(a, stream);
+    t_open[name] = a;
+}
+
+void timing_end(const char *name, hipStream_t stream)
+{
+    if (!g_timing) return;
+    auto it = t_open.find(name);
+    if (it == t_open.end()) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) return;
+    (void)hipEventRecord(b, stream);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_pending.push_back({name, it->second, b});
+    t_open.erase(it);
+}
+}  // namespace zs
+
+namespace {
+
+// Chunking of tall-skinny row runs for the Gram / projection kernels.
+constexpr int kStoreChunkRows = 2048;
+constexpr int kQueryChunkRows = 512;
+
+// Upload `bytes` of host data through the workspace's pinned staging buffer.
+zs_status upload(Workspace &w, const void *src, size_t bytes, hipStream_t stream)
+{
+    if (w.copied) HIP_TRY(hipEventSynchronize(w.copied));
+    if (bytes > w.host_bytes) {
+        if (w.host) HIP_TRY(hipHostFree(w.host));
+        w.host = nullptr;
+        size_t want = std::max(bytes, w.host_bytes * 2);
+        HIP_TRY(hipHostMalloc(&w.host, want, hipHostMallocDefault));
+        w.host_bytes = want;
+    }
+    if (!w.copied) HIP_TRY(hipEventCreateWithFlags(&w.copied, hipEventDisableTiming));
+    HIP_TRY(w.desc.ensure(bytes));
+    std::memcpy(w.host, src, bytes);
+    HIP_TRY(hipMemcpyAsync(w.desc.p, w.host, bytes, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(w.copied, stream));
+    return ZS_OK;
+}
+
+// Descriptor blob: several typed arrays packed at 256-byte boundaries.
+struct Blob {
+    std::vector<char> bytes;
+    template <class T> size_t add(const std::vector<T> &v)
+    {
+        size_t off = align_up(bytes.size(), 256);
+        bytes.resize(off + v.size() * sizeof(T) + 1);
+        if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+        return off;
+    }
+};
+
+zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t *te,
+                     const int32_t *kq, double *U, const int64_t *u_off, const int64_t *ldu,
+                     double *S, const int64_t *s_off, double *V, const int64_t *v_off,
+                     const int64_t *ldv, int32_t *k_out, hipStream_t stream)
+{
+    const int64_t c = st->c, b = st->b;
+    const int32_t k = st->k;
+    // ---- plan (Alg. 3 lines 1-3 for every query) --------------------------------
+    std::vector<Piece> pieces;
+    std::vector<int32_t> pidx;        // pieces that need a Partial-SVD
+    std::vector<Chunk> chunks;
+    std::vector<Prob> probs(nq);
+    int64_t m_rows = 0, y_elems = 0, c_elems = 0;
+    // Fixed chunking: a query's partial sums never depend on the rest of the batch.
+    const int chunk_rows = kQueryChunkRows;
+    int32_t slot = 0;
+    for (int32_t q = 0; q < nq; ++q) {
+        const int64_t S_ = ts[q] / b, E_ = (te[q] - 1) / b;
+        const int64_t lo = ts[q] - S_ * b, hi = te[q] - E_ * b;
+        const int64_t np = E_ - S_ + 1;
+        const int64_t Kq = np * k;
+        const int64_t m0 = m_rows, y0 = y_elems;
+        for (int64_t p = 0; p < np; ++p) {
+            const int64_t i = S_ + p;
+            const int64_t rows = st->block_rows(i);
+            Piece pc;
+            std::memset(&pc, 0, sizeof pc);
+            pc.blk = i;
+            pc.r0 = (int32_t)(i == S_ ? lo : 0);
+            pc.r1 = (int32_t)(i == E_ ? hi : rows);
+            pc.m_row = m0 + p * k;
+            pc.y_off = y0 + p * k * kq[q];
+            pc.c_off = c_elems;
+            c_elems += (int64_t)k * kq[q];
+            pc.out_off = u_off[q] + (i * b + pc.r0 - ts[q]) * ldu[q];
+            pc.ldu = ldu[q];
+            pc.q = q;
+            pc.kq = kq[q];
+            const bool partial = pc.r0 != 0 || pc.r1 != rows;
+            pc.t_idx = partial ? (int32_t)pidx.size() : -1;
+            if (partial) pidx.push_back((int32_t)pieces.size());
+            pieces.push_back(pc);
+        }
+        Prob pr;
+        std::memset(&pr, 0, sizeof pr);
+        pr.slot0 = slot;
+        for (int64_t r = 0; r < Kq; r += chunk_rows) {
+            Chunk ch;
+            ch.x_off = (m0 + r) * c;
+            ch.y_off = y0 + r * kq[q];
+            ch.rows = (int32_t)std::min<int64_t>(chunk_rows, Kq - r);
+            ch.prob = q;
+            ch.slot = slot++;
+            ch.kk = kq[q];
+            chunks.push_back(ch);
+        }
+        pr.nslots = slot - pr.slot0;
+        pr.kk = kq[q];
+        pr.v_dst = V + v_off[q];
+        pr.v_rs = ldv[q];
+        pr.v_cs = 1;
+        pr.s_dst = S + s_off[q];
+        pr.k_dst = k_out + q;
+        probs[q] = pr;
+        m_rows += Kq;
+        y_elems += Kq * kq[q];
+    }
+    // ---- workspace ---------------------------------------------------------------
+    Workspace *w;
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        auto it = st->ws.find(stream);
+        if (it == st->ws.end()) it = st->ws.emplace(stream, new Workspace()).first;
+        w = it->second;
+    }
+    const int nchunks = (int)chunks.size(), npieces = (int)pieces.size();
+    const int npartial = (int)pidx.size();
+    HIP_TRY(w->M.ensure(sizeof(double) * std::max<int64_t>(1, m_rows * c)));
+    HIP_TRY(w->Gpart.ensure(sizeof(double) * std::max<int64_t>(1, (int64_t)nchunks * c * c)));
+    HIP_TRY(w->Vk.ensure(sizeof(double) * (size_t)nq * c * kMaxK));
+    HIP_TRY(w->Y.ensure(sizeof(double) * std::max<int64_t>(1, y_elems)));
+    HIP_TRY(w->GY.ensure(sizeof(double) * (size_t)nchunks * kSlotK));
+    HIP_TRY(w->F.ensure(sizeof(double) * (size_t)nq * kSlotK));
+    HIP_TRY(w->T.ensure(sizeof(double) * std::max<int64_t>(1, (int64_t)npartial * k * k)));
+    HIP_TRY(w->C.ensure(sizeof(double) * std::max<int64_t>(1, c_elems)));
+    Blob blob;
+    const size_t o_chunks = blob.add(chunks), o_probs = blob.add(probs);
+    const size_t o_pieces = blob.add(pieces), o_pidx = blob.add(pidx);
+    zs_status s = upload(*w, blob.bytes.data(), blob.bytes.size(), stream);
+    if (s != ZS_OK) return s;
+    char *d = w->desc.as<char>();
+    const Chunk *d_chunks = (const Chunk *)(d + o_chunks);
+    const Prob *d_probs = (const Prob *)(d + o_probs);
+    const Piece *d_pieces = (const Piece *)(d + o_pieces);
+    const int32_t *d_pidx = (const int32_t *)(d + o_pidx);
+    const StoreView sv = st->view();
+    double *M = w->M.as<double>();
+    // ---- launches ---------------------------------------------------------------
+    HIP_TRY(launch_partial(sv, d_pieces, d_pidx, npartial, M, w->T.as<double>(), kRankTolFP64,
+                           st->conv, stream));
+    HIP_TRY(launch_gather(sv, d_pieces, npieces, M, stream));
+    HIP_TRY(launch_gram(M, c, (int)c, d_chunks, nchunks, w->Gpart.as<double>(), stream));
+    HIP_TRY(launch_eig((int)c, d_probs, nq, w->Gpart.as<double>(), w->Vk.as<double>(), st->conv,
+                       stream));
+    HIP_TRY(launch_project(M, c, (int)c, d_chunks, nchunks, w->Vk.as<double>(), w->Y.as<double>(),
+                           w->GY.as<double>(), stream));
+    HIP_TRY(launch_finalize((int)c, d_probs, nq, w->GY.as<double>(), w->Vk.as<double>(),
+                            w->F.as<double>(), kRankTolFP64, st->conv, stream));
+    HIP_TRY(launch_coef(k, d_pieces, npieces, w->Y.as<double>(), w->F.as<double>(),
+                        w->T.as<double>(), w->C.as<double>(), stream));
+    HIP_TRY(launch_blockprod(sv, d_pieces, npieces, w->C.as<double>(), U, stream));
+    return ZS_OK;
+}
+
+zs_status check_query(const zs_store *st, int64_t ts, int64_t te, int32_t kq)
+{
+    if (ts < 0 || te > st->t || ts >= te)
+        return fail(ZS_ERANGE, "range [%lld, %lld) outside [0, %lld) or empty", (long long)ts,
+                    (long long)te, (long long)st->t);
+    if (kq < 1 || kq > st->k)
+        return fail(ZS_ERANGE, "k_q = %d outside [1, k = %d]", kq, st->k);
+    return ZS_OK;
+}
+
+}  // namespace
+
+// =============================================================== C ABI
+extern "C" {
+
+const char *zs_last_error(void) { return t_err.c_str(); }
+
+const char *zs_version(void) { return "zoomsvd-gfx950 0.1"; }
+
+zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_dtype a_type,
+                          int64_t b, int32_t k, zs_mode mode, hipStream_t stream, zs_store **out)
+{
+    if (!out) return fail(ZS_EINVAL, "out is null");
+    *out = nullptr;
+    if (!A) return fail(ZS_EINVAL, "A is null");
+    if (t < 1) return fail(ZS_EINVAL, "t = %lld < 1", (long long)t);
+    if (c < 1) return fail(ZS_EINVAL, "c = %lld < 1", (long long)c);
+    if (lda < c) return fail(ZS_EINVAL, "lda = %lld < c = %lld", (long long)lda, (long long)c);
+    if (b < 1) return fail(ZS_EINVAL, "b = %lld < 1", (long long)b);
+    if (k < 1 || k > c) return fail(ZS_EINVAL, "k = %d outside [1, c = %lld]", k, (long long)c);
+    if (c > ZS_MAX_C) return fail(ZS_EUNSUPPORTED, "c = %lld > %d", (long long)c, ZS_MAX_C);
+    if (k > ZS_MAX_K) return fail(ZS_EUNSUPPORTED, "k = %d > %d", k, ZS_MAX_K);
+    if (mode != ZS_MODE_FP64 || a_type != ZS_F64)
+        return fail(ZS_EUNSUPPORTED, "only FP64 input in FP64 mode is built");
+    if (b > (int64_t)1 << 30) return fail(ZS_EINVAL, "b too large");
+
+    zs_store *st = new zs_store();
+    st->t = t; st->c = c; st->b = b; st->k = k; st->mode = mode;
+    st->nb = (t + b - 1) / b;
+    const int64_t nb = st->nb;
+    auto cleanup = [&](zs_status s) {
+        zs_store_free(st);
+        return s;
+    };
+    if (hipGetDevice(&st->device) != hipSuccess) return cleanup(fail(ZS_EDEVICE, "no HIP device"));
+#define ST_TRY(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return cleanup(fail(e_ == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "%s: %s", \
+                                #expr, hipGetErrorString(e_)));                             \
+    } while (0)
+    ST_TRY(hipMalloc(&st->U, sizeof(double) * t * k));
+    ST_TRY(hipMalloc(&st->Vt, sizeof(double) * nb * k * c));
+    ST_TRY(hipMalloc(&st->S, sizeof(double) * nb * k));
+    ST_TRY(hipMalloc(&st->kvec, sizeof(int32_t) * nb));
+    ST_TRY(hipMalloc(&st->conv, sizeof(int)));
+    ST_TRY(hipMemsetAsync(st->conv, 0, sizeof(int), stream));
+
+    // Work lists: one problem per block, chunks of at most kStoreChunkRows rows.
+    std::vector<Chunk> chunks;
+    std::vector<Prob> probs(nb);
+    int32_t slot = 0;
+    for (int64_t i = 0; i < nb; ++i) {
+        const int64_t rows = st->block_rows(i);
+        Prob pr;
+        std::memset(&pr, 0, sizeof pr);
+        pr.slot0 = slot;
+        for (int64_t r = 0; r < rows; r += kStoreChunkRows) {
+            Chunk ch;
+            ch.x_off = (i * b + r) * lda;
+            ch.y_off = (i * b + r) * k;
+            ch.rows = (int32_t)std::min<int64_t>(kStoreChunkRows, rows - r);
+            ch.prob = (int32_t)i;
+            ch.slot = slot++;
+            ch.kk = k;
+            chunks.push_back(ch);
+        }
+        pr.nslots = slot - pr.slot0;
+        pr.kk = k;
+        pr.v_dst = st->Vt + i * k * c;      // V_(i)^T: element (a, j) at j * c + a
+        pr.v_rs = 1;
+        pr.v_cs = c;
+        pr.s_dst = st->S + i * k;
+        pr.k_dst = st->kvec + i;
+        probs[i] = pr;
+    }
+    const int nchunks = (int)chunks.size();
+    DevBuf Gpart, Vk, GY, F, desc;
+    auto release = [&]() {
+        Gpart.release(); Vk.release(); GY.release(); F.release(); desc.release();
+    };
+#define ST_TRY2(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            release();                                                                      \
+            return cleanup(fail(e_ == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "%s: %s", \
+                                #expr, hipGetErrorString(e_)));                             \
+        }                                                                                   \
+    } while (0)
+    ST_TRY2(Gpart.ensure(sizeof(double) * (size_t)nchunks * c * c));
+    ST_TRY2(Vk.ensure(sizeof(double) * (size_t)nb * c * kMaxK));
+    ST_TRY2(GY.ensure(sizeof(double) * (size_t)nchunks * kSlotK));
+    ST_TRY2(F.ensure(sizeof(double) * (size_t)nb * kSlotK));
+    Blob blob;
+    const size_t o_chunks = blob.add(chunks), o_probs = blob.add(probs);
+    ST_TRY2(desc.ensure(blob.bytes.size()));
+    ST_TRY2(hipMemcpyAsync(desc.p, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice,
+                           stream));
+    const Chunk *d_chunks = (const Chunk *)(desc.as<char>() + o_chunks);
+    const Prob *d_probs = (const Prob *)(desc.as<char>() + o_probs);
+    const double *Ad = static_cast<const double *>(A);
+    ST_TRY2(launch_gram(Ad, lda, (int)c, d_chunks, nchunks, Gpart.as<double>(), stream));
+    ST_TRY2(launch_eig((int)c, d_probs, (int)nb, Gpart.as<double>(), Vk.as<double>(), st->conv,
+                       stream));
+    ST_TRY2(launch_project(Ad, lda, (int)c, d_chunks, nchunks, Vk.as<double>(), st->U,
+                           GY.as<double>(), stream));
+    ST_TRY2(launch_finalize((int)c, d_probs, (int)nb, GY.as<double>(), Vk.as<double>(),
+                            F.as<double>(), kRankTolFP64, st->conv, stream));
+    ST_TRY2(launch_utransform(st->U, k, d_chunks, nchunks, F.as<double>(), stream));
+    ST_TRY2(hipStreamSynchronize(stream));
+    int conv = 0;
+    ST_TRY2(hipMemcpy(&conv, st->conv, sizeof(int), hipMemcpyDeviceToHost));
+    release();
+    *out = st;
+    if (conv) {
+        int zero = 0;
+        (void)hipMemcpy(st->conv, &zero, sizeof(int), hipMemcpyHostToDevice);
+        return fail(ZS_ENOCONV, "a block eigen-solve hit the sweep cap");
+    }
+    return ZS_OK;
+#undef ST_TRY
+#undef ST_TRY2
+}
+
+zs_status zs_query(const zs_store *cst, int64_t t_s, int64_t t_e, int32_t k_q, void *U,
+                   int64_t ldu, double *S, void *V, int64_t ldv, int32_t *k_out,
+                   hipStream_t stream)
+{
+    if (!cst) return fail(ZS_EINVAL, "store is null");
+    zs_status s = check_query(cst, t_s, t_e, k_q);
+    if (s != ZS_OK) return s;
+    if (!U || !S || !V || !k_out) return fail(ZS_EINVAL, "null output pointer");
+    if (ldu < k_q || ldv < k_q) return fail(ZS_EINVAL, "ldu/ldv < k_q");
+    zs_store *st = const_cast<zs_store *>(cst);
+    const int64_t zero = 0;
+    return query_impl(st, 1, &t_s, &t_e, &k_q, static_cast<double *>(U), &zero, &ldu, S, &zero,
+                      static_cast<double *>(V), &zero, &ldv, k_out, stream);
+}
+
+zs_status zs_query_batch(const zs_store *cst, int32_t nq, const int64_t *t_s, const int64_t *t_e,
+                         const int32_t *k_q, void *U, const int64_t *u_off, double *S,
+                         const int64_t *s_off, void *V, const int64_t *v_off, int32_t *k_out,
+                         hipStream_t stream)
+{
+    if (!cst) return fail(ZS_EINVAL, "store is null");
+    if (nq < 1) return fail(ZS_EINVAL, "nq = %d < 1", nq);
+    if (!t_s || !t_e || !k_q || !u_off || !s_off || !v_off)
+        return fail(ZS_EINVAL, "null host array");
+    if (!U || !S || !V || !k_out) return fail(ZS_EINVAL, "null output pointer");
+    for (int32_t q = 0; q < nq; ++q) {
+        zs_status s = check_query(cst, t_s[q], t_e[q], k_q[q]);
+        if (s != ZS_OK) return s;
+        if (u_off[q] < 0 || s_off[q] < 0 || v_off[q] < 0)
+            return fail(ZS_EINVAL, "negative output offset for query %d", q);
+    }
+    std::vector<int64_t> ld(nq);
+    for (int32_t q = 0; q < nq; ++q) ld[q] = k_q[q];
+    zs_store *st = const_cast<zs_store *>(cst);
+    return query_impl(st, nq, t_s, t_e, k_q, static_cast<double *>(U), u_off, ld.data(), S, s_off,
+                      static_cast<double *>(V), v_off, ld.data(), k_out, stream);
+}
+
+void zs_store_free(zs_store *st)
+{
+    if (!st) return;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : st->ws) {
+        kv.second->release();
+        delete kv.second;
+    }
+    if (st->U) (void)hipFree(st->U);
+    if (st->Vt) (void)hipFree(st->Vt);
+    if (st->S) (void)hipFree(st->S);
+    if (st->kvec) (void)hipFree(st->kvec);
+    if (st->conv) (void)hipFree(st->conv);
+    delete st;
+}
+
+int64_t zs_store_bytes(const zs_store *st)
+{
+    if (!st) return 0;
+    return (int64_t)sizeof(double) * (st->t * st->k + st->nb * st->k * st->c + st->nb * st->k) +
+           (int64_t)sizeof(int32_t) * st->nb;
+}
+
+zs_status zs_store_info(const zs_store *st, int64_t *t, int64_t *c, int64_t *b, int32_t *k,
+                        int64_t *nb, int32_t *mode)
+{
+    if (!st) return fail(ZS_EINVAL, "store is null");
+    if (t) *t = st->t;
+    if (c) *c = st->c;
+    if (b) *b = st->b;
+    if (k) *k = st->k;
+    if (nb) *nb = st->nb;
+    if (mode) *mode = (int32_t)st->mode;
+    return ZS_OK;
+}
+
+zs_status zs_store_get_block(const zs_store *st, int64_t i, void *U, double *S, void *V,
+                             int32_t *k_i, hipStream_t stream)
+{
+    if (!st) return fail(ZS_EINVAL, "store is null");
+    if (i < 0 || i >= st->nb) return fail(ZS_ERANGE, "block %lld outside [0, %lld)", (long long)i,
+                                          (long long)st->nb);
+    if (!U || !S || !V || !k_i) return fail(ZS_EINVAL, "null output pointer");
+    const int64_t rows = st->block_rows(i), k = st->k, c = st->c;
+    HIP_TRY(hipMemcpyAsync(U, st->U + i * st->b * k, sizeof(double) * rows * k,
+                           hipMemcpyDeviceToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(S, st->S + i * k, sizeof(double) * k, hipMemcpyDeviceToDevice, stream));
+    // V_(i) = (V_(i)^T)^T: c x k from the stored k x c rows.
+    for (int64_t j = 0; j < k; ++j)
+        HIP_TRY(hipMemcpy2DAsync(static_cast<double *>(V) + j, sizeof(double) * k,
+                                 st->Vt + (i * k + j) * c, sizeof(double), sizeof(double), c,
+                                 hipMemcpyDeviceToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(k_i, st->kvec + i, sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
+    return ZS_OK;
+}
+
+zs_status zs_sync_status(const zs_store *cst, hipStream_t stream)
+{
+    if (!cst) return fail(ZS_EINVAL, "store is null");
+    HIP_TRY(hipStreamSynchronize(stream));
+    int conv = 0;
+    HIP_TRY(hipMemcpy(&conv, cst->conv, sizeof(int), hipMemcpyDeviceToHost));
+    if (conv) {
+        int zero = 0;
+        HIP_TRY(hipMemcpy(cst->conv, &zero, sizeof(int), hipMemcpyHostToDevice));
+        return fail(ZS_ENOCONV, "an eigen-solve hit the sweep cap");
+    }
+    return ZS_OK;
+}
+
+void zs_timing_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = on != 0;
+}
+
+void zs_timing_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto &p : g_pending) {
+        (void)hipEventSynchronize(p.b);
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    g_pending.clear();
+    g_acc.clear();
+}
+
+zs_status zs_timing_get(const char *name, int64_t *launches, double *total_ms)
+{
+    if (!name) return fail(ZS_EINVAL, "name is null");
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto &p : g_pending) {
+        HIP_TRY(hipEventSynchronize(p.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.a, p.b));
+        auto &acc = g_acc[p.name];
+        acc.first += 1;
+        acc.second += ms;
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    g_pending.clear();
+    auto it = g_acc.find(name);
+    if (launches) *launches = it == g_acc.end() ? 0 : it->second.first;
+    if (total_ms) *total_ms = it == g_acc.end() ? 0.0 : it->second.second;
+    return ZS_OK;
+}
+
+}  // extern "C"

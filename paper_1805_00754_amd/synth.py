@@ -98,8 +98,10 @@ def sinusoid_mixture(t: int, c: int, sources: int, seed: int, noise: str = "iid"
                 start = 0
             from scipy.signal import lfilter
             if r1 - r0 > start:
-                zi = (ar_phi * ar_state)[None, :]
-                e[start:], _ = lfilter([1.0], [1.0, -ar_phi], eta[start:], axis=0, zi=zi)
+                zi = (ar_phi * ar_state)[:, None]
+                out, _ = lfilter([1.0], [1.0, -ar_phi], np.ascontiguousarray(eta[start:].T),
+                                 axis=-1, zi=zi)
+                e[start:] = out.T
             ar_state = e[-1].copy()
             blk += e
         elif noise == "none":

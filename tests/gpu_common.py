@@ -1,0 +1,62 @@
+"""Shared helpers of the GPU tests (parity of the HIP path against the oracle)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+from paper_1805_00754_amd import zoomsvd as zs
+from tests.helpers import check_sigma, orth_err, subspace_errs
+
+# Tolerances of the FP64 path: relative error on sigma_1..k, switching to
+# |error| / sigma_1 below 10 sqrt(c) u sigma_1; singular subspaces within
+# TOL / g_j where g_j = (sigma_j - sigma_{j+1}) / sigma_1.
+TOL_FP64 = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(A: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(A)).to("cuda")
+
+
+def download_store(st: zs.Store):
+    """All block factors of a GPU store, in the oracle's layout."""
+    U = np.zeros((st.t, st.k))
+    S = np.zeros((st.nb, st.k))
+    V = np.zeros((st.nb, st.c, st.k))
+    kk = np.zeros(st.nb, np.int32)
+    for i in range(st.nb):
+        Ui, Si, Vi, ki = zs.zs_store_get_block(st, i)
+        torch.cuda.synchronize()
+        r = st.block_rows(i)
+        U[i * st.b:i * st.b + r] = Ui.double().cpu().numpy()
+        S[i] = Si.cpu().numpy()
+        V[i] = Vi.double().cpu().numpy()
+        kk[i] = int(ki.item())
+    return U, S, V, kk
+
+
+def compare_svd(got, ref, tol, c, what=""):
+    """got/ref = (U, s, V, k_out).  Asserts sigma, orthonormality, subspaces."""
+    Ug, sg, Vg, kg = got
+    Ur, sr, Vr, kr = ref
+    assert kg == kr, "%s: k_out %d vs %d" % (what, kg, kr)
+    floor = 10.0 * np.sqrt(c) * 1.1e-16
+    e = check_sigma(sg, sr, tol, floor)
+    assert e <= 1.0, "%s: sigma error %.3g x tol" % (what, e)
+    assert np.all(sg[kg:] == 0), what
+    assert np.all(Ug[:, kg:] == 0) and np.all(Vg[:, kg:] == 0), what
+    assert orth_err(Vg[:, :kg]) < 1e-12, what
+    assert orth_err(Ug[:, :kg]) < 1e-11, what
+    ev = subspace_errs(Vg[:, :kg], Vr[:, :kg], sr[:kg], tol)
+    eu = subspace_errs(Ug[:, :kg], Ur[:, :kg], sr[:kg], tol)
+    assert ev <= 1.0 and eu <= 1.0, "%s: subspace errors V %.3g U %.3g (x tol/gap)" % (what, ev, eu)
+    # sign rule: largest-|v| entry positive
+    for j in range(kg):
+        assert Vg[np.argmax(np.abs(Vg[:, j])), j] > 0, what
+    return e, ev, eu

@@ -1,0 +1,174 @@
+"""GPU parity of the HIP path against the CPU oracle (FP64 mode).
+
+Decoupled, as the storage phase's truncation is not unique when two singular
+values of a block tie at the cut: (1) store parity block by block against
+the oracle's storage phase; (2) query parity by running the oracle's query
+phase on the store downloaded from the GPU; (3) end-to-end against the
+direct SVD of the raw rows on block-rank-<=k data, where the method is exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1805_00754_amd import synth
+from paper_1805_00754_amd import zoomsvd as zs
+from tests.gpu_common import TOL_FP64, compare_svd, download_store, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    zs.load()
+    oracle.load()
+
+
+def gpu_store(A, b, k):
+    st = zs.zs_store_blocks(to_dev(A), b, k)
+    torch.cuda.synchronize()
+    return st
+
+
+def gpu_query(st, ts, te, kq):
+    U, S, V, ko = zs.zs_query(st, ts, te, kq)
+    zs.zs_sync_status(st)       # raises on an eigen-solve that hit its sweep cap
+    return U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy(), int(ko.item())
+
+
+def check_store(A, b, k, what):
+    say("store parity", what, A.shape, "b", b, "k", k)
+    st = gpu_store(A, b, k)
+    Ug, Sg, Vg, kg = download_store(st)
+    ost = oracle.store(A, b, k)
+    c = A.shape[1]
+    for i in range(st.nb):
+        r = st.block_rows(i)
+        got = (Ug[i * b:i * b + r], Sg[i], Vg[i], int(kg[i]))
+        ref = (ost.U[i * b:i * b + r], ost.S[i], ost.V[i], int(ost.k_i[i]))
+        compare_svd(got, ref, TOL_FP64, c, "%s block %d" % (what, i))
+    return st, (Ug, Sg, Vg, kg)
+
+
+# ------------------------------------------------------------------ storage
+@pytest.mark.parametrize("t,c,b,k", [(10_000, 64, 100, 10), (21_100, 128, 1000, 20),
+                                     (3_050, 9, 128, 4), (700, 33, 64, 33), (50, 16, 100, 8)])
+def test_store_parity_sinmix(t, c, b, k):
+    ser = synth.sinusoid_mixture(t, c, sources=min(8, c), seed=7 + c, noise="iid", noise_sigma=0.1)
+    check_store(ser.A, b, k, "sinmix %dx%d" % (t, c))
+
+
+def test_store_parity_rank_deficient_and_zero_block():
+    t, c, b, k = 1_000, 24, 100, 6
+    A = synth.block_low_rank(t, c, b, rank=3, seed=5)
+    A[300:400] = 0.0                  # an all-zero block
+    st, (Ug, Sg, Vg, kg) = check_store(A, b, k, "rank3")
+    assert kg[3] == 0 and np.all(Sg[3] == 0)
+    assert all(kg[i] == 3 for i in range(st.nb) if i != 3)
+
+
+# ------------------------------------------------------------------ queries
+QUERY_RANGES = [(0, 10_000), (37, 9_963), (100, 200), (150, 151), (199, 201), (4_321, 4_399),
+                (5_000, 5_100), (0, 1), (9_999, 10_000), (250, 8_250)]
+
+
+@pytest.fixture(scope="module")
+def sinmix64():
+    ser, cfg = synth.workload("sinmix_10k_x64_f64")
+    st = gpu_store(ser.A, cfg["b"], cfg["k"])
+    U, S, V, kk = download_store(st)
+    ost = oracle.store_from_arrays(st.t, st.c, st.b, st.k, U, S, V, kk)
+    return ser.A, cfg, st, ost
+
+
+@pytest.mark.parametrize("rng", QUERY_RANGES)
+@pytest.mark.parametrize("kq", [10, 3])
+def test_query_parity_on_gpu_store(sinmix64, rng, kq):
+    A, cfg, st, ost = sinmix64
+    ts, te = rng
+    say("query parity", ts, te, kq)
+    got = gpu_query(st, ts, te, kq)
+    ref = oracle.query(ost, ts, te, kq)
+    compare_svd(got, ref, TOL_FP64, st.c, "query [%d,%d) kq %d" % (ts, te, kq))
+
+
+def test_query_exact_on_block_low_rank():
+    """Block rank <= k: the stitched SVD equals the direct SVD of A[t_s:t_e)."""
+    t, c, b, k = 5_300, 40, 100, 6
+    A = synth.block_low_rank(t, c, b, rank=5, seed=9)
+    st = gpu_store(A, b, k)
+    for ts, te in [(0, 5_300), (37, 4_563), (120, 180), (99, 101), (200, 300), (5_250, 5_300)]:
+        say("exact", ts, te)
+        got = gpu_query(st, ts, te, k)
+        ref = oracle.direct(A, ts, te, k)
+        compare_svd(got, ref, TOL_FP64, c, "exact [%d,%d)" % (ts, te))
+
+
+def test_rank_one_closed_form():
+    t, c, b = 4_000, 12, 256
+    A, s_vec, m = synth.rank_one(t, c, seed=3)
+    st = gpu_store(A, b, 4)
+    for ts, te in [(0, 4_000), (10, 3_900), (256, 512), (255, 257), (3_999, 4_000)]:
+        U, S, V, ko = gpu_query(st, ts, te, 4)
+        assert ko == 1
+        np.testing.assert_allclose(S[0], np.linalg.norm(s_vec[ts:te]) * np.linalg.norm(m),
+                                   rtol=1e-12)
+        assert np.all(S[1:] == 0)
+        u = s_vec[ts:te] / np.linalg.norm(s_vec[ts:te])
+        assert abs(abs(U[:, 0] @ u) - 1) < 1e-12
+        assert abs(abs(V[:, 0] @ (m / np.linalg.norm(m))) - 1) < 1e-12
+
+
+def test_short_matrix_single_short_block():
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((37, 20))
+    st = gpu_store(A, 100, 8)
+    got = gpu_query(st, 3, 30, 8)
+    ost = oracle.store(A, 100, 8)
+    ref = oracle.query(ost, 3, 30, 8)
+    compare_svd(got, ref, TOL_FP64, 20, "short")
+
+
+# ------------------------------------------------------------------ batching
+def test_batch_equals_single_bitwise(sinmix64):
+    A, cfg, st, ost = sinmix64
+    rng = synth.rng_for(11)
+    ts, te = synth.queries_uniform(rng, st.t, 40, 150, 8_000)
+    kq = rng.integers(1, st.k + 1, size=40).astype(np.int32)
+    batch = zs.zs_query_batch(st, ts, te, kq)
+    torch.cuda.synchronize()
+    for q in range(len(ts)):
+        Ub, Sb, Vb, kb = [x.cpu().numpy() for x in batch.result(q)]
+        Us, Ss, Vs, ks = gpu_query(st, int(ts[q]), int(te[q]), int(kq[q]))
+        assert int(kb[0]) == ks
+        np.testing.assert_array_equal(Sb, Ss)
+        np.testing.assert_array_equal(Vb, Vs)
+        np.testing.assert_array_equal(Ub, Us)
+
+
+def test_batch_matches_oracle(sinmix64):
+    A, cfg, st, ost = sinmix64
+    rng = synth.rng_for(12)
+    ts, te = synth.queries_uniform(rng, st.t, 20, 150, 8_000)
+    batch = zs.zs_query_batch(st, ts, te, st.k)
+    zs.zs_sync_status(st)
+    refs = oracle.query_batch(ost, ts, te, st.k)
+    for q in range(len(ts)):
+        got = [x.cpu().numpy() for x in batch.result(q)]
+        got[3] = int(got[3][0])
+        compare_svd(tuple(got), refs[q], TOL_FP64, st.c, "batch q%d" % q)
+
+
+def test_sync_status_ok(sinmix64):
+    A, cfg, st, ost = sinmix64
+    zs.zs_query(st, 0, 500, 5)
+    zs.zs_sync_status(st)
+
+
+def test_bad_query_raises(sinmix64):
+    A, cfg, st, ost = sinmix64
+    for ts, te, kq in [(-1, 5, 2), (5, 5, 2), (0, st.t + 1, 2), (0, 10, 0), (0, 10, st.k + 1)]:
+        with pytest.raises(zs.ZSError) as ei:
+            zs.zs_query(st, ts, te, kq)
+        assert ei.value.status == zs.ZS_ERANGE
