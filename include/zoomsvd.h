@@ -108,7 +108,9 @@ zs_status zs_query_batch(const zs_store *st, int32_t nq, const int64_t *t_s, con
 /* Releases the store's device memory (synchronises the device first). */
 void zs_store_free(zs_store *st);
 
-/* Device bytes held by the store (factors only, not scratch). */
+/* Device bytes held by the store: the block factors and the Gram tree of the
+ * blocks (2 n2 c x c FP64 matrices, n2 = smallest power of two >= nb), not the
+ * per-stream query scratch. */
 int64_t zs_store_bytes(const zs_store *st);
 
 /* Shape of a store: any pointer may be null. */

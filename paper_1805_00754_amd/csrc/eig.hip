@@ -3,7 +3,9 @@
 //
 // This is the first stage of every rank-k SVD the method takes (the block
 // SVD of the storage phase and the SVD of a query's stacked matrix):
-//   1. G  <- sum of the problem's partial Grams (fixed order);
+//   1. G  <- sum of the problem's Gram terms (fixed order): partial Grams of
+//            a block's row chunks, or, for a query, the Gram-tree nodes that
+//            cover its whole blocks plus the Grams of its Partial-SVD rows;
 //   2. L  <- Cholesky factor of G + s I, s = 4 (c+1) eps tr(G).  The shift
 //            keeps the factorisation alive on rank-deficient input and does
 //            not move the eigenvectors of G;
@@ -33,8 +35,9 @@ __device__ __forceinline__ void rr_pair(int step, int pi, int N, int &p, int &q)
 }
 
 template <int NMAX>
-__global__ __launch_bounds__(kThreads) void eig_kernel(int c, const Prob *__restrict__ probs,
-                                                       const double *__restrict__ Gpart,
+__global__ __launch_bounds__(kThreads) void eig_kernel(int c, int k, const Prob *__restrict__ probs,
+                                                       const double *const *__restrict__ gsrc,
+                                                       const double *const *__restrict__ msrc,
                                                        double *__restrict__ Vk,
                                                        int *__restrict__ conv_flag)
 {
@@ -43,22 +46,39 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(int c, const Prob *__rest
     constexpr int TPP0 = kThreads / NP;
     constexpr int TPP = TPP0 < NMAX / 2 ? TPP0 : NMAX / 2;
     constexpr int ELEMS = (NMAX + TPP - 1) / TPP;
+    constexpr int MR = 8;              // rows of a k x c block staged at a time
     extern __shared__ __align__(16) double smem[];
     double *X = smem;                  // column-major, column j at X + j * LDX
     double *nu = X + NMAX * LDX;       // column norms
+    double *Rs = nu + NMAX;            // MR x c staging of row blocks
     __shared__ int rot_count;
     __shared__ double sh_shift, sh_tr;
 
     const Prob P = probs[blockIdx.x];
     const int tid = threadIdx.x;
-    const int64_t cc = (int64_t)c * c;
 
-    // 1. G = sum of partial Grams (symmetric: column-major == row-major).
+    // 1. G = sum of the problem's c x c Gram terms (fixed order) plus the
+    //    Grams R^T R of its k x c row blocks.  Symmetric: column-major == row-major.
     for (int e = tid; e < c * c; e += kThreads) {
         const int i = e / c, j = e % c;
         double s = 0.0;
-        for (int sl = 0; sl < P.nslots; ++sl) s += Gpart[(int64_t)(P.slot0 + sl) * cc + e];
+        for (int g = 0; g < P.ng; ++g) s += gsrc[P.g0 + g][e];
         X[j * LDX + i] = s;
+    }
+    for (int m = 0; m < P.nm; ++m) {
+        const double *R = msrc[P.m0 + m];
+        for (int r0 = 0; r0 < k; r0 += MR) {
+            const int nr = min(MR, k - r0);
+            __syncthreads();
+            for (int e = tid; e < nr * c; e += kThreads) Rs[e] = R[(int64_t)r0 * c + e];
+            __syncthreads();
+            for (int e = tid; e < c * c; e += kThreads) {
+                const int i = e / c, j = e % c;
+                double s = X[j * LDX + i];
+                for (int r = 0; r < nr; ++r) s = fma(Rs[r * c + i], Rs[r * c + j], s);
+                X[j * LDX + i] = s;
+            }
+        }
     }
     __syncthreads();
     if (tid == 0) {
@@ -181,34 +201,30 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(int c, const Prob *__rest
 }
 
 template <int NMAX>
-hipError_t run_eig(int c, const Prob *probs, int nprob, const double *Gpart, double *Vk,
-                   int *conv_flag, hipStream_t stream)
+hipError_t run_eig(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
+                   const double *const *msrc, double *Vk, int *conv_flag, hipStream_t stream)
 {
-    const size_t lds = (size_t)(NMAX * (NMAX + 1) + NMAX) * sizeof(double);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)eig_kernel<NMAX>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    eig_kernel<NMAX><<<nprob, kThreads, lds, stream>>>(c, probs, Gpart, Vk, conv_flag);
+    const size_t lds = (size_t)(NMAX * (NMAX + 1) + NMAX + 8 * NMAX) * sizeof(double);
+    static size_t cur = 0;
+    hipError_t e = ensure_lds((const void *)eig_kernel<NMAX>, lds, cur);
+    if (e != hipSuccess) return e;
+    eig_kernel<NMAX><<<nprob, kThreads, lds, stream>>>(c, k, probs, gsrc, msrc, Vk, conv_flag);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_eig(int c, const Prob *probs, int nprob, const double *Gpart, double *Vk,
-                      int *conv_flag, hipStream_t stream)
+hipError_t launch_eig(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
+                      const double *const *msrc, double *Vk, int *conv_flag, hipStream_t stream)
 {
     if (nprob <= 0) return hipSuccess;
     if (c > kMaxC) return hipErrorInvalidValue;
     timing_begin("eig", stream);
     hipError_t e;
-    if (c <= 16) e = run_eig<16>(c, probs, nprob, Gpart, Vk, conv_flag, stream);
-    else if (c <= 32) e = run_eig<32>(c, probs, nprob, Gpart, Vk, conv_flag, stream);
-    else if (c <= 64) e = run_eig<64>(c, probs, nprob, Gpart, Vk, conv_flag, stream);
-    else e = run_eig<128>(c, probs, nprob, Gpart, Vk, conv_flag, stream);
+    if (c <= 16) e = run_eig<16>(c, k, probs, nprob, gsrc, msrc, Vk, conv_flag, stream);
+    else if (c <= 32) e = run_eig<32>(c, k, probs, nprob, gsrc, msrc, Vk, conv_flag, stream);
+    else if (c <= 64) e = run_eig<64>(c, k, probs, nprob, gsrc, msrc, Vk, conv_flag, stream);
+    else e = run_eig<128>(c, k, probs, nprob, gsrc, msrc, Vk, conv_flag, stream);
     timing_end("eig", stream);
     return e;
 }

@@ -1,7 +1,5 @@
 // Query-phase kernels around the stacked SVD (Alg. 2):
 //
-//  * gather: the stack rows of whole blocks, Sigma_(i) V_(i)^T (Alg. 2 line 2);
-//    boundary blocks cut by the range get theirs from the Partial-SVD.
 //  * coef: per touched block, the k x kq factor C_i with
 //    U_(S:E) rows of block i = U_(i)[r0:r1) C_i.  For a whole block
 //    C_i = U_r(i) (its rows of U_r = Y F); for a boundary block
@@ -14,22 +12,6 @@
 
 namespace zs {
 namespace {
-
-__global__ __launch_bounds__(kThreads) void gather_kernel(StoreView st,
-                                                          const Piece *__restrict__ pieces,
-                                                          double *__restrict__ M)
-{
-    const Piece pc = pieces[blockIdx.x];
-    if (pc.t_idx >= 0) return;             // boundary block: written by the Partial-SVD
-    const int k = st.k;
-    const int64_t c = st.c;
-    const double *Vt = st.Vt + pc.blk * k * c;
-    const double *S = st.S + pc.blk * k;
-    for (int64_t e = threadIdx.x; e < k * c; e += kThreads) {
-        const int j = (int)(e / c);
-        M[pc.m_row * c + e] = S[j] * Vt[e];
-    }
-}
 
 __global__ __launch_bounds__(kThreads) void coef_kernel(int k, const Piece *__restrict__ pieces,
                                                         const double *__restrict__ Y,
@@ -111,17 +93,6 @@ __global__ __launch_bounds__(kThreads) void blockprod_kernel(StoreView st,
 }
 
 }  // namespace
-
-hipError_t launch_gather(StoreView st, const Piece *pieces, int npieces, double *M,
-                         hipStream_t stream)
-{
-    if (npieces <= 0) return hipSuccess;
-    timing_begin("gather", stream);
-    gather_kernel<<<npieces, kThreads, 0, stream>>>(st, pieces, M);
-    hipError_t e = hipGetLastError();
-    timing_end("gather", stream);
-    return e;
-}
 
 hipError_t launch_coef(int k, const Piece *pieces, int npieces, const double *Y, const double *F,
                        const double *T, double *C, hipStream_t stream)

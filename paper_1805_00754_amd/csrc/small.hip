@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *_
     for (int e = tid; e < kk * kk; e += kThreads) {
         const int a = e / kk, b = e % kk;
         double s = 0.0;
-        for (int sl = 0; sl < P.nslots; ++sl) s += GYpart[(int64_t)(P.slot0 + sl) * kSlotK + e];
+        for (int sl = 0; sl < P.ny; ++sl) s += GYpart[(int64_t)(P.y0 + sl) * kSlotK + e];
         G[a * LDS_N + b] = s;
         W[a * LDS_N + b] = (a == b) ? 1.0 : 0.0;
     }
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *_
 __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
                                                            const Piece *__restrict__ pieces,
                                                            const int32_t *__restrict__ pidx,
-                                                           double *__restrict__ M,
+                                                           double *__restrict__ Mp,
                                                            double *__restrict__ T, double rank_tol,
                                                            int *__restrict__ conv_flag)
 {
@@ -311,13 +311,14 @@ __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
     double smax = 0.0;
     for (int j = 0; j < k; ++j) smax = fmax(smax, sig[j]);
 
-    // stack rows: M[m_row + j] = sigma~_j (V_(i) v~_j)^T = sigma~_j sum_l v~_lj V_(i)^T[l]
+    // stack rows: Mp[j] = sigma~_j (V_(i) v~_j)^T = sigma~_j sum_l v~_lj V_(i)^T[l]
     const double *Vt = st.Vt + pc.blk * k * st.c;
+    double *Mrows = Mp + (int64_t)pc.t_idx * k * c;
     for (int e = tid; e < k * c; e += kThreads) {
         const int j = e / c, col = e % c;
         double s = 0.0;
         for (int l = 0; l < k; ++l) s = fma(G[l * LDS_N + j], Vt[(int64_t)l * c + col], s);
-        M[(pc.m_row + j) * c + col] = sig[j] * s;
+        Mrows[e] = sig[j] * s;
     }
     // T = Sigma_(i) V~ Sigma~^+  (k x k, row-major)
     double *Tp = T + (int64_t)pc.t_idx * k * k;
@@ -337,13 +338,10 @@ hipError_t launch_finalize(int c, const Prob *probs, int nprob, const double *GY
     if (nprob <= 0) return hipSuccess;
     timing_begin("finalize", stream);
     const size_t lds = (size_t)(2 * kMaxK * LDS_N + c * kMaxK) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)finalize_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)((2 * kMaxK * LDS_N + kMaxC * kMaxK) * sizeof(double)));
+    static size_t cur = 0;
+    {
+        hipError_t e = ensure_lds((const void *)finalize_kernel, lds, cur);
         if (e != hipSuccess) return e;
-        attr = true;
     }
     finalize_kernel<<<nprob, kThreads, lds, stream>>>(c, probs, GYpart, Vk, F, rank_tol, conv_flag);
     hipError_t e = hipGetLastError();
@@ -352,20 +350,18 @@ hipError_t launch_finalize(int c, const Prob *probs, int nprob, const double *GY
 }
 
 hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx, int npartial,
-                          double *M, double *T, double rank_tol, int *conv_flag,
+                          double *Mp, double *T, double rank_tol, int *conv_flag,
                           hipStream_t stream)
 {
     if (npartial <= 0) return hipSuccess;
     timing_begin("partial", stream);
     const size_t lds = (size_t)(3 * kMaxK * LDS_N + 2 * 32 * kMaxK) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)partial_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    static size_t cur = 0;
+    {
+        hipError_t e = ensure_lds((const void *)partial_kernel, lds, cur);
         if (e != hipSuccess) return e;
-        attr = true;
     }
-    partial_kernel<<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, M, T, rank_tol, conv_flag);
+    partial_kernel<<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T, rank_tol, conv_flag);
     hipError_t e = hipGetLastError();
     timing_end("partial", stream);
     return e;

@@ -24,10 +24,22 @@ struct Chunk {
     int32_t kk;       // columns of Y (the rank wanted for the problem)
 };
 
+// A run of whole pieces of one query's stacked matrix (projection kernel).
+struct StackChunk {
+    int64_t y_off;    // element offset of the chunk's first stack row in Y (row length kk)
+    int32_t piece0;   // first piece of the chunk
+    int32_t npieces;  // pieces in the chunk (k stack rows each)
+    int32_t prob;     // query
+    int32_t slot;     // G_Y partial-sum slot
+    int32_t kk;       // k_q of the query
+    int32_t pad;
+};
+
 // One eigen / finalisation problem (a block of the store or a query).
 struct Prob {
-    int32_t slot0;    // first partial-sum slot of this problem
-    int32_t nslots;   // number of partial-sum slots
+    int32_t g0, ng;   // c x c Gram terms: gsrc[g0 .. g0+ng)
+    int32_t m0, nm;   // k x c row blocks whose Gram is added: msrc[m0 .. m0+nm)
+    int32_t y0, ny;   // G_Y partial-sum slots
     int32_t kk;       // triplets wanted
     int32_t pad;
     double *v_dst;    // V(a, j) written at v_dst[a * v_rs + j * v_cs]
@@ -39,7 +51,6 @@ struct Prob {
 // One touched block of one query (a piece of the stitched range).
 struct Piece {
     int64_t blk;      // block index i
-    int64_t m_row;    // first row of its k stack rows in the batch's stack buffer M
     int64_t y_off;    // element offset of its k rows in the batch's Y buffer (row length kq)
     int64_t c_off;    // element offset of its k x kq coefficient matrix in the C buffer
     int64_t out_off;  // element offset of its first output row in the caller's U
@@ -47,7 +58,7 @@ struct Piece {
     int32_t r0, r1;   // kept rows of the block
     int32_t q;        // query index
     int32_t kq;       // requested rank of the query
-    int32_t t_idx;    // slot in the Partial-SVD factor buffer, -1 for a whole block
+    int32_t t_idx;    // Partial-SVD slot (stack rows Mp, factor T), -1 for a whole block
     int32_t pad;
 };
 
@@ -64,24 +75,43 @@ struct StoreView {
 // All launches are asynchronous on `stream` and return the launch status.
 hipError_t launch_gram(const double *X, int64_t ld, int c, const Chunk *chunks, int nchunks,
                        double *Gpart, hipStream_t stream);
-hipError_t launch_eig(int c, const Prob *probs, int nprob, const double *Gpart, double *Vk,
-                      int *conv_flag, hipStream_t stream);
+hipError_t launch_eig(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
+                      const double *const *msrc, double *Vk, int *conv_flag, hipStream_t stream);
 hipError_t launch_project(const double *X, int64_t ld, int c, const Chunk *chunks, int nchunks,
-                          const double *Vk, double *Y, double *GYpart, hipStream_t stream);
+                          int kk, const double *Vk, double *Y, double *GYpart, hipStream_t stream);
+hipError_t launch_stack_project(StoreView st, const Piece *pieces, const double *Mp,
+                                const StackChunk *chunks, int nchunks, int kq_max,
+                                const double *Vk, double *Y, double *GYpart, hipStream_t stream);
 hipError_t launch_finalize(int c, const Prob *probs, int nprob, const double *GYpart,
                            const double *Vk, double *F, double rank_tol, int *conv_flag,
                            hipStream_t stream);
 hipError_t launch_utransform(double *U, int k, const Chunk *chunks, int nchunks, const double *F,
                              hipStream_t stream);
+hipError_t launch_leaf_gram(StoreView st, int64_t nleaves, double *tree, int64_t leaf0,
+                            hipStream_t stream);
+hipError_t launch_tree_level(int c, double *tree, int64_t node0, int64_t nnodes,
+                             hipStream_t stream);
 hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx, int npartial,
-                          double *M, double *T, double rank_tol, int *conv_flag,
+                          double *Mp, double *T, double rank_tol, int *conv_flag,
                           hipStream_t stream);
-hipError_t launch_gather(StoreView st, const Piece *pieces, int npieces, double *M,
-                         hipStream_t stream);
 hipError_t launch_coef(int k, const Piece *pieces, int npieces, const double *Y, const double *F,
                        const double *T, double *C, hipStream_t stream);
 hipError_t launch_blockprod(StoreView st, const Piece *pieces, int npieces, const double *C,
                             double *U, hipStream_t stream);
+
+// Raises a kernel's dynamic-LDS limit to `bytes` if it is below (the limit
+// only grows; `cur` caches the value set).  Clears the error state on failure.
+inline hipError_t ensure_lds(const void *kernel, size_t bytes, size_t &cur)
+{
+    if (bytes <= cur) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e;
+    }
+    cur = bytes;
+    return hipSuccess;
+}
 
 // Kernel timing hooks (implemented in the runtime).
 void timing_begin(const char *name, hipStream_t stream);

@@ -85,13 +85,13 @@ struct DevBuf {
 
 // Scratch of the query pipeline for one stream (grow-only).
 struct Workspace {
-    DevBuf M, Gpart, Vk, Y, GY, F, T, C, desc;
+    DevBuf Mp, Vk, Y, GY, F, T, C, desc;
     void *host = nullptr;        // pinned staging of the descriptors
     size_t host_bytes = 0;
     hipEvent_t copied = nullptr; // the last upload from `host` has completed
     void release()
     {
-        M.release(); Gpart.release(); Vk.release(); Y.release(); GY.release();
+        Mp.release(); Vk.release(); Y.release(); GY.release();
         F.release(); T.release(); C.release(); desc.release();
         if (host) (void)hipHostFree(host);
         if (copied) (void)hipEventDestroy(copied);
@@ -111,6 +111,8 @@ struct zs_store {
     int device = 0;
     double *U = nullptr, *Vt = nullptr, *S = nullptr;
     int32_t *kvec = nullptr;
+    double *tree = nullptr;       // Gram tree: 2 * n2 nodes of c x c (node 0 unused)
+    int64_t n2 = 1;               // leaves of the Gram tree (power of two >= nb)
     int *conv = nullptr;          // set by kernels when a Jacobi hits its cap
     std::mutex mu;
     std::map<hipStream_t, Workspace *> ws;
@@ -152,7 +154,7 @@ namespace {
 
 // Chunking of tall-skinny row runs for the Gram / projection kernels.
 constexpr int kStoreChunkRows = 2048;
-constexpr int kQueryChunkRows = 512;
+constexpr int kQueryChunkPieces = 32;   // whole pieces per projection work-group
 
 // Upload `bytes` of host data through the workspace's pinned staging buffer.
 zs_status upload(Workspace &w, const void *src, size_t bytes, hipStream_t stream)
@@ -193,20 +195,28 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
     const int64_t c = st->c, b = st->b;
     const int32_t k = st->k;
     // ---- plan (Alg. 3 lines 1-3 for every query) --------------------------------
+    // Pieces: the touched blocks; boundary blocks cut by the range go through the
+    // Partial-SVD.  Whole blocks form one contiguous run [a, e) whose Gram comes
+    // from the Gram tree.  Every per-query quantity depends only on the query.
     std::vector<Piece> pieces;
-    std::vector<int32_t> pidx;        // pieces that need a Partial-SVD
-    std::vector<Chunk> chunks;
+    std::vector<int32_t> pidx;          // pieces that need a Partial-SVD
+    std::vector<StackChunk> chunks;
     std::vector<Prob> probs(nq);
-    int64_t m_rows = 0, y_elems = 0, c_elems = 0;
-    // Fixed chunking: a query's partial sums never depend on the rest of the batch.
-    const int chunk_rows = kQueryChunkRows;
-    int32_t slot = 0;
+    std::vector<int64_t> gsrc_off;      // tree node indices (converted to pointers below)
+    std::vector<int32_t> msrc_idx;      // Partial-SVD slots
+    int64_t y_elems = 0, c_elems = 0;
+    int32_t slot = 0, kq_max = 1;
     for (int32_t q = 0; q < nq; ++q) {
+        kq_max = std::max(kq_max, kq[q]);
         const int64_t S_ = ts[q] / b, E_ = (te[q] - 1) / b;
         const int64_t lo = ts[q] - S_ * b, hi = te[q] - E_ * b;
         const int64_t np = E_ - S_ + 1;
-        const int64_t Kq = np * k;
-        const int64_t m0 = m_rows, y0 = y_elems;
+        const int64_t y0 = y_elems;
+        const int32_t piece0 = (int32_t)pieces.size();
+        Prob pr;
+        std::memset(&pr, 0, sizeof pr);
+        pr.m0 = (int32_t)msrc_idx.size();
+        int64_t whole_a = -1, whole_e = -1;
         for (int64_t p = 0; p < np; ++p) {
             const int64_t i = S_ + p;
             const int64_t rows = st->block_rows(i);
@@ -215,7 +225,6 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
             pc.blk = i;
             pc.r0 = (int32_t)(i == S_ ? lo : 0);
             pc.r1 = (int32_t)(i == E_ ? hi : rows);
-            pc.m_row = m0 + p * k;
             pc.y_off = y0 + p * k * kq[q];
             pc.c_off = c_elems;
             c_elems += (int64_t)k * kq[q];
@@ -225,23 +234,41 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
             pc.kq = kq[q];
             const bool partial = pc.r0 != 0 || pc.r1 != rows;
             pc.t_idx = partial ? (int32_t)pidx.size() : -1;
-            if (partial) pidx.push_back((int32_t)pieces.size());
+            if (partial) {
+                msrc_idx.push_back(pc.t_idx);
+                pidx.push_back((int32_t)pieces.size());
+            } else {
+                if (whole_a < 0) whole_a = i;
+                whole_e = i + 1;
+            }
             pieces.push_back(pc);
         }
-        Prob pr;
-        std::memset(&pr, 0, sizeof pr);
-        pr.slot0 = slot;
-        for (int64_t r = 0; r < Kq; r += chunk_rows) {
-            Chunk ch;
-            ch.x_off = (m0 + r) * c;
-            ch.y_off = y0 + r * kq[q];
-            ch.rows = (int32_t)std::min<int64_t>(chunk_rows, Kq - r);
+        pr.nm = (int32_t)msrc_idx.size() - pr.m0;
+        // Whole blocks [whole_a, whole_e) are contiguous: cover them with tree nodes.
+        pr.g0 = (int32_t)gsrc_off.size();
+        if (whole_a >= 0) {
+            int64_t l = whole_a + st->n2, r = whole_e + st->n2;
+            while (l < r) {
+                if (l & 1) gsrc_off.push_back(l++);
+                if (r & 1) gsrc_off.push_back(--r);
+                l >>= 1;
+                r >>= 1;
+            }
+        }
+        pr.ng = (int32_t)gsrc_off.size() - pr.g0;
+        pr.y0 = slot;
+        for (int64_t p = 0; p < np; p += kQueryChunkPieces) {
+            StackChunk ch;
+            std::memset(&ch, 0, sizeof ch);
+            ch.y_off = y0 + p * k * kq[q];
+            ch.piece0 = piece0 + (int32_t)p;
+            ch.npieces = (int32_t)std::min<int64_t>(kQueryChunkPieces, np - p);
             ch.prob = q;
             ch.slot = slot++;
             ch.kk = kq[q];
             chunks.push_back(ch);
         }
-        pr.nslots = slot - pr.slot0;
+        pr.ny = slot - pr.y0;
         pr.kk = kq[q];
         pr.v_dst = V + v_off[q];
         pr.v_rs = ldv[q];
@@ -249,8 +276,7 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
         pr.s_dst = S + s_off[q];
         pr.k_dst = k_out + q;
         probs[q] = pr;
-        m_rows += Kq;
-        y_elems += Kq * kq[q];
+        y_elems += np * k * kq[q];
     }
     // ---- workspace ---------------------------------------------------------------
     Workspace *w;
@@ -262,35 +288,38 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
     }
     const int nchunks = (int)chunks.size(), npieces = (int)pieces.size();
     const int npartial = (int)pidx.size();
-    HIP_TRY(w->M.ensure(sizeof(double) * std::max<int64_t>(1, m_rows * c)));
-    HIP_TRY(w->Gpart.ensure(sizeof(double) * std::max<int64_t>(1, (int64_t)nchunks * c * c)));
+    HIP_TRY(w->Mp.ensure(sizeof(double) * std::max<int64_t>(1, (int64_t)npartial * k * c)));
     HIP_TRY(w->Vk.ensure(sizeof(double) * (size_t)nq * c * kMaxK));
     HIP_TRY(w->Y.ensure(sizeof(double) * std::max<int64_t>(1, y_elems)));
     HIP_TRY(w->GY.ensure(sizeof(double) * (size_t)nchunks * kSlotK));
     HIP_TRY(w->F.ensure(sizeof(double) * (size_t)nq * kSlotK));
     HIP_TRY(w->T.ensure(sizeof(double) * std::max<int64_t>(1, (int64_t)npartial * k * k)));
     HIP_TRY(w->C.ensure(sizeof(double) * std::max<int64_t>(1, c_elems)));
+    double *Mp = w->Mp.as<double>();
+    std::vector<const double *> gsrc(gsrc_off.size()), msrc(msrc_idx.size());
+    for (size_t i = 0; i < gsrc_off.size(); ++i) gsrc[i] = st->tree + gsrc_off[i] * c * c;
+    for (size_t i = 0; i < msrc_idx.size(); ++i) msrc[i] = Mp + (int64_t)msrc_idx[i] * k * c;
     Blob blob;
     const size_t o_chunks = blob.add(chunks), o_probs = blob.add(probs);
     const size_t o_pieces = blob.add(pieces), o_pidx = blob.add(pidx);
+    const size_t o_gsrc = blob.add(gsrc), o_msrc = blob.add(msrc);
     zs_status s = upload(*w, blob.bytes.data(), blob.bytes.size(), stream);
     if (s != ZS_OK) return s;
     char *d = w->desc.as<char>();
-    const Chunk *d_chunks = (const Chunk *)(d + o_chunks);
+    const StackChunk *d_chunks = (const StackChunk *)(d + o_chunks);
     const Prob *d_probs = (const Prob *)(d + o_probs);
     const Piece *d_pieces = (const Piece *)(d + o_pieces);
     const int32_t *d_pidx = (const int32_t *)(d + o_pidx);
+    const double *const *d_gsrc = (const double *const *)(d + o_gsrc);
+    const double *const *d_msrc = (const double *const *)(d + o_msrc);
     const StoreView sv = st->view();
-    double *M = w->M.as<double>();
     // ---- launches ---------------------------------------------------------------
-    HIP_TRY(launch_partial(sv, d_pieces, d_pidx, npartial, M, w->T.as<double>(), kRankTolFP64,
+    HIP_TRY(launch_partial(sv, d_pieces, d_pidx, npartial, Mp, w->T.as<double>(), kRankTolFP64,
                            st->conv, stream));
-    HIP_TRY(launch_gather(sv, d_pieces, npieces, M, stream));
-    HIP_TRY(launch_gram(M, c, (int)c, d_chunks, nchunks, w->Gpart.as<double>(), stream));
-    HIP_TRY(launch_eig((int)c, d_probs, nq, w->Gpart.as<double>(), w->Vk.as<double>(), st->conv,
+    HIP_TRY(launch_eig((int)c, k, d_probs, nq, d_gsrc, d_msrc, w->Vk.as<double>(), st->conv,
                        stream));
-    HIP_TRY(launch_project(M, c, (int)c, d_chunks, nchunks, w->Vk.as<double>(), w->Y.as<double>(),
-                           w->GY.as<double>(), stream));
+    HIP_TRY(launch_stack_project(sv, d_pieces, Mp, d_chunks, nchunks, kq_max, w->Vk.as<double>(),
+                                 w->Y.as<double>(), w->GY.as<double>(), stream));
     HIP_TRY(launch_finalize((int)c, d_probs, nq, w->GY.as<double>(), w->Vk.as<double>(),
                             w->F.as<double>(), kRankTolFP64, st->conv, stream));
     HIP_TRY(launch_coef(k, d_pieces, npieces, w->Y.as<double>(), w->F.as<double>(),
@@ -355,6 +384,8 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
     ST_TRY(hipMalloc(&st->Vt, sizeof(double) * nb * k * c));
     ST_TRY(hipMalloc(&st->S, sizeof(double) * nb * k));
     ST_TRY(hipMalloc(&st->kvec, sizeof(int32_t) * nb));
+    while (st->n2 < nb) st->n2 *= 2;
+    ST_TRY(hipMalloc(&st->tree, sizeof(double) * 2 * st->n2 * c * c));
     ST_TRY(hipMalloc(&st->conv, sizeof(int)));
     ST_TRY(hipMemsetAsync(st->conv, 0, sizeof(int), stream));
 
@@ -366,7 +397,8 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
         const int64_t rows = st->block_rows(i);
         Prob pr;
         std::memset(&pr, 0, sizeof pr);
-        pr.slot0 = slot;
+        pr.g0 = slot;
+        pr.y0 = slot;
         for (int64_t r = 0; r < rows; r += kStoreChunkRows) {
             Chunk ch;
             ch.x_off = (i * b + r) * lda;
@@ -377,7 +409,8 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
             ch.kk = k;
             chunks.push_back(ch);
         }
-        pr.nslots = slot - pr.slot0;
+        pr.ng = slot - pr.g0;
+        pr.ny = slot - pr.y0;
         pr.kk = k;
         pr.v_dst = st->Vt + i * k * c;      // V_(i)^T: element (a, j) at j * c + a
         pr.v_rs = 1;
@@ -404,22 +437,29 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
     ST_TRY2(Vk.ensure(sizeof(double) * (size_t)nb * c * kMaxK));
     ST_TRY2(GY.ensure(sizeof(double) * (size_t)nchunks * kSlotK));
     ST_TRY2(F.ensure(sizeof(double) * (size_t)nb * kSlotK));
+    std::vector<const double *> gsrc(nchunks);
+    for (int s2 = 0; s2 < nchunks; ++s2) gsrc[s2] = Gpart.as<double>() + (int64_t)s2 * c * c;
     Blob blob;
-    const size_t o_chunks = blob.add(chunks), o_probs = blob.add(probs);
+    const size_t o_chunks = blob.add(chunks), o_probs = blob.add(probs), o_gsrc = blob.add(gsrc);
     ST_TRY2(desc.ensure(blob.bytes.size()));
     ST_TRY2(hipMemcpyAsync(desc.p, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice,
                            stream));
     const Chunk *d_chunks = (const Chunk *)(desc.as<char>() + o_chunks);
     const Prob *d_probs = (const Prob *)(desc.as<char>() + o_probs);
+    const double *const *d_gsrc = (const double *const *)(desc.as<char>() + o_gsrc);
     const double *Ad = static_cast<const double *>(A);
     ST_TRY2(launch_gram(Ad, lda, (int)c, d_chunks, nchunks, Gpart.as<double>(), stream));
-    ST_TRY2(launch_eig((int)c, d_probs, (int)nb, Gpart.as<double>(), Vk.as<double>(), st->conv,
+    ST_TRY2(launch_eig((int)c, k, d_probs, (int)nb, d_gsrc, nullptr, Vk.as<double>(), st->conv,
                        stream));
-    ST_TRY2(launch_project(Ad, lda, (int)c, d_chunks, nchunks, Vk.as<double>(), st->U,
+    ST_TRY2(launch_project(Ad, lda, (int)c, d_chunks, nchunks, k, Vk.as<double>(), st->U,
                            GY.as<double>(), stream));
     ST_TRY2(launch_finalize((int)c, d_probs, (int)nb, GY.as<double>(), Vk.as<double>(),
                             F.as<double>(), kRankTolFP64, st->conv, stream));
     ST_TRY2(launch_utransform(st->U, k, d_chunks, nchunks, F.as<double>(), stream));
+    // Gram tree over the stored blocks: leaves, then one launch per level.
+    ST_TRY2(launch_leaf_gram(st->view(), st->n2, st->tree, st->n2, stream));
+    for (int64_t lev = st->n2 / 2; lev >= 1; lev /= 2)
+        ST_TRY2(launch_tree_level((int)c, st->tree, lev, lev, stream));
     ST_TRY2(hipStreamSynchronize(stream));
     int conv = 0;
     ST_TRY2(hipMemcpy(&conv, st->conv, sizeof(int), hipMemcpyDeviceToHost));
@@ -485,6 +525,7 @@ void zs_store_free(zs_store *st)
     if (st->Vt) (void)hipFree(st->Vt);
     if (st->S) (void)hipFree(st->S);
     if (st->kvec) (void)hipFree(st->kvec);
+    if (st->tree) (void)hipFree(st->tree);
     if (st->conv) (void)hipFree(st->conv);
     delete st;
 }
@@ -492,7 +533,8 @@ void zs_store_free(zs_store *st)
 int64_t zs_store_bytes(const zs_store *st)
 {
     if (!st) return 0;
-    return (int64_t)sizeof(double) * (st->t * st->k + st->nb * st->k * st->c + st->nb * st->k) +
+    return (int64_t)sizeof(double) * (st->t * st->k + st->nb * st->k * st->c + st->nb * st->k +
+                                      2 * st->n2 * st->c * st->c) +
            (int64_t)sizeof(int32_t) * st->nb;
 }
 
