@@ -77,6 +77,8 @@ hipError_t launch_gram(const double *X, int64_t ld, int c, const Chunk *chunks, 
                        double *Gpart, hipStream_t stream);
 hipError_t launch_eig(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
                       const double *const *msrc, double *Vk, int *conv_flag, hipStream_t stream);
+hipError_t launch_eig_tri(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
+                          const double *const *msrc, double *Vk, hipStream_t stream);
 hipError_t launch_project(const double *X, int64_t ld, int c, const Chunk *chunks, int nchunks,
                           int kk, const double *Vk, double *Y, double *GYpart, hipStream_t stream);
 hipError_t launch_stack_project(StoreView st, const Piece *pieces, const double *Mp,

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -151,6 +152,19 @@ void timing_end(const char *name, hipStream_t stream)
 }  // namespace zs
 
 namespace {
+
+// First-stage eigen-solver: tridiagonalisation (default) or one-sided Jacobi
+// (ZS_EIG=jacobi), both on the same Gram terms.
+hipError_t first_stage_eig(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
+                           const double *const *msrc, double *Vk, int *conv, hipStream_t stream)
+{
+    static const bool use_jacobi = [] {
+        const char *v = getenv("ZS_EIG");
+        return v && std::strcmp(v, "jacobi") == 0;
+    }();
+    if (use_jacobi) return launch_eig(c, k, probs, nprob, gsrc, msrc, Vk, conv, stream);
+    return launch_eig_tri(c, k, probs, nprob, gsrc, msrc, Vk, stream);
+}
 
 // Chunking of tall-skinny row runs for the Gram / projection kernels.
 constexpr int kStoreChunkRows = 2048;
@@ -316,8 +330,8 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
     // ---- launches ---------------------------------------------------------------
     HIP_TRY(launch_partial(sv, d_pieces, d_pidx, npartial, Mp, w->T.as<double>(), kRankTolFP64,
                            st->conv, stream));
-    HIP_TRY(launch_eig((int)c, k, d_probs, nq, d_gsrc, d_msrc, w->Vk.as<double>(), st->conv,
-                       stream));
+    HIP_TRY(first_stage_eig((int)c, k, d_probs, nq, d_gsrc, d_msrc, w->Vk.as<double>(),
+                            st->conv, stream));
     HIP_TRY(launch_stack_project(sv, d_pieces, Mp, d_chunks, nchunks, kq_max, w->Vk.as<double>(),
                                  w->Y.as<double>(), w->GY.as<double>(), stream));
     HIP_TRY(launch_finalize((int)c, d_probs, nq, w->GY.as<double>(), w->Vk.as<double>(),
@@ -449,8 +463,8 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
     const double *const *d_gsrc = (const double *const *)(desc.as<char>() + o_gsrc);
     const double *Ad = static_cast<const double *>(A);
     ST_TRY2(launch_gram(Ad, lda, (int)c, d_chunks, nchunks, Gpart.as<double>(), stream));
-    ST_TRY2(launch_eig((int)c, k, d_probs, (int)nb, d_gsrc, nullptr, Vk.as<double>(), st->conv,
-                       stream));
+    ST_TRY2(first_stage_eig((int)c, k, d_probs, (int)nb, d_gsrc, nullptr, Vk.as<double>(),
+                            st->conv, stream));
     ST_TRY2(launch_project(Ad, lda, (int)c, d_chunks, nchunks, k, Vk.as<double>(), st->U,
                            GY.as<double>(), stream));
     ST_TRY2(launch_finalize((int)c, d_probs, (int)nb, GY.as<double>(), Vk.as<double>(),

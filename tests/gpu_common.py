@@ -48,6 +48,9 @@ def compare_svd(got, ref, tol, c, what=""):
     assert kg == kr, "%s: k_out %d vs %d" % (what, kg, kr)
     floor = 10.0 * np.sqrt(c) * 1.1e-16
     e = check_sigma(sg, sr, tol, floor)
+    if e > 1.0:
+        say("%s: sigma got %s" % (what, np.array2string(np.asarray(sg), precision=12)))
+        say("%s: sigma ref %s" % (what, np.array2string(np.asarray(sr), precision=12)))
     assert e <= 1.0, "%s: sigma error %.3g x tol" % (what, e)
     assert np.all(sg[kg:] == 0), what
     assert np.all(Ug[:, kg:] == 0) and np.all(Vg[:, kg:] == 0), what
