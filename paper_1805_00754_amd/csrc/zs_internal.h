@@ -71,6 +71,15 @@ struct StoreView {
     int32_t k;
 };
 
+// Row stride of a piece's coefficient matrix C_i (stored transposed, k_q rows
+// of prod_ld(k) values, zero beyond k): k rounded up to a size blockprod is
+// compiled for.
+__host__ __device__ inline int prod_ld(int k)
+{
+    if (k <= 32) return (k + 3) & ~3;
+    return (k + 15) & ~15;
+}
+
 // ---------------------------------------------------------------- launches
 // All launches are asynchronous on `stream` and return the launch status.
 hipError_t launch_gram(const double *X, int64_t ld, int c, const Chunk *chunks, int nchunks,

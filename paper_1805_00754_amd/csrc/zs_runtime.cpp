@@ -241,7 +241,7 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
             pc.r1 = (int32_t)(i == E_ ? hi : rows);
             pc.y_off = y0 + p * k * kq[q];
             pc.c_off = c_elems;
-            c_elems += (int64_t)k * kq[q];
+            c_elems += (int64_t)prod_ld(k) * kq[q];
             pc.out_off = u_off[q] + (i * b + pc.r0 - ts[q]) * ldu[q];
             pc.ldu = ldu[q];
             pc.q = q;

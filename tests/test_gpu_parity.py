@@ -147,6 +147,25 @@ def test_batch_equals_single_bitwise(sinmix64):
         np.testing.assert_array_equal(Ub, Us)
 
 
+def test_strided_outputs_equal_dense(sinmix64):
+    """Outputs with leading dimensions above k_q (column slices of wider
+    tensors) hold the same values as dense outputs; the padding is untouched."""
+    A, cfg, st, ost = sinmix64
+    dev = torch.device("cuda", 0)
+    for (ts, te, kq) in [(137, 1789, st.k), (250, 4_321, 3), (1_000, 1_100, 7)]:
+        n = te - ts
+        Ub = torch.full((n, kq + 5), 7.0, dtype=torch.float64, device=dev)
+        Vb = torch.full((st.c, kq + 2), 7.0, dtype=torch.float64, device=dev)
+        Us, Ss, Vs, ks = zs.zs_query(st, ts, te, kq, U=Ub[:, :kq], V=Vb[:, :kq])
+        Ud, Sd, Vd, kd = zs.zs_query(st, ts, te, kq)
+        torch.cuda.synchronize()
+        assert int(ks.item()) == int(kd.item())
+        np.testing.assert_array_equal(Us.cpu().numpy(), Ud.cpu().numpy())
+        np.testing.assert_array_equal(Vs.cpu().numpy(), Vd.cpu().numpy())
+        np.testing.assert_array_equal(Ss.cpu().numpy(), Sd.cpu().numpy())
+        assert bool((Ub[:, kq:] == 7.0).all()) and bool((Vb[:, kq:] == 7.0).all())
+
+
 def test_batch_matches_oracle(sinmix64):
     A, cfg, st, ost = sinmix64
     rng = synth.rng_for(12)
