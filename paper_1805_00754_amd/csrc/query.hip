@@ -63,87 +63,115 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Buffer resource over `bytes` bytes at `p`: loads beyond the range return
+// zero and stores beyond it are dropped, so the tile loops need no guards
+// (raw buffer, dword format word of the gfx9 family).
+// Its arguments are wave-uniform; readfirstlane says so to the compiler.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void *p, int bytes)
+{
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    void *q = reinterpret_cast<void *>(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(q, 0, __builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+// aux 2: nontemporal; the output is written once and not read back here
+__device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, int off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v),
+                                          r, off, 0, 2);
+}
+
 // One wave per piece.  Rows go in tiles of 64, one row per lane:
 //   1. the tile's rows of U_(i) (contiguous in HBM) are loaded with coalesced
-//      8-byte loads, one tile ahead, and copied to LDS unchanged (row stride k);
+//      8-byte buffer loads one tile ahead, and copied to LDS unchanged;
 //   2. each lane takes its row into registers (zero beyond k) and forms its
 //      k_q outputs; column j of C_i is KM contiguous values at a wave-uniform
 //      address, read through the scalar cache;
 //   3. the outputs go back through LDS (row stride k_q) and are written with
-//      coalesced stores.
+//      coalesced nontemporal stores.
+// Every load and store of the loop is issued unconditionally (the buffer
+// range does the bounds check), so the number of memory operations between
+// a tile's prefetch and its use is fixed and the wait for the prefetch does
+// not also wait for the previous tile's stores.  The prologue issues KM
+// dropped stores to give the first iteration the same count.
 // Every output is sum_l U(r, l) C(l, j) accumulated in l order (the padding
 // adds exact zeros).
 constexpr int kProdRows = 64;
 
-template <int KM>
+template <int KM, bool CONTIG>
 __global__ __launch_bounds__(64) void blockprod_kernel(StoreView st, const Piece *__restrict__ pieces,
                                                        const double *__restrict__ C,
                                                        double *__restrict__ Uout)
 {
-    extern __shared__ __align__(16) double tile[];    // 64 x k
+    extern __shared__ __align__(16) double tile[];    // 64 x KM
     const Piece pc = pieces[blockIdx.x];
     const int k = st.k;
     const int kq = pc.kq;
     const int lane = threadIdx.x;
     const double *__restrict__ Cp = C + pc.c_off;
-    const double *__restrict__ Ub = st.U + (pc.blk * st.b + pc.r0) * k;
-    double *__restrict__ out = Uout + pc.out_off;
+    const double *Ub = st.U + (pc.blk * st.b + pc.r0) * k;
+    double *out = Uout + pc.out_off;
     const int64_t ldu = pc.ldu;
     const int nrows = pc.r1 - pc.r0;
     const int ntiles = (nrows + kProdRows - 1) / kProdRows;
+    auto urange = [&](int row0) {
+        const int nr = max(0, min(kProdRows, nrows - row0));
+        return buf(Ub + (int64_t)row0 * k, nr * k * (int)sizeof(double));
+    };
 
     double pre[KM];
     {
-        const int n = min(kProdRows, nrows) * k;
+        const __amdgpu_buffer_rsrc_t r = urange(0);
 #pragma unroll
-        for (int i = 0; i < KM; ++i) {
-            const int e = lane + i * kProdRows;
-            pre[i] = (e < n) ? Ub[e] : 0.0;
-        }
+        for (int i = 0; i < KM; ++i) pre[i] = buf_load(r, (lane + i * kProdRows) * 8);
+        const __amdgpu_buffer_rsrc_t none = buf(out, 0);
+#pragma unroll
+        for (int i = 0; i < KM; ++i) buf_store_nt(none, (lane + i * kProdRows) * 8, 0.0);
     }
     for (int t = 0; t < ntiles; ++t) {
         const int row0 = t * kProdRows;
         const int nr = min(kProdRows, nrows - row0);
-        wave_sync();                               // the previous tile's outputs are out
+        wave_sync();                               // the previous tile's outputs are read
 #pragma unroll
-        for (int i = 0; i < KM; ++i)
-            if (i < k) tile[lane + i * kProdRows] = pre[i];
-        if (t + 1 < ntiles) {
-            const double *Un = Ub + (int64_t)(row0 + kProdRows) * k;
-            const int n = min(kProdRows, nrows - row0 - kProdRows) * k;
+        for (int i = 0; i < KM; ++i) tile[lane + i * kProdRows] = pre[i];
+        {
+            const __amdgpu_buffer_rsrc_t r = urange(row0 + kProdRows);   // empty after the last
 #pragma unroll
-            for (int i = 0; i < KM; ++i) {
-                const int e = lane + i * kProdRows;
-                if (e < n) pre[i] = Un[e];
-            }
+            for (int i = 0; i < KM; ++i) pre[i] = buf_load(r, (lane + i * kProdRows) * 8);
         }
         wave_sync();
         double u[KM];
 #pragma unroll
-        for (int l = 0; l < KM; ++l) u[l] = (l < k) ? tile[lane * k + l] : 0.0;
+        for (int l = 0; l < KM; ++l) {
+            const double x = tile[lane * k + l];
+            u[l] = (l < k) ? x : 0.0;
+        }
         wave_sync();                               // every lane holds its row
-        if (lane < nr) {
-            for (int j = 0; j < kq; ++j) {
-                const double *cj = Cp + j * KM;
-                double a = 0.0;
+        for (int j = 0; j < kq; ++j) {
+            const double *cj = Cp + j * KM;
+            double a = 0.0;
 #pragma unroll
-                for (int l = 0; l < KM; ++l) a = fma(u[l], cj[l], a);
-                tile[lane * kq + j] = a;
-            }
+            for (int l = 0; l < KM; ++l) a = fma(u[l], cj[l], a);
+            tile[lane * kq + j] = a;
         }
         wave_sync();
-        const int n = nr * kq;
-        if (ldu == kq) {                           // the tile is contiguous in the output
-            double *o = out + (int64_t)row0 * kq;
+        if (CONTIG) {                              // the tile is contiguous in the output
+            const __amdgpu_buffer_rsrc_t r = buf(out + (int64_t)row0 * kq, nr * kq * (int)sizeof(double));
 #pragma unroll
-            for (int i = 0; i < KM; ++i) {
-                const int e = lane + i * kProdRows;
-                if (i < kq && e < n) o[e] = tile[e];
-            }
+            for (int i = 0; i < KM; ++i)
+                buf_store_nt(r, (lane + i * kProdRows) * 8, tile[lane + i * kProdRows]);
         } else {
+            const int n = nr * kq;
             for (int e = lane; e < n; e += kProdRows) {
-                const int r = e / kq;
-                out[(int64_t)(row0 + r) * ldu + (e - r * kq)] = tile[e];
+                const int rr = e / kq;
+                out[(int64_t)(row0 + rr) * ldu + (e - rr * kq)] = tile[e];
             }
         }
     }
@@ -164,15 +192,18 @@ hipError_t launch_coef(int k, const Piece *pieces, int npieces, const double *Y,
 
 template <int KM>
 hipError_t run_blockprod(StoreView st, const Piece *pieces, int npieces, const double *C, double *U,
-                         hipStream_t stream)
+                         bool contiguous, hipStream_t stream)
 {
-    const size_t lds = (size_t)kProdRows * st.k * sizeof(double);
-    blockprod_kernel<KM><<<npieces, kProdRows, lds, stream>>>(st, pieces, C, U);
+    const size_t lds = (size_t)kProdRows * KM * sizeof(double);
+    if (contiguous)
+        blockprod_kernel<KM, true><<<npieces, kProdRows, lds, stream>>>(st, pieces, C, U);
+    else
+        blockprod_kernel<KM, false><<<npieces, kProdRows, lds, stream>>>(st, pieces, C, U);
     return hipGetLastError();
 }
 
 hipError_t launch_blockprod(StoreView st, const Piece *pieces, int npieces, const double *C,
-                            double *U, hipStream_t stream)
+                            double *U, bool contiguous, hipStream_t stream)
 {
     if (npieces <= 0) return hipSuccess;
     if (st.k < 1 || st.k > kMaxK) return hipErrorInvalidValue;
@@ -180,7 +211,7 @@ hipError_t launch_blockprod(StoreView st, const Piece *pieces, int npieces, cons
     hipError_t e;
     switch (prod_ld(st.k)) {
 #define ZS_PROD_CASE(KM) \
-    case KM: e = run_blockprod<KM>(st, pieces, npieces, C, U, stream); break;
+    case KM: e = run_blockprod<KM>(st, pieces, npieces, C, U, contiguous, stream); break;
         ZS_PROD_CASE(4) ZS_PROD_CASE(8) ZS_PROD_CASE(12) ZS_PROD_CASE(16) ZS_PROD_CASE(20)
         ZS_PROD_CASE(24) ZS_PROD_CASE(28) ZS_PROD_CASE(32) ZS_PROD_CASE(48) ZS_PROD_CASE(64)
 #undef ZS_PROD_CASE

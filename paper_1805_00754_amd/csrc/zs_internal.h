@@ -107,8 +107,9 @@ hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx
                           hipStream_t stream);
 hipError_t launch_coef(int k, const Piece *pieces, int npieces, const double *Y, const double *F,
                        const double *T, double *C, hipStream_t stream);
+// contiguous: every query's U has leading dimension k_q (rows back to back)
 hipError_t launch_blockprod(StoreView st, const Piece *pieces, int npieces, const double *C,
-                            double *U, hipStream_t stream);
+                            double *U, bool contiguous, hipStream_t stream);
 
 // Raises a kernel's dynamic-LDS limit to `bytes` if it is below (the limit
 // only grows; `cur` caches the value set).  Clears the error state on failure.

@@ -338,7 +338,9 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
                             w->F.as<double>(), kRankTolFP64, st->conv, stream));
     HIP_TRY(launch_coef(k, d_pieces, npieces, w->Y.as<double>(), w->F.as<double>(),
                         w->T.as<double>(), w->C.as<double>(), stream));
-    HIP_TRY(launch_blockprod(sv, d_pieces, npieces, w->C.as<double>(), U, stream));
+    bool contiguous = true;
+    for (int32_t q = 0; q < nq; ++q) contiguous = contiguous && ldu[q] == kq[q];
+    HIP_TRY(launch_blockprod(sv, d_pieces, npieces, w->C.as<double>(), U, contiguous, stream));
     return ZS_OK;
 }
 
