@@ -15,6 +15,34 @@
 namespace zs {
 namespace {
 
+// Pieces of every query from its descriptor: piece p of query q is block
+// S + p, rows [lo, rows) for the first, [0, hi) for the last (Alg. 3 index
+// math), with its offsets in Y, C and the caller's U.
+__global__ __launch_bounds__(kThreads) void expand_pieces_kernel(StoreView st,
+                                                                 const QueryDesc *__restrict__ qd,
+                                                                 Piece *__restrict__ pieces)
+{
+    const QueryDesc d = qd[blockIdx.y];
+    const int p = blockIdx.x * kThreads + threadIdx.x;
+    if (p >= d.np) return;
+    const int64_t blk = d.S + p;
+    const int64_t rows = min(st.b, st.t - blk * st.b);
+    Piece pc;
+    pc.blk = blk;
+    pc.r0 = p == 0 ? d.lo : 0;
+    pc.r1 = p == d.np - 1 ? d.hi : (int32_t)rows;
+    pc.y_off = d.y0 + (int64_t)p * st.k * d.kq;
+    pc.c_off = d.c0 + (int64_t)p * prod_ld(st.k) * d.kq;
+    pc.out_off = d.u_off + (blk * st.b + pc.r0 - d.ts) * d.ldu;
+    pc.ldu = d.ldu;
+    pc.q = blockIdx.y;
+    pc.kq = d.kq;
+    const bool partial = pc.r0 != 0 || pc.r1 != rows;
+    pc.t_idx = partial ? d.t0 + (p == 0 ? 0 : d.first_partial) : -1;
+    pc.pad = 0;
+    pieces[d.piece0 + p] = pc;
+}
+
 __global__ __launch_bounds__(kThreads) void coef_kernel(int k, const Piece *__restrict__ pieces,
                                                         const double *__restrict__ Y,
                                                         const double *__restrict__ F,
@@ -178,6 +206,18 @@ __global__ __launch_bounds__(64) void blockprod_kernel(StoreView st, const Piece
 }
 
 }  // namespace
+
+hipError_t launch_expand_pieces(StoreView st, const QueryDesc *qd, int nq, int max_np, Piece *pieces,
+                                hipStream_t stream)
+{
+    if (nq <= 0 || max_np <= 0) return hipSuccess;
+    timing_begin("expand", stream);
+    const dim3 grid((unsigned)((max_np + kThreads - 1) / kThreads), (unsigned)nq);
+    expand_pieces_kernel<<<grid, kThreads, 0, stream>>>(st, qd, pieces);
+    hipError_t e = hipGetLastError();
+    timing_end("expand", stream);
+    return e;
+}
 
 hipError_t launch_coef(int k, const Piece *pieces, int npieces, const double *Y, const double *F,
                        const double *T, double *C, hipStream_t stream)

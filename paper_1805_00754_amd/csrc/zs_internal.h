@@ -62,6 +62,22 @@ struct Piece {
     int32_t pad;
 };
 
+// One query of a batch, as the piece expansion kernel reads it (the O(1)
+// per-query part of the plan; the O(pieces) part is expanded on the device).
+struct QueryDesc {
+    int64_t S;        // first touched block
+    int64_t ts;       // t_s
+    int64_t piece0;   // index of the first piece
+    int64_t y0, c0;   // element offsets of the first piece in Y and C
+    int64_t u_off;    // element offset of the query's U
+    int64_t ldu;      // its leading dimension
+    int32_t np;       // touched blocks
+    int32_t lo, hi;   // first block kept from row lo; last block kept up to row hi
+    int32_t kq;
+    int32_t t0;       // Partial-SVD slot of the first partial piece
+    int32_t first_partial;  // 1 if the first piece goes through the Partial-SVD
+};
+
 // Device-side view of a store.
 struct StoreView {
     const double *U;  // t x k, rows of block i hold U_(i)
@@ -105,6 +121,8 @@ hipError_t launch_tree_level(int c, double *tree, int64_t node0, int64_t nnodes,
 hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx, int npartial,
                           double *Mp, double *T, double rank_tol, int *conv_flag,
                           hipStream_t stream);
+hipError_t launch_expand_pieces(StoreView st, const QueryDesc *qd, int nq, int max_np, Piece *pieces,
+                                hipStream_t stream);
 hipError_t launch_coef(int k, const Piece *pieces, int npieces, const double *Y, const double *F,
                        const double *T, double *C, hipStream_t stream);
 // contiguous: every query's U has leading dimension k_q (rows back to back)

@@ -86,14 +86,14 @@ struct DevBuf {
 
 // Scratch of the query pipeline for one stream (grow-only).
 struct Workspace {
-    DevBuf Mp, Vk, Y, GY, F, T, C, desc;
+    DevBuf Mp, Vk, Y, GY, F, T, C, P, desc;
     void *host = nullptr;        // pinned staging of the descriptors
     size_t host_bytes = 0;
     hipEvent_t copied = nullptr; // the last upload from `host` has completed
     void release()
     {
         Mp.release(); Vk.release(); Y.release(); GY.release();
-        F.release(); T.release(); C.release(); desc.release();
+        F.release(); T.release(); C.release(); P.release(); desc.release();
         if (host) (void)hipHostFree(host);
         if (copied) (void)hipEventDestroy(copied);
         host = nullptr;
@@ -208,59 +208,63 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
 {
     const int64_t c = st->c, b = st->b;
     const int32_t k = st->k;
-    // ---- plan (Alg. 3 lines 1-3 for every query) --------------------------------
-    // Pieces: the touched blocks; boundary blocks cut by the range go through the
-    // Partial-SVD.  Whole blocks form one contiguous run [a, e) whose Gram comes
-    // from the Gram tree.  Every per-query quantity depends only on the query.
-    std::vector<Piece> pieces;
+    // ---- plan (Alg. 3 index math for every query) ---------------------------------
+    // Pieces are the touched blocks; boundary blocks cut by the range go through
+    // the Partial-SVD.  Whole blocks form one contiguous run [a, e) whose Gram
+    // comes from the Gram tree.  The host computes the O(1) part of each query
+    // (its descriptor, partial slots, projection chunks, tree nodes); the
+    // pieces themselves are expanded on the device.  Every per-query quantity
+    // depends only on that query.
+    std::vector<QueryDesc> qds(nq);
     std::vector<int32_t> pidx;          // pieces that need a Partial-SVD
     std::vector<StackChunk> chunks;
     std::vector<Prob> probs(nq);
     std::vector<int64_t> gsrc_off;      // tree node indices (converted to pointers below)
     std::vector<int32_t> msrc_idx;      // Partial-SVD slots
-    int64_t y_elems = 0, c_elems = 0;
-    int32_t slot = 0, kq_max = 1;
+    int64_t y_elems = 0, c_elems = 0, npieces64 = 0;
+    int32_t slot = 0, kq_max = 1, max_np = 0;
+    const int kp = prod_ld(k);
     for (int32_t q = 0; q < nq; ++q) {
         kq_max = std::max(kq_max, kq[q]);
         const int64_t S_ = ts[q] / b, E_ = (te[q] - 1) / b;
         const int64_t lo = ts[q] - S_ * b, hi = te[q] - E_ * b;
         const int64_t np = E_ - S_ + 1;
-        const int64_t y0 = y_elems;
-        const int32_t piece0 = (int32_t)pieces.size();
+        max_np = std::max<int32_t>(max_np, (int32_t)np);
+        QueryDesc &d = qds[q];
+        std::memset(&d, 0, sizeof d);
+        d.S = S_;
+        d.ts = ts[q];
+        d.piece0 = npieces64;
+        d.y0 = y_elems;
+        d.c0 = c_elems;
+        d.u_off = u_off[q];
+        d.ldu = ldu[q];
+        d.np = (int32_t)np;
+        d.lo = (int32_t)lo;
+        d.hi = (int32_t)hi;
+        d.kq = kq[q];
+        d.t0 = (int32_t)pidx.size();
+        // first piece: rows [lo, np == 1 ? hi : rows_S); last piece (np > 1): [0, hi)
+        const bool first_partial = lo != 0 || (np == 1 ? hi != st->block_rows(S_) : false);
+        const bool last_partial = np > 1 && hi != st->block_rows(E_);
+        d.first_partial = first_partial ? 1 : 0;
         Prob pr;
         std::memset(&pr, 0, sizeof pr);
         pr.m0 = (int32_t)msrc_idx.size();
-        int64_t whole_a = -1, whole_e = -1;
-        for (int64_t p = 0; p < np; ++p) {
-            const int64_t i = S_ + p;
-            const int64_t rows = st->block_rows(i);
-            Piece pc;
-            std::memset(&pc, 0, sizeof pc);
-            pc.blk = i;
-            pc.r0 = (int32_t)(i == S_ ? lo : 0);
-            pc.r1 = (int32_t)(i == E_ ? hi : rows);
-            pc.y_off = y0 + p * k * kq[q];
-            pc.c_off = c_elems;
-            c_elems += (int64_t)prod_ld(k) * kq[q];
-            pc.out_off = u_off[q] + (i * b + pc.r0 - ts[q]) * ldu[q];
-            pc.ldu = ldu[q];
-            pc.q = q;
-            pc.kq = kq[q];
-            const bool partial = pc.r0 != 0 || pc.r1 != rows;
-            pc.t_idx = partial ? (int32_t)pidx.size() : -1;
-            if (partial) {
-                msrc_idx.push_back(pc.t_idx);
-                pidx.push_back((int32_t)pieces.size());
-            } else {
-                if (whole_a < 0) whole_a = i;
-                whole_e = i + 1;
-            }
-            pieces.push_back(pc);
+        if (first_partial) {
+            msrc_idx.push_back((int32_t)pidx.size());
+            pidx.push_back((int32_t)npieces64);
+        }
+        if (last_partial) {
+            msrc_idx.push_back((int32_t)pidx.size());
+            pidx.push_back((int32_t)(npieces64 + np - 1));
         }
         pr.nm = (int32_t)msrc_idx.size() - pr.m0;
         // Whole blocks [whole_a, whole_e) are contiguous: cover them with tree nodes.
+        const int64_t whole_a = S_ + (first_partial ? 1 : 0);
+        const int64_t whole_e = E_ + 1 - (last_partial ? 1 : 0);
         pr.g0 = (int32_t)gsrc_off.size();
-        if (whole_a >= 0) {
+        if (whole_a < whole_e) {
             int64_t l = whole_a + st->n2, r = whole_e + st->n2;
             while (l < r) {
                 if (l & 1) gsrc_off.push_back(l++);
@@ -274,8 +278,8 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
         for (int64_t p = 0; p < np; p += kQueryChunkPieces) {
             StackChunk ch;
             std::memset(&ch, 0, sizeof ch);
-            ch.y_off = y0 + p * k * kq[q];
-            ch.piece0 = piece0 + (int32_t)p;
+            ch.y_off = y_elems + p * k * kq[q];
+            ch.piece0 = (int32_t)(npieces64 + p);
             ch.npieces = (int32_t)std::min<int64_t>(kQueryChunkPieces, np - p);
             ch.prob = q;
             ch.slot = slot++;
@@ -291,7 +295,12 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
         pr.k_dst = k_out + q;
         probs[q] = pr;
         y_elems += np * k * kq[q];
+        c_elems += np * kp * kq[q];
+        npieces64 += np;
     }
+    if (npieces64 > INT32_MAX)
+        return fail(ZS_EUNSUPPORTED, "batch touches %lld blocks (limit %d)", (long long)npieces64,
+                    INT32_MAX);
     // ---- workspace ---------------------------------------------------------------
     Workspace *w;
     {
@@ -300,7 +309,7 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
         if (it == st->ws.end()) it = st->ws.emplace(stream, new Workspace()).first;
         w = it->second;
     }
-    const int nchunks = (int)chunks.size(), npieces = (int)pieces.size();
+    const int nchunks = (int)chunks.size(), npieces = (int)npieces64;
     const int npartial = (int)pidx.size();
     HIP_TRY(w->Mp.ensure(sizeof(double) * std::max<int64_t>(1, (int64_t)npartial * k * c)));
     HIP_TRY(w->Vk.ensure(sizeof(double) * (size_t)nq * c * kMaxK));
@@ -309,25 +318,28 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
     HIP_TRY(w->F.ensure(sizeof(double) * (size_t)nq * kSlotK));
     HIP_TRY(w->T.ensure(sizeof(double) * std::max<int64_t>(1, (int64_t)npartial * k * k)));
     HIP_TRY(w->C.ensure(sizeof(double) * std::max<int64_t>(1, c_elems)));
+    HIP_TRY(w->P.ensure(sizeof(Piece) * std::max<int64_t>(1, npieces64)));
     double *Mp = w->Mp.as<double>();
     std::vector<const double *> gsrc(gsrc_off.size()), msrc(msrc_idx.size());
     for (size_t i = 0; i < gsrc_off.size(); ++i) gsrc[i] = st->tree + gsrc_off[i] * c * c;
     for (size_t i = 0; i < msrc_idx.size(); ++i) msrc[i] = Mp + (int64_t)msrc_idx[i] * k * c;
     Blob blob;
     const size_t o_chunks = blob.add(chunks), o_probs = blob.add(probs);
-    const size_t o_pieces = blob.add(pieces), o_pidx = blob.add(pidx);
+    const size_t o_qds = blob.add(qds), o_pidx = blob.add(pidx);
     const size_t o_gsrc = blob.add(gsrc), o_msrc = blob.add(msrc);
     zs_status s = upload(*w, blob.bytes.data(), blob.bytes.size(), stream);
     if (s != ZS_OK) return s;
     char *d = w->desc.as<char>();
     const StackChunk *d_chunks = (const StackChunk *)(d + o_chunks);
     const Prob *d_probs = (const Prob *)(d + o_probs);
-    const Piece *d_pieces = (const Piece *)(d + o_pieces);
+    const QueryDesc *d_qds = (const QueryDesc *)(d + o_qds);
+    const Piece *d_pieces = w->P.as<Piece>();
     const int32_t *d_pidx = (const int32_t *)(d + o_pidx);
     const double *const *d_gsrc = (const double *const *)(d + o_gsrc);
     const double *const *d_msrc = (const double *const *)(d + o_msrc);
     const StoreView sv = st->view();
     // ---- launches ---------------------------------------------------------------
+    HIP_TRY(launch_expand_pieces(sv, d_qds, nq, max_np, w->P.as<Piece>(), stream));
     HIP_TRY(launch_partial(sv, d_pieces, d_pidx, npartial, Mp, w->T.as<double>(), kRankTolFP64,
                            st->conv, stream));
     HIP_TRY(first_stage_eig((int)c, k, d_probs, nq, d_gsrc, d_msrc, w->Vk.as<double>(),
