@@ -6,13 +6,14 @@
 //  * stack_project: the same for a query's stacked matrix M, whose rows are
 //    read where they live: Sigma_(i) V_(i)^T rows of the store for whole
 //    blocks, the Partial-SVD rows for boundary blocks (Alg. 2 line 2).  M is
-//    never materialised.
+//    never materialised.  (Its own layout is described at the kernel.)
 //  * utransform: U_(i) <- Y_(i) F_(i) in place (F = W Sigma^-1 with the sign
 //    rule folded in), giving the block's left singular vectors.
 //
-// Rows are staged through LDS with coalesced loads; V_k stays in LDS for the
-// whole chunk.  Thread (rg, j) computes column j of RQ consecutive rows with
-// independent accumulators, reading two X values per 16-byte LDS load.
+// project: rows are staged through LDS with coalesced loads; V_k stays in LDS
+// for the whole chunk.  Thread (rg, j) computes column j of RQ consecutive
+// rows with independent accumulators, reading two X values per 16-byte LDS
+// load.
 #include "zs_internal.h"
 
 namespace zs {
@@ -144,56 +145,138 @@ __global__ __launch_bounds__(kThreads) void project_kernel(const double *__restr
     }
 }
 
-__global__ __launch_bounds__(kThreads) void stack_project_kernel(
-    StoreView st, const Piece *__restrict__ pieces, const double *__restrict__ Mp,
-    const StackChunk *__restrict__ chunks, const double *__restrict__ Vk, double *__restrict__ Y,
-    double *__restrict__ GYpart)
+// Orders the wave's LDS accesses (stack_project work-groups are one wave).
+__device__ __forceinline__ void wave_sync()
 {
-    extern __shared__ __align__(16) double smem[];
-    __shared__ const double *rsrc[kMaxGroups * RQ];
-    __shared__ double rscale[kMaxGroups * RQ];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// stack_project: one wave per chunk of pieces, one stack row per lane, tiles
+// of 64 rows.  A lane's row is s_r x_r with x_r = V_(i)^T row j of the store
+// (s_r = sigma_ij) for a whole block, or Partial-SVD row j (s_r = 1).  Rows
+// come into LDS in 16-column panels (coalesced loads through the lanes' row
+// pointers); each lane then accumulates y_r = x_r V_k over the panel with
+// V_k rows read through the scalar cache (wave-uniform addresses), and
+// scales by s_r.  The Y tile is stored through LDS with coalesced stores, and
+// its Gram Y^T Y is accumulated from LDS: lane g owns entries (a, b0..b0+3)
+// of group g = a * nb4 + b0 / 4.
+constexpr int kPanel = 16;
+
+template <int KQM>
+__global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const Piece *__restrict__ pieces,
+                                                           const double *__restrict__ Mp,
+                                                           const StackChunk *__restrict__ chunks,
+                                                           const double *__restrict__ Vk,
+                                                           double *__restrict__ Y,
+                                                           double *__restrict__ GYpart)
+{
+    extern __shared__ __align__(16) double sm[];
+    constexpr int NB4 = (KQM + 3) / 4;
+    constexpr int NPASS = (KQM * NB4 + 63) / 64;
     const StackChunk ch = chunks[blockIdx.x];
-    const int c = (int)st.c, k = st.k;
-    const TileGeom g = tile_geom(c, ch.kk);
-    double *Vs = smem;
-    double *Xs = Vs + g.cpad * g.kk;
-    double *Ys = Xs + g.rb * g.ldx;
-    const int tid = threadIdx.x;
-    load_vk(g, c, Vk + (int64_t)ch.prob * c * kMaxK, Vs);
-    double gacc[EPT];
-#pragma unroll
-    for (int x = 0; x < EPT; ++x) gacc[x] = 0.0;
+    const int c = (int)st.c, k = st.k, kq = ch.kk;
+    const int lane = threadIdx.x;
+    const double *__restrict__ V = Vk + (int64_t)ch.prob * c * kMaxK;   // c x kq, row-major
     const int rows = ch.npieces * k;
-    for (int r0 = 0; r0 < rows; r0 += g.rb) {
-        const int nr = min(g.rb, rows - r0);
-        __syncthreads();
-        if (tid < nr) {
-            const int r = r0 + tid;
+    const int nb4 = (kq + 3) / 4;
+    const int ldy = kq + 1;
+    double gy[NPASS][4];
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) gy[p][u] = 0.0;
+
+    for (int r0 = 0; r0 < rows; r0 += 64) {
+        const int nr = min(64, rows - r0);
+        // the lane's stack row
+        const double *xp = st.Vt;
+        double scale = 0.0;
+        if (lane < nr) {
+            const int r = r0 + lane;
             const Piece &pc = pieces[ch.piece0 + r / k];
             const int j = r % k;
             if (pc.t_idx >= 0) {
-                rsrc[tid] = Mp + ((int64_t)pc.t_idx * k + j) * c;
-                rscale[tid] = 1.0;
+                xp = Mp + ((int64_t)pc.t_idx * k + j) * c;
+                scale = 1.0;
             } else {
-                rsrc[tid] = st.Vt + (pc.blk * k + j) * c;
-                rscale[tid] = st.S[pc.blk * k + j];
+                xp = st.Vt + (pc.blk * k + j) * c;
+                scale = st.S[pc.blk * k + j];
             }
         }
-        __syncthreads();
-        for (int e = tid; e < g.rb * g.cpad; e += kThreads) {
-            const int rr = e / g.cpad, col = e % g.cpad;
-            Xs[rr * g.ldx + col] = (rr < nr && col < c) ? rsrc[rr][col] * rscale[rr] : 0.0;
+        const uint64_t xa = reinterpret_cast<uint64_t>(xp);
+        double acc[KQM];
+#pragma unroll
+        for (int j = 0; j < KQM; ++j) acc[j] = 0.0;
+        for (int a0 = 0; a0 < c; a0 += kPanel) {
+            wave_sync();
+            // panel: 64 rows x 16 columns, 16 lanes per row, 4 rows per step;
+            // all 16 loads are issued before the first LDS write
+            const int col = a0 + lane % 16;
+            const int colc = min(col, c - 1);          // in bounds for every lane
+            double v[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int row = i * 4 + lane / 16;
+                const uint32_t lo = __shfl((uint32_t)xa, row, 64);
+                const uint32_t hi = __shfl((uint32_t)(xa >> 32), row, 64);
+                typedef const double __attribute__((address_space(1))) gdouble;
+                v[i] = reinterpret_cast<gdouble *>(((uint64_t)hi << 32) | lo)[colc];
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                sm[(i * 4 + lane / 16) * (kPanel + 1) + lane % 16] = col < c ? v[i] : 0.0;
+            wave_sync();
+            const int na = min(kPanel, c - a0);
+#pragma unroll
+            for (int a = 0; a < kPanel; ++a) {
+                if (a < na) {
+                    const double x = sm[lane * (kPanel + 1) + a];
+                    const double *vr = V + (int64_t)(a0 + a) * kq;
+#pragma unroll
+                    for (int j = 0; j < KQM; ++j) acc[j] = fma(x, vr[j], acc[j]);
+                }
+            }
         }
-        __syncthreads();
-        project_tile(g, Xs, Vs, nr, Ys, Y + ch.y_off + (int64_t)r0 * ch.kk);
-        __syncthreads();
-        gram_accumulate(Ys, ch.kk, nr, gacc);
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < KQM; ++j)
+            if (j < kq) sm[lane * ldy + j] = scale * acc[j];
+        wave_sync();
+        {
+            double *Yt = Y + ch.y_off + (int64_t)r0 * kq;
+            const int n = nr * kq;
+            for (int e = lane; e < n; e += 64) {
+                const int rr = e / kq;
+                Yt[e] = sm[rr * ldy + (e - rr * kq)];
+            }
+        }
+        // Gram of the tile: entries (a, b0..b0+3) per lane and pass
+#pragma unroll
+        for (int p = 0; p < NPASS; ++p) {
+            const int g = lane + 64 * p;
+            if (g < kq * nb4) {
+                const int a = g / nb4, b0 = 4 * (g - a * nb4);
+                for (int rr = 0; rr < nr; ++rr) {
+                    const double *yr = sm + rr * ldy;
+                    const double ya = yr[a];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) gy[p][u] = fma(ya, yr[b0 + u], gy[p][u]);
+                }
+            }
+        }
     }
     double *G = GYpart + (int64_t)ch.slot * kSlotK;
 #pragma unroll
-    for (int x = 0; x < EPT; ++x) {
-        const int e = tid + x * kThreads;
-        if (e < ch.kk * ch.kk) G[e] = gacc[x];
+    for (int p = 0; p < NPASS; ++p) {
+        const int g = lane + 64 * p;
+        if (g < kq * nb4) {
+            const int a = g / nb4, b0 = 4 * (g - a * nb4);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (b0 + u < kq) G[a * kq + b0 + u] = gy[p][u];
+        }
     }
 }
 
@@ -242,25 +325,35 @@ hipError_t launch_project(const double *X, int64_t ld, int c, const Chunk *chunk
     return e;
 }
 
+template <int KQM>
+hipError_t run_stack_project(StoreView st, const Piece *pieces, const double *Mp,
+                             const StackChunk *chunks, int nchunks, int kq_max, const double *Vk,
+                             double *Y, double *GYpart, hipStream_t stream)
+{
+    // panel (64 x 17) or Y tile (64 x (kq + 1)), plus 4 doubles read past the
+    // last row by the Gram groups
+    const int w = kq_max + 1 > kPanel + 1 ? kq_max + 1 : kPanel + 1;
+    const size_t lds = (size_t)(64 * w + 4) * sizeof(double);
+    stack_project_kernel<KQM><<<nchunks, 64, lds, stream>>>(st, pieces, Mp, chunks, Vk, Y, GYpart);
+    return hipGetLastError();
+}
+
 hipError_t launch_stack_project(StoreView st, const Piece *pieces, const double *Mp,
                                 const StackChunk *chunks, int nchunks, int kq_max,
                                 const double *Vk, double *Y, double *GYpart, hipStream_t stream)
 {
     if (nchunks <= 0) return hipSuccess;
-    // The LDS layout depends on each chunk's kq: size for the worst kq <= kq_max.
-    size_t lds = 0;
-    for (int kk = 1; kk <= kq_max; ++kk) {
-        const size_t b = project_lds_bytes((int)st.c, kk);
-        if (b > lds) lds = b;
-    }
-    static size_t cur = 0;
-    {
-        hipError_t e = ensure_lds((const void *)stack_project_kernel, lds, cur);
-        if (e != hipSuccess) return e;
-    }
+    if (kq_max < 1 || kq_max > kMaxK) return hipErrorInvalidValue;
     timing_begin("stack_project", stream);
-    stack_project_kernel<<<nchunks, kThreads, lds, stream>>>(st, pieces, Mp, chunks, Vk, Y, GYpart);
-    hipError_t e = hipGetLastError();
+    hipError_t e;
+    switch (prod_ld(kq_max)) {
+#define ZS_SP_CASE(KQM) \
+    case KQM: e = run_stack_project<KQM>(st, pieces, Mp, chunks, nchunks, kq_max, Vk, Y, GYpart, stream); break;
+        ZS_SP_CASE(4) ZS_SP_CASE(8) ZS_SP_CASE(12) ZS_SP_CASE(16) ZS_SP_CASE(20)
+        ZS_SP_CASE(24) ZS_SP_CASE(28) ZS_SP_CASE(32) ZS_SP_CASE(48) ZS_SP_CASE(64)
+#undef ZS_SP_CASE
+    default: e = hipErrorInvalidValue;
+    }
     timing_end("stack_project", stream);
     return e;
 }
