@@ -111,7 +111,7 @@ def main():
     zs.zs_timing_enable(False)
     kernels = {}
     for name in ("gram", "eig", "project", "finalize", "utransform", "leaf_gram", "tree_level",
-                 "expand", "partial", "stack_project", "coef", "blockprod"):
+                 "expand", "order", "partial", "stack_project", "coef", "blockprod"):
         n, ms = zs.zs_timing_get(name)
         if n:
             kernels[name] = {"launches": n, "total_ms": ms, "avg_ms": ms / n}

@@ -215,6 +215,7 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
         sh_a = gl - 2.1 * tn * __DBL_EPSILON__ * c - 4.2 * pivmin;
         sh_b = gu + 2.1 * tn * __DBL_EPSILON__ * c + 4.2 * pivmin;
     }
+    __syncthreads();                               // e[c - 2] was written by thread 0
     for (int i = tid; i + 1 < c; i += NTH) e2[i] = e[i] * e[i];
     __syncthreads();
     const double tnorm = sh_tnorm, pivmin = sh_pivmin;

@@ -8,8 +8,8 @@
 //    prod_ld(k) values.
 //  * blockprod: the block-diagonal product diag(U'_S, U_(S+1), ..., U'_E) U_r
 //    of Eq. (9), one wave per touched block, streaming the block's rows of U
-//    from HBM and writing the range's rows of U.  This kernel moves
-//    n*k + n*kq values per query and is bound by HBM bandwidth.
+//    and writing the range's rows of U.  This kernel moves n*k + n*kq values
+//    per query and is bound by memory bandwidth.
 #include "zs_internal.h"
 
 namespace zs {
@@ -41,6 +41,27 @@ __global__ __launch_bounds__(kThreads) void expand_pieces_kernel(StoreView st,
     pc.t_idx = partial ? d.t0 + (p == 0 ? 0 : d.first_partial) : -1;
     pc.pad = 0;
     pieces[d.piece0 + p] = pc;
+}
+
+__global__ __launch_bounds__(kThreads) void zero_i32_kernel(int32_t *__restrict__ a, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+
+// perm[boff[blk] + rank] = piece, rank taken from a per-block counter.  The
+// order of the pieces of one block among themselves does not matter: each
+// piece writes its own rows.
+__global__ __launch_bounds__(kThreads) void order_pieces_kernel(const Piece *__restrict__ pieces,
+                                                                int npieces,
+                                                                const int32_t *__restrict__ boff,
+                                                                int32_t *__restrict__ bcount,
+                                                                int32_t *__restrict__ perm)
+{
+    const int p = blockIdx.x * kThreads + threadIdx.x;
+    if (p >= npieces) return;
+    const int64_t blk = pieces[p].blk;
+    perm[boff[blk] + atomicAdd(&bcount[blk], 1)] = p;
 }
 
 __global__ __launch_bounds__(kThreads) void coef_kernel(int k, const Piece *__restrict__ pieces,
@@ -83,7 +104,7 @@ __global__ __launch_bounds__(kThreads) void coef_kernel(int k, const Piece *__re
 }
 
 // Orders the wave's LDS accesses: everything before it, from every lane, is
-// visible to everything after it.  The work-groups of blockprod are one wave.
+// visible to everything after it (blockprod work-groups are one wave).
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -109,6 +130,14 @@ __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int off)
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 
+// The same load marked volatile (aux bit 31, a compiler-only flag): the
+// compiler keeps it where it is written instead of sinking it next to its use.
+__device__ __forceinline__ double buf_load_pinned(__amdgpu_buffer_rsrc_t r, int off)
+{
+    return __builtin_bit_cast(double,
+                              __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, (int)0x80000000u));
+}
+
 // aux 2: nontemporal; the output is written once and not read back here
 __device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, int off, double v)
 {
@@ -116,34 +145,61 @@ __device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, int off, 
                                           r, off, 0, 2);
 }
 
-// One wave per piece.  Rows go in tiles of 64, one row per lane:
+// One wave per piece, rows in tiles of 64.  The product of a tile with C_i
+// runs on the matrix cores (FP64 MFMA 16x16x4): C_i stays in registers for
+// the whole piece as B fragments, so the tile loop reads no coefficients.
 //   1. the tile's rows of U_(i) (contiguous in HBM) are loaded with coalesced
-//      8-byte buffer loads one tile ahead, and copied to LDS unchanged;
-//   2. each lane takes its row into registers (zero beyond k) and forms its
-//      k_q outputs; column j of C_i is KM contiguous values at a wave-uniform
-//      address, read through the scalar cache;
-//   3. the outputs go back through LDS (row stride k_q) and are written with
-//      coalesced nontemporal stores.
+//      8-byte buffer loads one tile ahead and copied to LDS unchanged;
+//   2. A fragments (16 rows x 4 columns) come from LDS; four row blocks times
+//      ceil(k_q / 16) column blocks of 16 x 16 accumulators, KM / 4 steps;
+//   3. the accumulators go back through LDS (row stride k_q) and are written
+//      with coalesced nontemporal stores.
+// Operand layout of v_mfma_f64_16x16x4f64 (wave of 64 lanes): A(i, s) in lane
+// i + 16 s, B(s, j) in lane j + 16 s, D(i, j) in register i / 4 of lane
+// j + 16 (i mod 4).
 // Every load and store of the loop is issued unconditionally (the buffer
 // range does the bounds check), so the number of memory operations between
 // a tile's prefetch and its use is fixed and the wait for the prefetch does
 // not also wait for the previous tile's stores.  The prologue issues KM
 // dropped stores to give the first iteration the same count.
-// Every output is sum_l U(r, l) C(l, j) accumulated in l order (the padding
-// adds exact zeros).
+// Every output is sum_l U(r, l) C(l, j) over l in order, four terms per
+// step; the padding adds exact zeros.
 constexpr int kProdRows = 64;
 
+// Work-groups are dispatched to the eight XCDs round-robin; work-group w
+// takes position (w mod 8) * per + w / 8 of the block-major order, so each
+// XCD walks its own contiguous run of blocks and a block's rows of U are
+// fetched into one L2 and reused by every query that touches the block.
+constexpr int kXcds = 8;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 template <int KM, bool CONTIG>
-__global__ __launch_bounds__(64) void blockprod_kernel(StoreView st, const Piece *__restrict__ pieces,
-                                                       const double *__restrict__ C,
-                                                       double *__restrict__ Uout)
+__global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, const Piece *__restrict__ pieces,
+                                                              const int32_t *__restrict__ perm, int npieces,
+                                                              const double *__restrict__ C,
+                                                              double *__restrict__ Uout)
 {
+    constexpr int KS = KM / 4;                     // MFMA steps over l
+    constexpr int NCB = (KM + 15) / 16;            // 16-column blocks (k_q <= k <= KM)
     extern __shared__ __align__(16) double tile[];    // 64 x KM
-    const Piece pc = pieces[blockIdx.x];
+    const int per = (npieces + kXcds - 1) / kXcds;
+    const int pos = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+    if (pos >= npieces) return;
+    const Piece pc = pieces[perm[pos]];
     const int k = st.k;
     const int kq = pc.kq;
     const int lane = threadIdx.x;
     const double *__restrict__ Cp = C + pc.c_off;
+    // B fragments: B(s, j) = C(4 t + s, 16 cb + j) for step t, zero beyond k_q
+    double bf[NCB][KS];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int t = 0; t < KS; ++t) {
+            const int j = 16 * cb + lane % 16, l = 4 * t + lane / 16;
+            bf[cb][t] = j < kq ? Cp[j * KM + l] : 0.0;
+        }
     const double *Ub = st.U + (pc.blk * st.b + pc.r0) * k;
     double *out = Uout + pc.out_off;
     const int64_t ldu = pc.ldu;
@@ -172,23 +228,34 @@ __global__ __launch_bounds__(64) void blockprod_kernel(StoreView st, const Piece
         {
             const __amdgpu_buffer_rsrc_t r = urange(row0 + kProdRows);   // empty after the last
 #pragma unroll
-            for (int i = 0; i < KM; ++i) pre[i] = buf_load(r, (lane + i * kProdRows) * 8);
+            for (int i = 0; i < KM; ++i) pre[i] = buf_load_pinned(r, (lane + i * kProdRows) * 8);
         }
         wave_sync();
-        double u[KM];
+        v4d acc[4][NCB];
 #pragma unroll
-        for (int l = 0; l < KM; ++l) {
-            const double x = tile[lane * k + l];
-            u[l] = (l < k) ? x : 0.0;
-        }
-        wave_sync();                               // every lane holds its row
-        for (int j = 0; j < kq; ++j) {
-            const double *cj = Cp + j * KM;
-            double a = 0.0;
+        for (int rb = 0; rb < 4; ++rb) {
 #pragma unroll
-            for (int l = 0; l < KM; ++l) a = fma(u[l], cj[l], a);
-            tile[lane * kq + j] = a;
+            for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s2 = 0; s2 < KS; ++s2) {
+                const int col = 4 * s2 + lane / 16;
+                const double x = tile[(16 * rb + lane % 16) * k + col];
+                const double a = col < k ? x : 0.0;
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[cb][s2], acc[rb][cb], 0, 0, 0);
+            }
         }
+        wave_sync();                               // every lane has read its A fragments
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * rb + 4 * v + lane / 16, col = 16 * cb + lane % 16;
+                    if (col < kq) tile[row * kq + col] = acc[rb][cb][v];
+                }
         wave_sync();
         if (CONTIG) {                              // the tile is contiguous in the output
             const __amdgpu_buffer_rsrc_t r = buf(out + (int64_t)row0 * kq, nr * kq * (int)sizeof(double));
@@ -231,19 +298,33 @@ hipError_t launch_coef(int k, const Piece *pieces, int npieces, const double *Y,
 }
 
 template <int KM>
-hipError_t run_blockprod(StoreView st, const Piece *pieces, int npieces, const double *C, double *U,
-                         bool contiguous, hipStream_t stream)
+hipError_t run_blockprod(StoreView st, const Piece *pieces, const int32_t *perm, int npieces,
+                         const double *C, double *U, bool contiguous, hipStream_t stream)
 {
     const size_t lds = (size_t)kProdRows * KM * sizeof(double);
+    const unsigned grid = (unsigned)(kXcds * ((npieces + kXcds - 1) / kXcds));
     if (contiguous)
-        blockprod_kernel<KM, true><<<npieces, kProdRows, lds, stream>>>(st, pieces, C, U);
+        blockprod_kernel<KM, true><<<grid, kProdRows, lds, stream>>>(st, pieces, perm, npieces, C, U);
     else
-        blockprod_kernel<KM, false><<<npieces, kProdRows, lds, stream>>>(st, pieces, C, U);
+        blockprod_kernel<KM, false><<<grid, kProdRows, lds, stream>>>(st, pieces, perm, npieces, C, U);
     return hipGetLastError();
 }
 
-hipError_t launch_blockprod(StoreView st, const Piece *pieces, int npieces, const double *C,
-                            double *U, bool contiguous, hipStream_t stream)
+hipError_t launch_order_pieces(const Piece *pieces, int npieces, int64_t nb, const int32_t *boff,
+                               int32_t *bcount, int32_t *perm, hipStream_t stream)
+{
+    if (npieces <= 0) return hipSuccess;
+    timing_begin("order", stream);
+    zero_i32_kernel<<<(unsigned)((nb + kThreads - 1) / kThreads), kThreads, 0, stream>>>(bcount, nb);
+    order_pieces_kernel<<<(unsigned)((npieces + kThreads - 1) / kThreads), kThreads, 0, stream>>>(
+        pieces, npieces, boff, bcount, perm);
+    hipError_t e = hipGetLastError();
+    timing_end("order", stream);
+    return e;
+}
+
+hipError_t launch_blockprod(StoreView st, const Piece *pieces, const int32_t *perm, int npieces,
+                            const double *C, double *U, bool contiguous, hipStream_t stream)
 {
     if (npieces <= 0) return hipSuccess;
     if (st.k < 1 || st.k > kMaxK) return hipErrorInvalidValue;
@@ -251,7 +332,7 @@ hipError_t launch_blockprod(StoreView st, const Piece *pieces, int npieces, cons
     hipError_t e;
     switch (prod_ld(st.k)) {
 #define ZS_PROD_CASE(KM) \
-    case KM: e = run_blockprod<KM>(st, pieces, npieces, C, U, contiguous, stream); break;
+    case KM: e = run_blockprod<KM>(st, pieces, perm, npieces, C, U, contiguous, stream); break;
         ZS_PROD_CASE(4) ZS_PROD_CASE(8) ZS_PROD_CASE(12) ZS_PROD_CASE(16) ZS_PROD_CASE(20)
         ZS_PROD_CASE(24) ZS_PROD_CASE(28) ZS_PROD_CASE(32) ZS_PROD_CASE(48) ZS_PROD_CASE(64)
 #undef ZS_PROD_CASE

@@ -295,17 +295,20 @@ __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
         if (sweeps < 0 && tid == 0) atomicOr(conv_flag, 1);
     }
     for (int j = tid; j < k; j += kThreads) sig[j] = sqrt(fmax(G[j * LDS_N + j], 0.0));
-    // V~ = W1 W2, kept in G (no longer needed)
+    // V~ = W1 W2, kept in G (no longer needed).  The k x k product is staged in
+    // the row buffers Us and Ys, which are contiguous and hold kMaxK^2 values.
+    double *Vs = Us;
+    static_assert(2 * RB >= kMaxK, "row buffers must hold a k x k matrix");
     for (int e = tid; e < k * k; e += kThreads) {
         const int a = e / k, j = e % k;
         double s = 0.0;
         for (int l = 0; l < k; ++l) s = fma(W1[a * LDS_N + l], W2[l * LDS_N + j], s);
-        Ys[e] = s;
+        Vs[e] = s;
     }
     __syncthreads();
     for (int e = tid; e < k * k; e += kThreads) {
         const int a = e / k, j = e % k;
-        G[a * LDS_N + j] = Ys[e];
+        G[a * LDS_N + j] = Vs[e];
     }
     __syncthreads();
     double smax = 0.0;

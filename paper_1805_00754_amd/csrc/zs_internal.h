@@ -125,9 +125,13 @@ hipError_t launch_expand_pieces(StoreView st, const QueryDesc *qd, int nq, int m
                                 hipStream_t stream);
 hipError_t launch_coef(int k, const Piece *pieces, int npieces, const double *Y, const double *F,
                        const double *T, double *C, hipStream_t stream);
+// Block-major order of the pieces: perm lists the pieces of block 0, then of
+// block 1, ... (boff[i] = first position of block i; bcount is nb counters).
+hipError_t launch_order_pieces(const Piece *pieces, int npieces, int64_t nb, const int32_t *boff,
+                               int32_t *bcount, int32_t *perm, hipStream_t stream);
 // contiguous: every query's U has leading dimension k_q (rows back to back)
-hipError_t launch_blockprod(StoreView st, const Piece *pieces, int npieces, const double *C,
-                            double *U, bool contiguous, hipStream_t stream);
+hipError_t launch_blockprod(StoreView st, const Piece *pieces, const int32_t *perm, int npieces,
+                            const double *C, double *U, bool contiguous, hipStream_t stream);
 
 // Raises a kernel's dynamic-LDS limit to `bytes` if it is below (the limit
 // only grows; `cur` caches the value set).  Clears the error state on failure.

@@ -86,14 +86,15 @@ struct DevBuf {
 
 // Scratch of the query pipeline for one stream (grow-only).
 struct Workspace {
-    DevBuf Mp, Vk, Y, GY, F, T, C, P, desc;
+    DevBuf Mp, Vk, Y, GY, F, T, C, P, perm, bcount, desc;
     void *host = nullptr;        // pinned staging of the descriptors
     size_t host_bytes = 0;
     hipEvent_t copied = nullptr; // the last upload from `host` has completed
     void release()
     {
         Mp.release(); Vk.release(); Y.release(); GY.release();
-        F.release(); T.release(); C.release(); P.release(); desc.release();
+        F.release(); T.release(); C.release(); P.release(); perm.release(); bcount.release();
+        desc.release();
         if (host) (void)hipHostFree(host);
         if (copied) (void)hipEventDestroy(copied);
         host = nullptr;
@@ -298,6 +299,20 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
         c_elems += np * kp * kq[q];
         npieces64 += np;
     }
+    // first position of each block in the block-major order of the pieces
+    std::vector<int32_t> boff(st->nb + 1, 0);
+    for (int32_t q = 0; q < nq; ++q) {
+        boff[qds[q].S] += 1;
+        boff[qds[q].S + qds[q].np] -= 1;
+    }
+    {
+        int64_t run = 0, pos = 0;
+        for (int64_t i = 0; i < st->nb; ++i) {
+            run += boff[i];             // pieces of block i
+            boff[i] = (int32_t)pos;
+            pos += run;
+        }
+    }
     if (npieces64 > INT32_MAX)
         return fail(ZS_EUNSUPPORTED, "batch touches %lld blocks (limit %d)", (long long)npieces64,
                     INT32_MAX);
@@ -319,13 +334,15 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
     HIP_TRY(w->T.ensure(sizeof(double) * std::max<int64_t>(1, (int64_t)npartial * k * k)));
     HIP_TRY(w->C.ensure(sizeof(double) * std::max<int64_t>(1, c_elems)));
     HIP_TRY(w->P.ensure(sizeof(Piece) * std::max<int64_t>(1, npieces64)));
+    HIP_TRY(w->perm.ensure(sizeof(int32_t) * std::max<int64_t>(1, npieces64)));
+    HIP_TRY(w->bcount.ensure(sizeof(int32_t) * st->nb));
     double *Mp = w->Mp.as<double>();
     std::vector<const double *> gsrc(gsrc_off.size()), msrc(msrc_idx.size());
     for (size_t i = 0; i < gsrc_off.size(); ++i) gsrc[i] = st->tree + gsrc_off[i] * c * c;
     for (size_t i = 0; i < msrc_idx.size(); ++i) msrc[i] = Mp + (int64_t)msrc_idx[i] * k * c;
     Blob blob;
     const size_t o_chunks = blob.add(chunks), o_probs = blob.add(probs);
-    const size_t o_qds = blob.add(qds), o_pidx = blob.add(pidx);
+    const size_t o_qds = blob.add(qds), o_pidx = blob.add(pidx), o_boff = blob.add(boff);
     const size_t o_gsrc = blob.add(gsrc), o_msrc = blob.add(msrc);
     zs_status s = upload(*w, blob.bytes.data(), blob.bytes.size(), stream);
     if (s != ZS_OK) return s;
@@ -334,6 +351,7 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
     const Prob *d_probs = (const Prob *)(d + o_probs);
     const QueryDesc *d_qds = (const QueryDesc *)(d + o_qds);
     const Piece *d_pieces = w->P.as<Piece>();
+    const int32_t *d_boff = (const int32_t *)(d + o_boff);
     const int32_t *d_pidx = (const int32_t *)(d + o_pidx);
     const double *const *d_gsrc = (const double *const *)(d + o_gsrc);
     const double *const *d_msrc = (const double *const *)(d + o_msrc);
@@ -352,7 +370,10 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
                         w->T.as<double>(), w->C.as<double>(), stream));
     bool contiguous = true;
     for (int32_t q = 0; q < nq; ++q) contiguous = contiguous && ldu[q] == kq[q];
-    HIP_TRY(launch_blockprod(sv, d_pieces, npieces, w->C.as<double>(), U, contiguous, stream));
+    HIP_TRY(launch_order_pieces(d_pieces, npieces, st->nb, d_boff, w->bcount.as<int32_t>(),
+                                w->perm.as<int32_t>(), stream));
+    HIP_TRY(launch_blockprod(sv, d_pieces, w->perm.as<int32_t>(), npieces, w->C.as<double>(), U,
+                             contiguous, stream));
     return ZS_OK;
 }
 

@@ -93,6 +93,28 @@ def test_query_parity_on_gpu_store(sinmix64, rng, kq):
     compare_svd(got, ref, TOL_FP64, st.c, "query [%d,%d) kq %d" % (ts, te, kq))
 
 
+# Stores of other widths and ranks: every compiled width of the block product
+# and of the stack projection (k rounded up to 4, 8, 12, ..., 32, 48, 64).
+OTHER_STORES = [(3_000, 128, 250, 20), (2_000, 33, 64, 33), (1_500, 64, 100, 64), (1_200, 9, 50, 4),
+                (1_700, 30, 128, 27), (900, 16, 40, 13)]
+
+
+@pytest.mark.parametrize("t,c,b,k", OTHER_STORES)
+def test_query_parity_other_widths(t, c, b, k):
+    ser = synth.sinusoid_mixture(t, c, sources=min(6, c), seed=31 + k, noise="iid",
+                                 noise_sigma=0.1)
+    st = gpu_store(ser.A, b, k)
+    U, S, V, kk = download_store(st)
+    ost = oracle.store_from_arrays(st.t, st.c, st.b, st.k, U, S, V, kk)
+    rng = synth.rng_for(40 + k)
+    ts, te = synth.queries_uniform(rng, t, 4, 1, t)
+    for q, kq in enumerate([k, 1, max(1, k // 2), max(1, k - 1)]):
+        say("query parity", (t, c, b, k), int(ts[q]), int(te[q]), kq)
+        got = gpu_query(st, int(ts[q]), int(te[q]), kq)
+        ref = oracle.query(ost, int(ts[q]), int(te[q]), kq)
+        compare_svd(got, ref, TOL_FP64, c, "c %d k %d [%d,%d) kq %d" % (c, k, ts[q], te[q], kq))
+
+
 def test_query_exact_on_block_low_rank():
     """Block rank <= k: the stitched SVD equals the direct SVD of A[t_s:t_e)."""
     t, c, b, k = 5_300, 40, 100, 6
