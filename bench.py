@@ -140,22 +140,30 @@ def main():
     # Roofline of the dominant kernel (largest share of the timed region).
     n_rows = int((te - ts).sum())
     pieces = int(sum((int(e) - 1) // b - int(s) // b + 1 for s, e in zip(ts, te)))
+    kp = prod_ld(k)
     algo = {
-        # U rows read (k) + output rows written (k_q) + coefficient blocks read
-        "blockprod": ("hbm", 8.0 * (n_rows * k + n_rows * k + pieces * k * k), "GB/s"),
+        # per query: its U rows read (k values each) and written (k_q each), plus
+        # one k x k_q coefficient block per touched block (stored k_q x prod_ld(k))
+        "blockprod": ("hbm", 8.0 * (n_rows * k + n_rows * k + pieces * kp * k), "GB/s"),
         # A read once
         "gram": ("hbm", 8.0 * t * c, "GB/s"),
         "project": ("hbm", 8.0 * (t * c + t * k), "GB/s"),
     }
     dom = max(kernels, key=lambda n: kernels[n]["total_ms"])
-    roof = None
     if dom in algo:
         bound, amount, unit = algo[dom]
         avg_s = kernels[dom]["avg_ms"] / 1e3
         achieved = amount / avg_s / 1e9
         roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                "unit": unit, "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                "algorithmic_bytes_per_launch": amount}
+                "unit": unit, "frac": achieved / HBM_PEAK_GBPS,
+                "traffic": profiled_traffic(dom), "algorithmic_bytes_per_launch": amount,
+                "avg_launch_ms": avg_s * 1e3}
+        if dom == "blockprod":
+            # bytes that must cross HBM at least once: U (each stored row once),
+            # the coefficient blocks and the output
+            unique = 8.0 * (t * k + pieces * kp * k + n_rows * k)
+            roof["unique_bytes_per_launch"] = unique
+            roof["unique_frac"] = unique / avg_s / 1e9 / HBM_PEAK_GBPS
     else:
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": None, "traffic": None}
@@ -192,6 +200,35 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
+
+
+def prod_ld(k):
+    """Row stride of a stored coefficient block (k rounded up to a compiled width)."""
+    return (k + 3) & ~3 if k <= 32 else (k + 15) & ~15
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this
+    kernel on this workload (FETCH_SIZE and WRITE_SIZE scaled by a plain copy),
+    or None when there is none or the kernel source has changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "%s_%s.md" % (kernel, WORKLOAD))
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line:
+            key, _, val = line.strip().partition(":")
+            fields[key.strip()] = val.strip()
+    try:
+        src = os.path.join(ROOT, fields["source"])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if sha != fields["source_sha256"]:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
 
 
 def cpu_baseline(A, b, k, ts, te, nq):
