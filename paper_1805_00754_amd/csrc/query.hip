@@ -1,6 +1,7 @@
 // Query-phase kernels around the stacked SVD (Alg. 2):
 //
-//  * coef: per touched block, the k x kq factor C_i with
+//  * coef: per touched block (one work-group per projection chunk), the
+//    k x kq factor C_i with
 //    U_(S:E) rows of block i = U_(i)[r0:r1) C_i.  For a whole block
 //    C_i = U_r(i) (its rows of U_r = Y F); for a boundary block
 //    C_i = T_i U_r(i) since U'_i = X U_(i) T_i (Eq. (9) with U' factored).
@@ -64,42 +65,58 @@ __global__ __launch_bounds__(kThreads) void order_pieces_kernel(const Piece *__r
     perm[boff[blk] + atomicAdd(&bcount[blk], 1)] = p;
 }
 
+// One work-group per chunk of pieces of one query (the projection chunks):
+// F (k_q x k_q) is loaded once; per piece, Y_i (k x k_q) gives U_r(i) = Y_i F,
+// and C_i = U_r(i) or T_i U_r(i) is written transposed and padded.
 __global__ __launch_bounds__(kThreads) void coef_kernel(int k, const Piece *__restrict__ pieces,
+                                                        const StackChunk *__restrict__ chunks,
                                                         const double *__restrict__ Y,
                                                         const double *__restrict__ F,
                                                         const double *__restrict__ T,
                                                         double *__restrict__ C)
 {
-    __shared__ double Ur[kMaxK * kMaxK];
-    __shared__ double Fs[kMaxK * kMaxK];
-    const Piece pc = pieces[blockIdx.x];
-    const int kq = pc.kq;
+    extern __shared__ __align__(16) double sm[];
+    const StackChunk ch = chunks[blockIdx.x];
+    const int kq = ch.kk;
     const int tid = threadIdx.x;
-    const double *Fp = F + (int64_t)pc.q * kSlotK;
-    for (int e = tid; e < kq * kq; e += kThreads) Fs[e] = Fp[e];
-    __syncthreads();
-    const double *Yp = Y + pc.y_off;
-    for (int e = tid; e < k * kq; e += kThreads) {
-        const int l = e / kq, j = e % kq;
-        double s = 0.0;
-        for (int m = 0; m < kq; ++m) s = fma(Yp[l * kq + m], Fs[m * kq + j], s);
-        Ur[e] = s;
-    }
-    __syncthreads();
-    double *Cp = C + pc.c_off;
     const int ld = prod_ld(k);
-    const double *Tp = pc.t_idx < 0 ? nullptr : T + (int64_t)pc.t_idx * k * k;
-    for (int e = tid; e < kq * ld; e += kThreads) {
-        const int j = e / ld, l = e % ld;
-        double s = 0.0;
-        if (l < k) {
-            if (Tp == nullptr) {
-                s = Ur[l * kq + j];
-            } else {
-                for (int a = 0; a < k; ++a) s = fma(Tp[l * k + a], Ur[a * kq + j], s);
-            }
+    double *Fs = sm;                      // kq x kq
+    double *Ys = Fs + kq * kq;            // k x kq
+    double *Ur = Ys + k * kq;             // k x kq
+    double *Ts = Ur + k * kq;             // k x k
+    const double *Fp = F + (int64_t)ch.prob * kSlotK;
+    for (int e = tid; e < kq * kq; e += kThreads) Fs[e] = Fp[e];
+    for (int p = 0; p < ch.npieces; ++p) {
+        const Piece &pc = pieces[ch.piece0 + p];
+        const double *Yp = Y + pc.y_off;
+        const bool partial = pc.t_idx >= 0;
+        __syncthreads();                  // the previous piece is done with Ys, Ur, Ts
+        for (int e = tid; e < k * kq; e += kThreads) Ys[e] = Yp[e];
+        if (partial) {
+            const double *Tp = T + (int64_t)pc.t_idx * k * k;
+            for (int e = tid; e < k * k; e += kThreads) Ts[e] = Tp[e];
         }
-        Cp[e] = s;
+        __syncthreads();
+        for (int e = tid; e < k * kq; e += kThreads) {
+            const int l = e / kq, j = e % kq;
+            double s = 0.0;
+            for (int m = 0; m < kq; ++m) s = fma(Ys[l * kq + m], Fs[m * kq + j], s);
+            Ur[e] = s;
+        }
+        __syncthreads();
+        double *Cp = C + pc.c_off;
+        for (int e = tid; e < kq * ld; e += kThreads) {
+            const int j = e / ld, l = e % ld;
+            double s = 0.0;
+            if (l < k) {
+                if (!partial) {
+                    s = Ur[l * kq + j];
+                } else {
+                    for (int a = 0; a < k; ++a) s = fma(Ts[l * k + a], Ur[a * kq + j], s);
+                }
+            }
+            Cp[e] = s;
+        }
     }
 }
 
@@ -286,12 +303,19 @@ hipError_t launch_expand_pieces(StoreView st, const QueryDesc *qd, int nq, int m
     return e;
 }
 
-hipError_t launch_coef(int k, const Piece *pieces, int npieces, const double *Y, const double *F,
-                       const double *T, double *C, hipStream_t stream)
+hipError_t launch_coef(int k, int kq_max, const Piece *pieces, const StackChunk *chunks,
+                       int nchunks, const double *Y, const double *F, const double *T, double *C,
+                       hipStream_t stream)
 {
-    if (npieces <= 0) return hipSuccess;
+    if (nchunks <= 0) return hipSuccess;
+    const size_t lds = (size_t)(kq_max * kq_max + 2 * k * kq_max + k * k) * sizeof(double);
+    static size_t cur = 0;
+    {
+        hipError_t e = ensure_lds((const void *)coef_kernel, lds, cur);
+        if (e != hipSuccess) return e;
+    }
     timing_begin("coef", stream);
-    coef_kernel<<<npieces, kThreads, 0, stream>>>(k, pieces, Y, F, T, C);
+    coef_kernel<<<nchunks, kThreads, lds, stream>>>(k, pieces, chunks, Y, F, T, C);
     hipError_t e = hipGetLastError();
     timing_end("coef", stream);
     return e;

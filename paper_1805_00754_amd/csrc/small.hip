@@ -14,7 +14,6 @@
 namespace zs {
 namespace {
 
-constexpr int LDS_N = kMaxK + 1;   // leading dimension of k x k LDS matrices
 
 __device__ __forceinline__ void rr_pair(int step, int pi, int N, int &p, int &q)
 {
@@ -29,7 +28,7 @@ __device__ __forceinline__ void rr_pair(int step, int pi, int N, int &p, int &q)
 }
 
 // Two-sided cyclic Jacobi, parallel round-robin ordering, on the symmetric
-// n x n matrix G (row-major, ld LDS_N) accumulating W (ld LDS_N, identity on
+// n x n matrix G (row-major, leading dimension ld) accumulating W (ld, identity on
 // entry).  A pair is rotated when |g_pq| > tol sqrt(g_pp g_qq), tol = n eps
 // (the relative stopping rule of Demmel & Veselic).  As in the classical
 // algorithm, the rotated 2 x 2 block is set exactly afterwards: g_pq = 0,
@@ -38,13 +37,13 @@ __device__ __forceinline__ void rr_pair(int step, int pi, int N, int &p, int &q)
 // numerically zero and are not rotated.
 // Returns the number of sweeps, or -1 if the cap was hit.  All threads of
 // the block must call it; cs/sn/dp/dq need n/2 entries.
-__device__ int sym_jacobi(double *G, double *W, int n, double *cs_sh, double *sn_sh, double *dp_sh,
-                          double *dq_sh, int *flag_sh, double *tr_sh)
+__device__ int sym_jacobi(double *G, double *W, int n, int ld, double *cs_sh, double *sn_sh,
+                          double *dp_sh, double *dq_sh, int *flag_sh, double *tr_sh)
 {
     const int tid = threadIdx.x;
     if (tid == 0) {
         double tr = 0.0;
-        for (int i = 0; i < n; ++i) tr += fabs(G[i * LDS_N + i]);
+        for (int i = 0; i < n; ++i) tr += fabs(G[i * ld + i]);
         *tr_sh = tr;
     }
     __syncthreads();
@@ -61,8 +60,8 @@ __device__ int sym_jacobi(double *G, double *W, int n, double *cs_sh, double *sn
                 rr_pair(step, pi, N, p, q);
                 double cs = 1.0, sn = 0.0, dp = 0.0, dq = 0.0;
                 if (p < n && q < n) {
-                    const double gpp = G[p * LDS_N + p], gqq = G[q * LDS_N + q];
-                    const double gpq = G[p * LDS_N + q];
+                    const double gpp = G[p * ld + p], gqq = G[q * ld + q];
+                    const double gpq = G[p * ld + q];
                     if (gpq != 0.0 && fabs(gpp) > floor && fabs(gqq) > floor &&
                         fabs(gpq) > tol * sqrt(fabs(gpp)) * sqrt(fabs(gqq))) {
                         const double zeta = (gqq - gpp) / (2.0 * gpq);
@@ -88,13 +87,13 @@ __device__ int sym_jacobi(double *G, double *W, int n, double *cs_sh, double *sn
                 const double cs = cs_sh[pi];
                 int p, q;
                 rr_pair(step, pi, N, p, q);
-                double gp = G[r * LDS_N + p], gq = G[r * LDS_N + q];
-                G[r * LDS_N + p] = cs * gp - sn * gq;
-                G[r * LDS_N + q] = sn * gp + cs * gq;
-                gp = W[r * LDS_N + p];
-                gq = W[r * LDS_N + q];
-                W[r * LDS_N + p] = cs * gp - sn * gq;
-                W[r * LDS_N + q] = sn * gp + cs * gq;
+                double gp = G[r * ld + p], gq = G[r * ld + q];
+                G[r * ld + p] = cs * gp - sn * gq;
+                G[r * ld + q] = sn * gp + cs * gq;
+                gp = W[r * ld + p];
+                gq = W[r * ld + q];
+                W[r * ld + p] = cs * gp - sn * gq;
+                W[r * ld + q] = sn * gp + cs * gq;
             }
             __syncthreads();
             // rows p, q of G: G <- J^T G
@@ -105,9 +104,9 @@ __device__ int sym_jacobi(double *G, double *W, int n, double *cs_sh, double *sn
                 const double cs = cs_sh[pi];
                 int p, q;
                 rr_pair(step, pi, N, p, q);
-                const double gp = G[p * LDS_N + r], gq = G[q * LDS_N + r];
-                G[p * LDS_N + r] = cs * gp - sn * gq;
-                G[q * LDS_N + r] = sn * gp + cs * gq;
+                const double gp = G[p * ld + r], gq = G[q * ld + r];
+                G[p * ld + r] = cs * gp - sn * gq;
+                G[q * ld + r] = sn * gp + cs * gq;
             }
             __syncthreads();
             // the rotated 2 x 2 blocks, exactly
@@ -115,10 +114,10 @@ __device__ int sym_jacobi(double *G, double *W, int n, double *cs_sh, double *sn
                 if (sn_sh[pi] == 0.0) continue;
                 int p, q;
                 rr_pair(step, pi, N, p, q);
-                G[p * LDS_N + p] = dp_sh[pi];
-                G[q * LDS_N + q] = dq_sh[pi];
-                G[p * LDS_N + q] = 0.0;
-                G[q * LDS_N + p] = 0.0;
+                G[p * ld + p] = dp_sh[pi];
+                G[q * ld + q] = dq_sh[pi];
+                G[p * ld + q] = 0.0;
+                G[q * ld + p] = 0.0;
             }
             __syncthreads();
         }
@@ -133,13 +132,14 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *_
                                                             const double *__restrict__ GYpart,
                                                             const double *__restrict__ Vk,
                                                             double *__restrict__ F,
-                                                            double rank_tol,
+                                                            double rank_tol, int kk_max,
                                                             int *__restrict__ conv_flag)
 {
     extern __shared__ __align__(16) double smem[];
-    double *G = smem;                         // kk x kk, ld LDS_N
-    double *W = G + kMaxK * LDS_N;            // kk x kk, ld LDS_N
-    double *Vn = W + kMaxK * LDS_N;           // c x kk (V_k W)
+    const int ld = kk_max + 1;                // leading dimension of the kk x kk matrices
+    double *G = smem;                         // kk x kk
+    double *W = G + kk_max * ld;              // kk x kk
+    double *Vn = W + kk_max * ld;             // c x kk (V_k W)
     __shared__ double cs_sh[kMaxK / 2], sn_sh[kMaxK / 2], dp_sh[kMaxK / 2], dq_sh[kMaxK / 2];
     __shared__ double sig[kMaxK], flip[kMaxK];
     __shared__ int pos[kMaxK], inv[kMaxK], keep[kMaxK];
@@ -153,14 +153,14 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *_
         const int a = e / kk, b = e % kk;
         double s = 0.0;
         for (int sl = 0; sl < P.ny; ++sl) s += GYpart[(int64_t)(P.y0 + sl) * kSlotK + e];
-        G[a * LDS_N + b] = s;
-        W[a * LDS_N + b] = (a == b) ? 1.0 : 0.0;
+        G[a * ld + b] = s;
+        W[a * ld + b] = (a == b) ? 1.0 : 0.0;
     }
     __syncthreads();
-    const int sweeps = sym_jacobi(G, W, kk, cs_sh, sn_sh, dp_sh, dq_sh, &flag_sh, &tr_sh);
+    const int sweeps = sym_jacobi(G, W, kk, ld, cs_sh, sn_sh, dp_sh, dq_sh, &flag_sh, &tr_sh);
     if (sweeps < 0 && tid == 0) atomicOr(conv_flag, 1);
 
-    for (int j = tid; j < kk; j += kThreads) sig[j] = sqrt(fmax(G[j * LDS_N + j], 0.0));
+    for (int j = tid; j < kk; j += kThreads) sig[j] = sqrt(fmax(G[j * ld + j], 0.0));
     __syncthreads();
     double smax = 0.0;
     for (int j = 0; j < kk; ++j) smax = fmax(smax, sig[j]);
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *_
     for (int e = tid; e < c * kk; e += kThreads) {
         const int a = e / kk, j = e % kk;
         double s = 0.0;
-        for (int l = 0; l < kk; ++l) s = fma(vk[a * kk + l], W[l * LDS_N + j], s);
+        for (int l = 0; l < kk; ++l) s = fma(vk[a * kk + l], W[l * ld + j], s);
         Vn[a * kk + j] = s;
     }
     __syncthreads();
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *_
     for (int e = tid; e < kk * kk; e += kThreads) {
         const int l = e / kk, pp = e % kk;
         const int j = inv[pp];
-        Fp[l * kk + pp] = keep[j] ? flip[j] * W[l * LDS_N + j] / sig[j] : 0.0;
+        Fp[l * kk + pp] = keep[j] ? flip[j] * W[l * ld + j] / sig[j] : 0.0;
     }
     for (int pp = tid; pp < kk; pp += kThreads) {
         const int j = inv[pp];
@@ -223,18 +223,19 @@ __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
 {
     constexpr int RB = 32;
     extern __shared__ __align__(16) double smem[];
-    double *G = smem;                         // k x k, ld LDS_N (G_P, then G_Y)
-    double *W1 = G + kMaxK * LDS_N;           // first-stage eigenvectors
-    double *W2 = W1 + kMaxK * LDS_N;          // second-stage rotation
-    double *Us = W2 + kMaxK * LDS_N;          // RB x k staged rows of P = X U Sigma
-    double *Ys = Us + RB * kMaxK;             // RB x k rows of Y = P W1
+    const int k = st.k;
+    const int ld = k + 1;                     // leading dimension of the k x k matrices
+    double *G = smem;                         // k x k (G_P, then G_Y)
+    double *W1 = G + k * ld;                  // first-stage eigenvectors
+    double *W2 = W1 + k * ld;                 // second-stage rotation
+    double *Us = W2 + k * ld;                 // RB x k staged rows of P = X U Sigma
+    double *Ys = Us + RB * k;                 // RB x k rows of Y = P W1
     __shared__ double cs_sh[kMaxK / 2], sn_sh[kMaxK / 2], dp_sh[kMaxK / 2], dq_sh[kMaxK / 2];
     __shared__ double sig[kMaxK], sblk[kMaxK];
     __shared__ int flag_sh;
     __shared__ double tr_sh;
 
     const Piece pc = pieces[pidx[blockIdx.x]];
-    const int k = st.k;
     const int c = (int)st.c;
     const int tid = threadIdx.x;
     const double *Ub = st.U + (pc.blk * st.b + pc.r0) * k;
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
                 for (int e = tid; e < nr * k; e += kThreads) {
                     const int rr = e / k, j = e % k;
                     double s = 0.0;
-                    for (int a = 0; a < k; ++a) s = fma(Us[rr * k + a], W1[a * LDS_N + j], s);
+                    for (int a = 0; a < k; ++a) s = fma(Us[rr * k + a], W1[a * ld + j], s);
                     Ys[e] = s;
                 }
                 __syncthreads();
@@ -286,29 +287,29 @@ __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
             const int e = tid + x * kThreads;
             if (e < k * k) {
                 const int a = e / k, b = e % k;
-                G[a * LDS_N + b] = acc[x];
-                Wp[a * LDS_N + b] = (a == b) ? 1.0 : 0.0;
+                G[a * ld + b] = acc[x];
+                Wp[a * ld + b] = (a == b) ? 1.0 : 0.0;
             }
         }
         __syncthreads();
-        const int sweeps = sym_jacobi(G, Wp, k, cs_sh, sn_sh, dp_sh, dq_sh, &flag_sh, &tr_sh);
+        const int sweeps = sym_jacobi(G, Wp, k, ld, cs_sh, sn_sh, dp_sh, dq_sh, &flag_sh, &tr_sh);
         if (sweeps < 0 && tid == 0) atomicOr(conv_flag, 1);
     }
-    for (int j = tid; j < k; j += kThreads) sig[j] = sqrt(fmax(G[j * LDS_N + j], 0.0));
+    for (int j = tid; j < k; j += kThreads) sig[j] = sqrt(fmax(G[j * ld + j], 0.0));
     // V~ = W1 W2, kept in G (no longer needed).  The k x k product is staged in
-    // the row buffers Us and Ys, which are contiguous and hold kMaxK^2 values.
+    // the row buffers Us and Ys, which are contiguous and hold 2 RB k >= k^2 values.
     double *Vs = Us;
     static_assert(2 * RB >= kMaxK, "row buffers must hold a k x k matrix");
     for (int e = tid; e < k * k; e += kThreads) {
         const int a = e / k, j = e % k;
         double s = 0.0;
-        for (int l = 0; l < k; ++l) s = fma(W1[a * LDS_N + l], W2[l * LDS_N + j], s);
+        for (int l = 0; l < k; ++l) s = fma(W1[a * ld + l], W2[l * ld + j], s);
         Vs[e] = s;
     }
     __syncthreads();
     for (int e = tid; e < k * k; e += kThreads) {
         const int a = e / k, j = e % k;
-        G[a * LDS_N + j] = Vs[e];
+        G[a * ld + j] = Vs[e];
     }
     __syncthreads();
     double smax = 0.0;
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
     for (int e = tid; e < k * c; e += kThreads) {
         const int j = e / c, col = e % c;
         double s = 0.0;
-        for (int l = 0; l < k; ++l) s = fma(G[l * LDS_N + j], Vt[(int64_t)l * c + col], s);
+        for (int l = 0; l < k; ++l) s = fma(G[l * ld + j], Vt[(int64_t)l * c + col], s);
         Mrows[e] = sig[j] * s;
     }
     // T = Sigma_(i) V~ Sigma~^+  (k x k, row-major)
@@ -328,25 +329,27 @@ __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
     for (int e = tid; e < k * k; e += kThreads) {
         const int a = e / k, j = e % k;
         const bool kp = sig[j] > rank_tol * smax && sig[j] > 0.0;
-        Tp[e] = kp ? sblk[a] * G[a * LDS_N + j] / sig[j] : 0.0;
+        Tp[e] = kp ? sblk[a] * G[a * ld + j] / sig[j] : 0.0;
     }
 }
 
 }  // namespace
 
-hipError_t launch_finalize(int c, const Prob *probs, int nprob, const double *GYpart,
+hipError_t launch_finalize(int c, const Prob *probs, int nprob, int kk_max, const double *GYpart,
                            const double *Vk, double *F, double rank_tol, int *conv_flag,
                            hipStream_t stream)
 {
     if (nprob <= 0) return hipSuccess;
+    if (kk_max < 1 || kk_max > kMaxK) return hipErrorInvalidValue;
     timing_begin("finalize", stream);
-    const size_t lds = (size_t)(2 * kMaxK * LDS_N + c * kMaxK) * sizeof(double);
+    const size_t lds = (size_t)(2 * kk_max * (kk_max + 1) + c * kk_max) * sizeof(double);
     static size_t cur = 0;
     {
         hipError_t e = ensure_lds((const void *)finalize_kernel, lds, cur);
         if (e != hipSuccess) return e;
     }
-    finalize_kernel<<<nprob, kThreads, lds, stream>>>(c, probs, GYpart, Vk, F, rank_tol, conv_flag);
+    finalize_kernel<<<nprob, kThreads, lds, stream>>>(c, probs, GYpart, Vk, F, rank_tol, kk_max,
+                                                      conv_flag);
     hipError_t e = hipGetLastError();
     timing_end("finalize", stream);
     return e;
@@ -358,7 +361,7 @@ hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx
 {
     if (npartial <= 0) return hipSuccess;
     timing_begin("partial", stream);
-    const size_t lds = (size_t)(3 * kMaxK * LDS_N + 2 * 32 * kMaxK) * sizeof(double);
+    const size_t lds = (size_t)(3 * st.k * (st.k + 1) + 2 * 32 * st.k) * sizeof(double);
     static size_t cur = 0;
     {
         hipError_t e = ensure_lds((const void *)partial_kernel, lds, cur);

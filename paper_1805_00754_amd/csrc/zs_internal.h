@@ -109,7 +109,7 @@ hipError_t launch_project(const double *X, int64_t ld, int c, const Chunk *chunk
 hipError_t launch_stack_project(StoreView st, const Piece *pieces, const double *Mp,
                                 const StackChunk *chunks, int nchunks, int kq_max,
                                 const double *Vk, double *Y, double *GYpart, hipStream_t stream);
-hipError_t launch_finalize(int c, const Prob *probs, int nprob, const double *GYpart,
+hipError_t launch_finalize(int c, const Prob *probs, int nprob, int kk_max, const double *GYpart,
                            const double *Vk, double *F, double rank_tol, int *conv_flag,
                            hipStream_t stream);
 hipError_t launch_utransform(double *U, int k, const Chunk *chunks, int nchunks, const double *F,
@@ -123,8 +123,9 @@ hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx
                           hipStream_t stream);
 hipError_t launch_expand_pieces(StoreView st, const QueryDesc *qd, int nq, int max_np, Piece *pieces,
                                 hipStream_t stream);
-hipError_t launch_coef(int k, const Piece *pieces, int npieces, const double *Y, const double *F,
-                       const double *T, double *C, hipStream_t stream);
+hipError_t launch_coef(int k, int kq_max, const Piece *pieces, const StackChunk *chunks,
+                       int nchunks, const double *Y, const double *F, const double *T, double *C,
+                       hipStream_t stream);
 // Block-major order of the pieces: perm lists the pieces of block 0, then of
 // block 1, ... (boff[i] = first position of block i; bcount is nb counters).
 hipError_t launch_order_pieces(const Piece *pieces, int npieces, int64_t nb, const int32_t *boff,

@@ -364,10 +364,10 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
                             st->conv, stream));
     HIP_TRY(launch_stack_project(sv, d_pieces, Mp, d_chunks, nchunks, kq_max, w->Vk.as<double>(),
                                  w->Y.as<double>(), w->GY.as<double>(), stream));
-    HIP_TRY(launch_finalize((int)c, d_probs, nq, w->GY.as<double>(), w->Vk.as<double>(),
+    HIP_TRY(launch_finalize((int)c, d_probs, nq, kq_max, w->GY.as<double>(), w->Vk.as<double>(),
                             w->F.as<double>(), kRankTolFP64, st->conv, stream));
-    HIP_TRY(launch_coef(k, d_pieces, npieces, w->Y.as<double>(), w->F.as<double>(),
-                        w->T.as<double>(), w->C.as<double>(), stream));
+    HIP_TRY(launch_coef(k, kq_max, d_pieces, d_chunks, nchunks, w->Y.as<double>(),
+                        w->F.as<double>(), w->T.as<double>(), w->C.as<double>(), stream));
     bool contiguous = true;
     for (int32_t q = 0; q < nq; ++q) contiguous = contiguous && ldu[q] == kq[q];
     HIP_TRY(launch_order_pieces(d_pieces, npieces, st->nb, d_boff, w->bcount.as<int32_t>(),
@@ -502,7 +502,7 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
                             st->conv, stream));
     ST_TRY2(launch_project(Ad, lda, (int)c, d_chunks, nchunks, k, Vk.as<double>(), st->U,
                            GY.as<double>(), stream));
-    ST_TRY2(launch_finalize((int)c, d_probs, (int)nb, GY.as<double>(), Vk.as<double>(),
+    ST_TRY2(launch_finalize((int)c, d_probs, (int)nb, k, GY.as<double>(), Vk.as<double>(),
                             F.as<double>(), kRankTolFP64, st->conv, stream));
     ST_TRY2(launch_utransform(st->U, k, d_chunks, nchunks, F.as<double>(), stream));
     // Gram tree over the stored blocks: leaves, then one launch per level.
