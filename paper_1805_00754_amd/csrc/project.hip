@@ -153,16 +153,21 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// stack_project: one wave per chunk of pieces, one stack row per lane, tiles
-// of 64 rows.  A lane's row is s_r x_r with x_r = V_(i)^T row j of the store
-// (s_r = sigma_ij) for a whole block, or Partial-SVD row j (s_r = 1).  Rows
-// come into LDS in 16-column panels (coalesced loads through the lanes' row
-// pointers); each lane then accumulates y_r = x_r V_k over the panel with
-// V_k rows read through the scalar cache (wave-uniform addresses), and
-// scales by s_r.  The Y tile is stored through LDS with coalesced stores, and
-// its Gram Y^T Y is accumulated from LDS: lane g owns entries (a, b0..b0+3)
-// of group g = a * nb4 + b0 / 4.
+// stack_project: one wave per chunk of pieces, tiles of 64 stack rows.  Row r
+// of a tile is s_r x_r with x_r = V_(i)^T row j of the store (s_r = sigma_ij)
+// for a whole block, or Partial-SVD row j (s_r = 1); lane r holds its row
+// pointer.  Rows come into LDS in 16-column panels (coalesced loads through
+// the lanes' row pointers) and the tile product X V_k runs on the matrix
+// cores (FP64 MFMA 16x16x4; A fragments from the LDS panel, B fragments of
+// V_k loaded per panel), four row blocks times ceil(kq / 16) column blocks.
+// Operand layout: A(i, s) in lane i + 16 s, B(s, j) in lane j + 16 s, D(i, j)
+// in register i / 4 of lane j + 16 (i mod 4).  Rows are scaled by s_r on the
+// way to LDS; the Y tile is stored with coalesced stores, and its Gram
+// Y^T Y is accumulated from LDS: lane g owns entries (a, b0..b0+3) of group
+// g = a * nb4 + b0 / 4.
 constexpr int kPanel = 16;
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef const double __attribute__((address_space(1))) gdouble;
 
 template <int KQM>
 __global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const Piece *__restrict__ pieces,
@@ -175,6 +180,7 @@ __global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const P
     extern __shared__ __align__(16) double sm[];
     constexpr int NB4 = (KQM + 3) / 4;
     constexpr int NPASS = (KQM * NB4 + 63) / 64;
+    constexpr int NCB = (KQM + 15) / 16;           // 16-column blocks of Y
     const StackChunk ch = chunks[blockIdx.x];
     const int c = (int)st.c, k = st.k, kq = ch.kk;
     const int lane = threadIdx.x;
@@ -206,9 +212,11 @@ __global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const P
             }
         }
         const uint64_t xa = reinterpret_cast<uint64_t>(xp);
-        double acc[KQM];
+        v4d acc[4][NCB];
 #pragma unroll
-        for (int j = 0; j < KQM; ++j) acc[j] = 0.0;
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = (v4d){0.0, 0.0, 0.0, 0.0};
         for (int a0 = 0; a0 < c; a0 += kPanel) {
             wave_sync();
             // panel: 64 rows x 16 columns, 16 lanes per row, 4 rows per step;
@@ -221,28 +229,46 @@ __global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const P
                 const int row = i * 4 + lane / 16;
                 const uint32_t lo = __shfl((uint32_t)xa, row, 64);
                 const uint32_t hi = __shfl((uint32_t)(xa >> 32), row, 64);
-                typedef const double __attribute__((address_space(1))) gdouble;
                 v[i] = reinterpret_cast<gdouble *>(((uint64_t)hi << 32) | lo)[colc];
             }
+            // B fragments: B(s, j) = V_k(a0 + 4 t + s, 16 cb + j), zero outside c x kq
+            double bf[NCB][4];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int vr = a0 + 4 * t + lane / 16, vc = 16 * cb + lane % 16;
+                    const double x = V[min(vr, c - 1) * kq + min(vc, kq - 1)];
+                    bf[cb][t] = (vr < c && vc < kq) ? x : 0.0;
+                }
 #pragma unroll
             for (int i = 0; i < 16; ++i)
                 sm[(i * 4 + lane / 16) * (kPanel + 1) + lane % 16] = col < c ? v[i] : 0.0;
             wave_sync();
-            const int na = min(kPanel, c - a0);
 #pragma unroll
-            for (int a = 0; a < kPanel; ++a) {
-                if (a < na) {
-                    const double x = sm[lane * (kPanel + 1) + a];
-                    const double *vr = V + (int64_t)(a0 + a) * kq;
+            for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-                    for (int j = 0; j < KQM; ++j) acc[j] = fma(x, vr[j], acc[j]);
+                for (int t = 0; t < 4; ++t) {
+                    const double a = sm[(16 * rb + lane % 16) * (kPanel + 1) + 4 * t + lane / 16];
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[cb][t], acc[rb][cb], 0, 0, 0);
                 }
-            }
         }
         wave_sync();
+        // D(i, j) of a 16 x 16 block sits in register i / 4 of lane j + 16 (i mod 4)
 #pragma unroll
-        for (int j = 0; j < KQM; ++j)
-            if (j < kq) sm[lane * ldy + j] = scale * acc[j];
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * rb + 4 * v + lane / 16;
+                const double sc = __shfl(scale, row, 64);
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) {
+                    const int col = 16 * cb + lane % 16;
+                    if (col < kq) sm[row * ldy + col] = sc * acc[rb][cb][v];
+                }
+            }
         wave_sync();
         {
             double *Yt = Y + ch.y_off + (int64_t)r0 * kq;
