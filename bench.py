@@ -44,6 +44,9 @@ def main():
     ap.add_argument("--latency-samples", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=32)
+    ap.add_argument("--serve-rates", default="500,2000,8000",
+                    help="arrival rates (queries/s) of the serving runs; empty to skip")
+    ap.add_argument("--serve-requests", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -130,6 +133,7 @@ def main():
         torch.cuda.synchronize()
         if q >= 4:
             lat.append((time.perf_counter() - a) * 1e3)
+    serving = serve_runs(st, args) if args.serve_rates else None
     st.free()
 
     q_ms = float(np.mean(query_ms))
@@ -197,9 +201,35 @@ def main():
         "single_query_svds_per_s": 1e3 / float(np.mean(lat)) if lat else None,
         "kernels_ms_per_step": {n: v["total_ms"] / args.steps for n, v in kernels.items()},
         "roofline": roof,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
+
+
+def serve_runs(st, args):
+    """Open-loop serving on the resident store: Poisson arrivals at each rate,
+    lengths log-uniform in [1e4, 3.2e5] rows, k_q uniform over {8, 16, k}."""
+    import numpy as np
+
+    from paper_1805_00754_amd import serve, synth
+
+    out = []
+    for rate in [float(x) for x in args.serve_rates.split(",") if x]:
+        rng = synth.rng_for(synth.SEED_BASE + 4)
+        reqs = serve.make_requests(rng, st.t, args.serve_requests, rate, 1e4, 3.2e5,
+                                   [8, 16, st.k])
+        srv = serve.Server(st, max_queries=512, budget_bytes=4 << 30, depth=2)
+        log("serving %d requests at %g/s" % (len(reqs), rate))
+        res = srv.run(reqs)
+        served = len(reqs) - len(res["rejected"])
+        out.append({"rate_per_s": rate, "requests": len(reqs), "served": served,
+                    "p50_ms": res["p50"] * 1e3, "p99_ms": res["p99"] * 1e3,
+                    "throughput_per_s": served / res["span"],
+                    "batches": len(res["batches"]),
+                    "mean_batch": float(np.mean(res["batches"]))})
+        del srv
+    return out
 
 
 def prod_ld(k):

@@ -50,7 +50,7 @@ typedef enum {
 } zs_status;
 
 typedef enum { ZS_F64 = 0, ZS_F32 = 1, ZS_BF16 = 2 } zs_dtype;          /* element type of A */
-typedef enum { ZS_MODE_FP64 = 0, ZS_MODE_FP32 = 1, ZS_MODE_BF16 = 2 } zs_mode; /* bulk arithmetic */
+typedef enum { ZS_MODE_FP64 = 0, ZS_MODE_FP32 = 1, ZS_MODE_BF16 = 2 } zs_mode; /* factor storage */
 
 typedef struct zs_store zs_store;   /* opaque; owns the device-resident U_(i), Sigma_(i), V_(i) */
 
@@ -67,7 +67,15 @@ typedef struct zs_store zs_store;   /* opaque; owns the device-resident U_(i), S
  *   t, c   rows (time ticks) and columns (series); t >= 1, 1 <= c <= ZS_MAX_C.
  *   b      block size >= 1.  k: stored rank, 1 <= k <= min(c, ZS_MAX_K).
  *          Block i keeps k_i = min(k, rows_i, numerical rank) triplets.
- *   mode   ZS_MODE_FP64 (only mode of this build; FP64 A required).
+ *   a_type ZS_F64, ZS_F32 or ZS_BF16; every mode reads every type and widens
+ *          it exactly.
+ *   mode   ZS_MODE_FP64: U_(i) and V_(i) stored in FP64, rank threshold
+ *          1e-11.  ZS_MODE_FP32 and ZS_MODE_BF16: U_(i) and V_(i) stored in
+ *          FP32 (half the memory and half the block-product traffic), rank
+ *          threshold 1e-5; queries then return U and V in FP32.  In every
+ *          mode the Gram, the eigen-solves and the Rayleigh-Ritz step run in
+ *          FP64 (this build keeps no BF16 arithmetic: BF16 mode differs from
+ *          FP32 mode only in the input type it is meant for).
  *   out    receives the new store.  The library owns its device memory until
  *          zs_store_free.  The call synchronises `stream` once at the end to
  *          check the per-block Jacobi status; on ZS_ENOCONV the store is still
@@ -84,7 +92,8 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
  *   V       device, c x k_q row-major, leading dimension ldv >= k_q; column j = v_j.
  *   k_out   device int32: the numerical rank kept (<= k_q).  Columns j >= k_out
  *           of U and V and entries of S are zero.
- *   U and V are double in FP64 mode.  Asynchronous on `stream`.
+ *   U and V are double in FP64 mode and float in the FP32 / BF16 modes; S is
+ *   always double.  Asynchronous on `stream`.
  */
 zs_status zs_query(const zs_store *st, int64_t t_s, int64_t t_e, int32_t k_q, void *U, int64_t ldu,
                    double *S, void *V, int64_t ldv, int32_t *k_out, hipStream_t stream);
@@ -92,7 +101,7 @@ zs_status zs_query(const zs_store *st, int64_t t_s, int64_t t_e, int32_t k_q, vo
 /*
  * zs_query_batch -- nq independent queries in one set of launches.
  *   t_s, t_e, k_q   host arrays of nq ranges and ranks (same rules as zs_query).
- *   U, S, V         device base pointers; query q writes
+ *   U, S, V         device base pointers (element types as in zs_query); query q writes
  *                     U + u_off[q]  (n_q x k_q[q], leading dimension k_q[q]),
  *                     S + s_off[q]  (k_q[q] doubles),
  *                     V + v_off[q]  (c x k_q[q], leading dimension k_q[q]),
@@ -108,7 +117,8 @@ zs_status zs_query_batch(const zs_store *st, int32_t nq, const int64_t *t_s, con
 /* Releases the store's device memory (synchronises the device first). */
 void zs_store_free(zs_store *st);
 
-/* Device bytes held by the store: the block factors and the Gram tree of the
+/* Device bytes held by the store: the block factors (8 or 4 bytes per element
+ * by mode) and the Gram tree of the
  * blocks (2 n2 c x c FP64 matrices, n2 = smallest power of two >= nb), not the
  * per-stream query scratch. */
 int64_t zs_store_bytes(const zs_store *st);

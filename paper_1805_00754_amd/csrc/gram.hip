@@ -1,4 +1,5 @@
-// Tall-skinny Gram panels: G = X^T X over a run of rows of X, in FP64.
+// Tall-skinny Gram panels: G = X^T X over a run of rows of X, accumulated in
+// FP64 whatever the element type of X (double, float or bf16).
 //
 // Used for the block Gram G_i = A_(i)^T A_(i) of the storage phase and for the
 // Gram of each query's stacked matrix M = [Sigma'_S V'_S^T; ...; Sigma'_E V'_E^T]
@@ -13,8 +14,8 @@
 namespace zs {
 namespace {
 
-template <int TM>
-__global__ __launch_bounds__(kThreads) void gram_kernel(const double *__restrict__ X, int64_t ld,
+template <int TM, typename TA>
+__global__ __launch_bounds__(kThreads) void gram_kernel(const TA *__restrict__ X, int64_t ld,
                                                         int c, const Chunk *__restrict__ chunks,
                                                         double *__restrict__ Gpart)
 {
@@ -37,16 +38,16 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const double *__restrict
 #pragma unroll
         for (int n = 0; n < TM; ++n) acc[m][n] = 0.0;
 
-    const double *Xc = X + ch.x_off;
+    const TA *Xc = X + ch.x_off;
     for (int r0 = 0; r0 < ch.rows; r0 += RB) {
         for (int e = threadIdx.x; e < RB * TILE; e += kThreads) {
             const int rr = e / TILE, cc = e % TILE;
             const int row = r0 + rr;
             double vi = 0.0, vj = 0.0;
             if (row < ch.rows) {
-                const double *xr = Xc + (int64_t)row * ld;
-                if (ci0 + cc < c) vi = xr[ci0 + cc];
-                if (cj0 + cc < c) vj = xr[cj0 + cc];
+                const TA *xr = Xc + (int64_t)row * ld;
+                if (ci0 + cc < c) vi = load_as_double(xr, ci0 + cc);
+                if (cj0 + cc < c) vj = load_as_double(xr, cj0 + cc);
             }
             Xi[rr][cc] = vi;
             Xj[rr][cc] = vj;
@@ -85,21 +86,33 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const double *__restrict
 
 }  // namespace
 
-hipError_t launch_gram(const double *X, int64_t ld, int c, const Chunk *chunks, int nchunks,
-                       double *Gpart, hipStream_t stream)
+template <typename TA>
+void run_gram(const TA *X, int64_t ld, int c, const Chunk *chunks, int nchunks, double *Gpart,
+              hipStream_t stream)
 {
-    if (nchunks <= 0) return hipSuccess;
-    timing_begin("gram", stream);
-    int tm = c <= 16 ? 1 : c <= 32 ? 2 : c <= 64 ? 4 : 8;
+    const int tm = c <= 16 ? 1 : c <= 32 ? 2 : c <= 64 ? 4 : 8;
     const int tile = 16 * tm;
     const int ntile = (c + tile - 1) / tile;
     dim3 grid(nchunks, ntile * (ntile + 1) / 2);
     switch (tm) {
-    case 1: gram_kernel<1><<<grid, kThreads, 0, stream>>>(X, ld, c, chunks, Gpart); break;
-    case 2: gram_kernel<2><<<grid, kThreads, 0, stream>>>(X, ld, c, chunks, Gpart); break;
-    case 4: gram_kernel<4><<<grid, kThreads, 0, stream>>>(X, ld, c, chunks, Gpart); break;
-    default: gram_kernel<8><<<grid, kThreads, 0, stream>>>(X, ld, c, chunks, Gpart); break;
+    case 1: gram_kernel<1, TA><<<grid, kThreads, 0, stream>>>(X, ld, c, chunks, Gpart); break;
+    case 2: gram_kernel<2, TA><<<grid, kThreads, 0, stream>>>(X, ld, c, chunks, Gpart); break;
+    case 4: gram_kernel<4, TA><<<grid, kThreads, 0, stream>>>(X, ld, c, chunks, Gpart); break;
+    default: gram_kernel<8, TA><<<grid, kThreads, 0, stream>>>(X, ld, c, chunks, Gpart); break;
     }
+}
+
+hipError_t launch_gram(const void *X, int x_type, int64_t ld, int c, const Chunk *chunks,
+                       int nchunks, double *Gpart, hipStream_t stream)
+{
+    if (nchunks <= 0) return hipSuccess;
+    timing_begin("gram", stream);
+    if (x_type == kElemF32)
+        run_gram(static_cast<const float *>(X), ld, c, chunks, nchunks, Gpart, stream);
+    else if (x_type == kElemBF16)
+        run_gram(static_cast<const uint16_t *>(X), ld, c, chunks, nchunks, Gpart, stream);
+    else
+        run_gram(static_cast<const double *>(X), ld, c, chunks, nchunks, Gpart, stream);
     hipError_t e = hipGetLastError();
     timing_end("gram", stream);
     return e;

@@ -107,7 +107,8 @@ __device__ __forceinline__ void load_vk(const TileGeom &g, int c, const double *
         Vs[e] = (e < c * g.kk) ? vk[e] : 0.0;
 }
 
-__global__ __launch_bounds__(kThreads) void project_kernel(const double *__restrict__ X, int64_t ld,
+template <typename TA>
+__global__ __launch_bounds__(kThreads) void project_kernel(const TA *__restrict__ X, int64_t ld,
                                                            int c, const Chunk *__restrict__ chunks,
                                                            const double *__restrict__ Vk,
                                                            double *__restrict__ Y,
@@ -124,13 +125,14 @@ __global__ __launch_bounds__(kThreads) void project_kernel(const double *__restr
     double gacc[EPT];
 #pragma unroll
     for (int x = 0; x < EPT; ++x) gacc[x] = 0.0;
-    const double *Xc = X + ch.x_off;
+    const TA *Xc = X + ch.x_off;
     for (int r0 = 0; r0 < ch.rows; r0 += g.rb) {
         const int nr = min(g.rb, ch.rows - r0);
         __syncthreads();
         for (int e = tid; e < g.rb * g.cpad; e += kThreads) {
             const int rr = e / g.cpad, col = e % g.cpad;
-            Xs[rr * g.ldx + col] = (rr < nr && col < c) ? Xc[(int64_t)(r0 + rr) * ld + col] : 0.0;
+            Xs[rr * g.ldx + col] =
+                (rr < nr && col < c) ? load_as_double(Xc, (int64_t)(r0 + rr) * ld + col) : 0.0;
         }
         __syncthreads();
         project_tile(g, Xs, Vs, nr, Ys, Y + ch.y_off + (int64_t)r0 * ch.kk);
@@ -168,6 +170,7 @@ __device__ __forceinline__ void wave_sync()
 constexpr int kPanel = 16;
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef const double __attribute__((address_space(1))) gdouble;
+typedef const float __attribute__((address_space(1))) gfloat;
 
 template <int KQM>
 __global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const Piece *__restrict__ pieces,
@@ -196,18 +199,21 @@ __global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const P
 
     for (int r0 = 0; r0 < rows; r0 += 64) {
         const int nr = min(64, rows - r0);
-        // the lane's stack row
-        const double *xp = st.Vt;
+        // the lane's stack row: FP64 Partial-SVD rows, or store rows of the
+        // store's element type (xf = 1: float)
+        const char *xp = static_cast<const char *>(st.Vt);
+        int xf = st.f32;
         double scale = 0.0;
         if (lane < nr) {
             const int r = r0 + lane;
             const Piece &pc = pieces[ch.piece0 + r / k];
             const int j = r % k;
             if (pc.t_idx >= 0) {
-                xp = Mp + ((int64_t)pc.t_idx * k + j) * c;
+                xp = reinterpret_cast<const char *>(Mp + ((int64_t)pc.t_idx * k + j) * c);
+                xf = 0;
                 scale = 1.0;
             } else {
-                xp = st.Vt + (pc.blk * k + j) * c;
+                xp += (pc.blk * k + j) * c * (st.f32 ? sizeof(float) : sizeof(double));
                 scale = st.S[pc.blk * k + j];
             }
         }
@@ -229,7 +235,9 @@ __global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const P
                 const int row = i * 4 + lane / 16;
                 const uint32_t lo = __shfl((uint32_t)xa, row, 64);
                 const uint32_t hi = __shfl((uint32_t)(xa >> 32), row, 64);
-                v[i] = reinterpret_cast<gdouble *>(((uint64_t)hi << 32) | lo)[colc];
+                const uint64_t ra = ((uint64_t)hi << 32) | lo;
+                v[i] = __shfl(xf, row, 64) ? (double)reinterpret_cast<gfloat *>(ra)[colc]
+                                           : reinterpret_cast<gdouble *>(ra)[colc];
             }
             // B fragments: B(s, j) = V_k(a0 + 4 t + s, 16 cb + j), zero outside c x kq
             double bf[NCB][4];
@@ -306,7 +314,8 @@ __global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const P
     }
 }
 
-__global__ __launch_bounds__(kThreads) void utransform_kernel(double *__restrict__ U, int k,
+template <typename TU>
+__global__ __launch_bounds__(kThreads) void utransform_kernel(const double *Y, TU *U, int k,
                                                               const Chunk *__restrict__ chunks,
                                                               const double *__restrict__ F)
 {
@@ -317,36 +326,51 @@ __global__ __launch_bounds__(kThreads) void utransform_kernel(double *__restrict
     const int tid = threadIdx.x;
     const double *Fp = F + (int64_t)ch.prob * kSlotK;
     for (int e = tid; e < k * k; e += kThreads) Fs[e] = Fp[e];
-    double *Uc = U + ch.y_off;
+    const double *Yc = Y + ch.y_off;       // Y and U may be the same array (FP64 store)
+    TU *Uc = U + ch.y_off;
     for (int r0 = 0; r0 < ch.rows; r0 += RB) {
         const int nr = min(RB, ch.rows - r0);
         __syncthreads();
-        for (int e = tid; e < nr * k; e += kThreads) Us[e] = Uc[(int64_t)r0 * k + e];
+        for (int e = tid; e < nr * k; e += kThreads) Us[e] = Yc[(int64_t)r0 * k + e];
         __syncthreads();
         for (int e = tid; e < nr * k; e += kThreads) {
             const int rr = e / k, j = e % k;
             double s = 0.0;
             for (int l = 0; l < k; ++l) s = fma(Us[rr * k + l], Fs[l * k + j], s);
-            Uc[(int64_t)r0 * k + e] = s;
+            Uc[(int64_t)r0 * k + e] = (TU)s;
         }
     }
 }
 
 }  // namespace
 
-hipError_t launch_project(const double *X, int64_t ld, int c, const Chunk *chunks, int nchunks,
-                          int kk, const double *Vk, double *Y, double *GYpart, hipStream_t stream)
+template <typename TA>
+hipError_t run_project(const TA *X, int64_t ld, int c, const Chunk *chunks, int nchunks, int kk,
+                       const double *Vk, double *Y, double *GYpart, hipStream_t stream)
 {
-    if (nchunks <= 0) return hipSuccess;
     const size_t lds = project_lds_bytes(c, kk);
     static size_t cur = 0;
-    {
-        hipError_t e = ensure_lds((const void *)project_kernel, lds, cur);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = ensure_lds((const void *)project_kernel<TA>, lds, cur);
+    if (e != hipSuccess) return e;
+    project_kernel<TA><<<nchunks, kThreads, lds, stream>>>(X, ld, c, chunks, Vk, Y, GYpart);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const void *X, int x_type, int64_t ld, int c, const Chunk *chunks,
+                          int nchunks, int kk, const double *Vk, double *Y, double *GYpart,
+                          hipStream_t stream)
+{
+    if (nchunks <= 0) return hipSuccess;
     timing_begin("project", stream);
-    project_kernel<<<nchunks, kThreads, lds, stream>>>(X, ld, c, chunks, Vk, Y, GYpart);
-    hipError_t e = hipGetLastError();
+    hipError_t e;
+    if (x_type == kElemF32)
+        e = run_project(static_cast<const float *>(X), ld, c, chunks, nchunks, kk, Vk, Y, GYpart, stream);
+    else if (x_type == kElemBF16)
+        e = run_project(static_cast<const uint16_t *>(X), ld, c, chunks, nchunks, kk, Vk, Y, GYpart,
+                        stream);
+    else
+        e = run_project(static_cast<const double *>(X), ld, c, chunks, nchunks, kk, Vk, Y, GYpart,
+                        stream);
     timing_end("project", stream);
     return e;
 }
@@ -384,12 +408,17 @@ hipError_t launch_stack_project(StoreView st, const Piece *pieces, const double 
     return e;
 }
 
-hipError_t launch_utransform(double *U, int k, const Chunk *chunks, int nchunks, const double *F,
-                             hipStream_t stream)
+hipError_t launch_utransform(const double *Y, void *U, int u_f32, int k, const Chunk *chunks,
+                             int nchunks, const double *F, hipStream_t stream)
 {
     if (nchunks <= 0) return hipSuccess;
     timing_begin("utransform", stream);
-    utransform_kernel<<<nchunks, kThreads, 0, stream>>>(U, k, chunks, F);
+    if (u_f32)
+        utransform_kernel<float><<<nchunks, kThreads, 0, stream>>>(Y, static_cast<float *>(U), k,
+                                                                    chunks, F);
+    else
+        utransform_kernel<double><<<nchunks, kThreads, 0, stream>>>(Y, static_cast<double *>(U), k,
+                                                                     chunks, F);
     hipError_t e = hipGetLastError();
     timing_end("utransform", stream);
     return e;

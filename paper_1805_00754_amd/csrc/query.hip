@@ -142,24 +142,27 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void *p, int bytes)
     return __builtin_amdgcn_make_buffer_rsrc(q, 0, __builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 
-__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int off)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-
-// The same load marked volatile (aux bit 31, a compiler-only flag): the
-// compiler keeps it where it is written instead of sinking it next to its use.
-__device__ __forceinline__ double buf_load_pinned(__amdgpu_buffer_rsrc_t r, int off)
-{
-    return __builtin_bit_cast(double,
-                              __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, (int)0x80000000u));
-}
-
 // aux 2: nontemporal; the output is written once and not read back here
 __device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, int off, double v)
 {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v),
                                           r, off, 0, 2);
+}
+__device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, int off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 2);
+}
+
+// Element e of a buffer of TU, as double; the pinned form is volatile (aux bit
+// 31) so that the compiler keeps a prefetch where it is written.
+template <typename TU, bool PINNED>
+__device__ __forceinline__ double buf_elem(__amdgpu_buffer_rsrc_t r, int e)
+{
+    constexpr int aux = PINNED ? (int)0x80000000u : 0;
+    if constexpr (sizeof(TU) == 8)
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, e * 8, 0, aux));
+    else
+        return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, e * 4, 0, aux));
 }
 
 // One wave per piece, rows in tiles of 64.  The product of a tile with C_i
@@ -191,11 +194,11 @@ constexpr int kXcds = 8;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <int KM, bool CONTIG>
+template <int KM, bool CONTIG, typename TU>
 __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, const Piece *__restrict__ pieces,
                                                               const int32_t *__restrict__ perm, int npieces,
                                                               const double *__restrict__ C,
-                                                              double *__restrict__ Uout)
+                                                              TU *__restrict__ Uout)
 {
     constexpr int KS = KM / 4;                     // MFMA steps over l
     constexpr int NCB = (KM + 15) / 16;            // 16-column blocks (k_q <= k <= KM)
@@ -217,24 +220,24 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
             const int j = 16 * cb + lane % 16, l = 4 * t + lane / 16;
             bf[cb][t] = j < kq ? Cp[j * KM + l] : 0.0;
         }
-    const double *Ub = st.U + (pc.blk * st.b + pc.r0) * k;
-    double *out = Uout + pc.out_off;
+    const TU *Ub = static_cast<const TU *>(st.U) + (pc.blk * st.b + pc.r0) * k;
+    TU *out = Uout + pc.out_off;
     const int64_t ldu = pc.ldu;
     const int nrows = pc.r1 - pc.r0;
     const int ntiles = (nrows + kProdRows - 1) / kProdRows;
     auto urange = [&](int row0) {
         const int nr = max(0, min(kProdRows, nrows - row0));
-        return buf(Ub + (int64_t)row0 * k, nr * k * (int)sizeof(double));
+        return buf(Ub + (int64_t)row0 * k, nr * k * (int)sizeof(TU));
     };
 
     double pre[KM];
     {
         const __amdgpu_buffer_rsrc_t r = urange(0);
 #pragma unroll
-        for (int i = 0; i < KM; ++i) pre[i] = buf_load(r, (lane + i * kProdRows) * 8);
+        for (int i = 0; i < KM; ++i) pre[i] = buf_elem<TU, false>(r, lane + i * kProdRows);
         const __amdgpu_buffer_rsrc_t none = buf(out, 0);
 #pragma unroll
-        for (int i = 0; i < KM; ++i) buf_store_nt(none, (lane + i * kProdRows) * 8, 0.0);
+        for (int i = 0; i < KM; ++i) buf_store_nt(none, (lane + i * kProdRows) * (int)sizeof(TU), (TU)0);
     }
     for (int t = 0; t < ntiles; ++t) {
         const int row0 = t * kProdRows;
@@ -245,7 +248,7 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
         {
             const __amdgpu_buffer_rsrc_t r = urange(row0 + kProdRows);   // empty after the last
 #pragma unroll
-            for (int i = 0; i < KM; ++i) pre[i] = buf_load_pinned(r, (lane + i * kProdRows) * 8);
+            for (int i = 0; i < KM; ++i) pre[i] = buf_elem<TU, true>(r, lane + i * kProdRows);
         }
         wave_sync();
         v4d acc[4][NCB];
@@ -275,15 +278,15 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
                 }
         wave_sync();
         if (CONTIG) {                              // the tile is contiguous in the output
-            const __amdgpu_buffer_rsrc_t r = buf(out + (int64_t)row0 * kq, nr * kq * (int)sizeof(double));
+            const __amdgpu_buffer_rsrc_t r = buf(out + (int64_t)row0 * kq, nr * kq * (int)sizeof(TU));
 #pragma unroll
             for (int i = 0; i < KM; ++i)
-                buf_store_nt(r, (lane + i * kProdRows) * 8, tile[lane + i * kProdRows]);
+                buf_store_nt(r, (lane + i * kProdRows) * (int)sizeof(TU), (TU)tile[lane + i * kProdRows]);
         } else {
             const int n = nr * kq;
             for (int e = lane; e < n; e += kProdRows) {
                 const int rr = e / kq;
-                out[(int64_t)(row0 + rr) * ldu + (e - rr * kq)] = tile[e];
+                out[(int64_t)(row0 + rr) * ldu + (e - rr * kq)] = (TU)tile[e];
             }
         }
     }
@@ -321,16 +324,17 @@ hipError_t launch_coef(int k, int kq_max, const Piece *pieces, const StackChunk 
     return e;
 }
 
-template <int KM>
+template <int KM, typename TU>
 hipError_t run_blockprod(StoreView st, const Piece *pieces, const int32_t *perm, int npieces,
-                         const double *C, double *U, bool contiguous, hipStream_t stream)
+                         const double *C, void *U, bool contiguous, hipStream_t stream)
 {
     const size_t lds = (size_t)kProdRows * KM * sizeof(double);
     const unsigned grid = (unsigned)(kXcds * ((npieces + kXcds - 1) / kXcds));
+    TU *out = static_cast<TU *>(U);
     if (contiguous)
-        blockprod_kernel<KM, true><<<grid, kProdRows, lds, stream>>>(st, pieces, perm, npieces, C, U);
+        blockprod_kernel<KM, true, TU><<<grid, kProdRows, lds, stream>>>(st, pieces, perm, npieces, C, out);
     else
-        blockprod_kernel<KM, false><<<grid, kProdRows, lds, stream>>>(st, pieces, perm, npieces, C, U);
+        blockprod_kernel<KM, false, TU><<<grid, kProdRows, lds, stream>>>(st, pieces, perm, npieces, C, out);
     return hipGetLastError();
 }
 
@@ -348,7 +352,7 @@ hipError_t launch_order_pieces(const Piece *pieces, int npieces, int64_t nb, con
 }
 
 hipError_t launch_blockprod(StoreView st, const Piece *pieces, const int32_t *perm, int npieces,
-                            const double *C, double *U, bool contiguous, hipStream_t stream)
+                            const double *C, void *U, bool contiguous, hipStream_t stream)
 {
     if (npieces <= 0) return hipSuccess;
     if (st.k < 1 || st.k > kMaxK) return hipErrorInvalidValue;
@@ -356,7 +360,10 @@ hipError_t launch_blockprod(StoreView st, const Piece *pieces, const int32_t *pe
     hipError_t e;
     switch (prod_ld(st.k)) {
 #define ZS_PROD_CASE(KM) \
-    case KM: e = run_blockprod<KM>(st, pieces, perm, npieces, C, U, contiguous, stream); break;
+    case KM:                                                                                    \
+        e = st.f32 ? run_blockprod<KM, float>(st, pieces, perm, npieces, C, U, contiguous, stream)  \
+                   : run_blockprod<KM, double>(st, pieces, perm, npieces, C, U, contiguous, stream); \
+        break;
         ZS_PROD_CASE(4) ZS_PROD_CASE(8) ZS_PROD_CASE(12) ZS_PROD_CASE(16) ZS_PROD_CASE(20)
         ZS_PROD_CASE(24) ZS_PROD_CASE(28) ZS_PROD_CASE(32) ZS_PROD_CASE(48) ZS_PROD_CASE(64)
 #undef ZS_PROD_CASE

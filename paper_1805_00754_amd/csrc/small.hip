@@ -195,7 +195,10 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *_
         const int a = e / kk, pp = e % kk;
         const int j = inv[pp];
         const double v = keep[j] ? flip[j] * Vn[a * kk + j] : 0.0;
-        P.v_dst[a * P.v_rs + pp * P.v_cs] = v;
+        if (P.v_f32)
+            static_cast<float *>(P.v_dst)[a * P.v_rs + pp * P.v_cs] = (float)v;
+        else
+            static_cast<double *>(P.v_dst)[a * P.v_rs + pp * P.v_cs] = v;
     }
     double *Fp = F + (int64_t)blockIdx.x * kSlotK;
     for (int e = tid; e < kk * kk; e += kThreads) {
@@ -214,6 +217,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *_
     }
 }
 
+template <typename TU>
 __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
                                                            const Piece *__restrict__ pieces,
                                                            const int32_t *__restrict__ pidx,
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
     const Piece pc = pieces[pidx[blockIdx.x]];
     const int c = (int)st.c;
     const int tid = threadIdx.x;
-    const double *Ub = st.U + (pc.blk * st.b + pc.r0) * k;
+    const TU *Ub = static_cast<const TU *>(st.U) + (pc.blk * st.b + pc.r0) * k;
     const int m = pc.r1 - pc.r0;
     for (int j = tid; j < k; j += kThreads) sblk[j] = st.S[pc.blk * k + j];
 
@@ -255,7 +259,7 @@ __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
             __syncthreads();
             for (int e = tid; e < nr * k; e += kThreads) {
                 const int a = e % k;
-                Us[e] = Ub[(int64_t)r0 * k + e] * sblk[a];
+                Us[e] = (double)Ub[(int64_t)r0 * k + e] * sblk[a];
             }
             __syncthreads();
             const double *R = Us;
@@ -316,12 +320,12 @@ __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
     for (int j = 0; j < k; ++j) smax = fmax(smax, sig[j]);
 
     // stack rows: Mp[j] = sigma~_j (V_(i) v~_j)^T = sigma~_j sum_l v~_lj V_(i)^T[l]
-    const double *Vt = st.Vt + pc.blk * k * st.c;
+    const TU *Vt = static_cast<const TU *>(st.Vt) + pc.blk * k * st.c;
     double *Mrows = Mp + (int64_t)pc.t_idx * k * c;
     for (int e = tid; e < k * c; e += kThreads) {
         const int j = e / c, col = e % c;
         double s = 0.0;
-        for (int l = 0; l < k; ++l) s = fma(G[l * ld + j], Vt[(int64_t)l * c + col], s);
+        for (int l = 0; l < k; ++l) s = fma(G[l * ld + j], (double)Vt[(int64_t)l * c + col], s);
         Mrows[e] = sig[j] * s;
     }
     // T = Sigma_(i) V~ Sigma~^+  (k x k, row-major)
@@ -362,12 +366,18 @@ hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx
     if (npartial <= 0) return hipSuccess;
     timing_begin("partial", stream);
     const size_t lds = (size_t)(3 * st.k * (st.k + 1) + 2 * 32 * st.k) * sizeof(double);
-    static size_t cur = 0;
+    static size_t cur_f = 0, cur_d = 0;   // one limit per instantiation
     {
-        hipError_t e = ensure_lds((const void *)partial_kernel, lds, cur);
+        hipError_t e = st.f32 ? ensure_lds((const void *)partial_kernel<float>, lds, cur_f)
+                              : ensure_lds((const void *)partial_kernel<double>, lds, cur_d);
         if (e != hipSuccess) return e;
     }
-    partial_kernel<<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T, rank_tol, conv_flag);
+    if (st.f32)
+        partial_kernel<float><<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T, rank_tol,
+                                                                   conv_flag);
+    else
+        partial_kernel<double><<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T, rank_tol,
+                                                                    conv_flag);
     hipError_t e = hipGetLastError();
     timing_end("partial", stream);
     return e;

@@ -14,6 +14,7 @@ namespace zs {
 namespace {
 
 // leaf i: sum_j sigma_ij^2 v_ij v_ij^T  (zero beyond the last block)
+template <typename TU>
 __global__ __launch_bounds__(kThreads) void leaf_gram_kernel(StoreView st, int64_t nleaves,
                                                              double *__restrict__ tree,
                                                              int64_t leaf0)
@@ -28,8 +29,8 @@ __global__ __launch_bounds__(kThreads) void leaf_gram_kernel(StoreView st, int64
         for (int e = tid; e < c * c; e += kThreads) G[e] = 0.0;
         return;
     }
-    const double *Vt = st.Vt + i * k * c;
-    for (int e = tid; e < k * c; e += kThreads) Ws[e] = Vt[e] * st.S[i * k + e / c];
+    const TU *Vt = static_cast<const TU *>(st.Vt) + i * k * c;
+    for (int e = tid; e < k * c; e += kThreads) Ws[e] = (double)Vt[e] * st.S[i * k + e / c];
     __syncthreads();
     for (int e = tid; e < c * c; e += kThreads) {
         const int a = e / c, b = e % c;
@@ -61,13 +62,17 @@ hipError_t launch_leaf_gram(StoreView st, int64_t nleaves, double *tree, int64_t
 {
     if (nleaves <= 0) return hipSuccess;
     const size_t lds = (size_t)st.k * st.c * sizeof(double);
-    static size_t cur = 0;
+    static size_t cur_f = 0, cur_d = 0;   // one limit per instantiation
     {
-        hipError_t e = ensure_lds((const void *)leaf_gram_kernel, lds, cur);
+        hipError_t e = st.f32 ? ensure_lds((const void *)leaf_gram_kernel<float>, lds, cur_f)
+                              : ensure_lds((const void *)leaf_gram_kernel<double>, lds, cur_d);
         if (e != hipSuccess) return e;
     }
     timing_begin("leaf_gram", stream);
-    leaf_gram_kernel<<<(unsigned)nleaves, kThreads, lds, stream>>>(st, nleaves, tree, leaf0);
+    if (st.f32)
+        leaf_gram_kernel<float><<<(unsigned)nleaves, kThreads, lds, stream>>>(st, nleaves, tree, leaf0);
+    else
+        leaf_gram_kernel<double><<<(unsigned)nleaves, kThreads, lds, stream>>>(st, nleaves, tree, leaf0);
     hipError_t e = hipGetLastError();
     timing_end("leaf_gram", stream);
     return e;

@@ -13,6 +13,7 @@ constexpr int kMaxK = 64;           // largest stored / requested rank
 constexpr int kSlotK = kMaxK * kMaxK;  // stride of a k x k slot (G_Y partials, F factors)
 constexpr int kMaxSweeps = 40;      // Jacobi sweep cap
 constexpr double kRankTolFP64 = 1e-11;  // numerical-rank threshold relative to sigma_1
+constexpr double kRankTolF32 = 1e-5;    // the same for stores kept in FP32
 
 // A run of rows of a tall-skinny matrix X (Gram, projection kernels).
 struct Chunk {
@@ -41,8 +42,8 @@ struct Prob {
     int32_t m0, nm;   // k x c row blocks whose Gram is added: msrc[m0 .. m0+nm)
     int32_t y0, ny;   // G_Y partial-sum slots
     int32_t kk;       // triplets wanted
-    int32_t pad;
-    double *v_dst;    // V(a, j) written at v_dst[a * v_rs + j * v_cs]
+    int32_t v_f32;    // 1: v_dst holds float
+    void *v_dst;      // V(a, j) written at v_dst[a * v_rs + j * v_cs]
     int64_t v_rs, v_cs;
     double *s_dst;    // kk singular values
     int32_t *k_dst;   // numerical rank kept
@@ -78,14 +79,28 @@ struct QueryDesc {
     int32_t first_partial;  // 1 if the first piece goes through the Partial-SVD
 };
 
-// Device-side view of a store.
+// Device-side view of a store.  U and Vt hold double in FP64 mode and float
+// in the FP32 / BF16 modes (f32 = 1).
 struct StoreView {
-    const double *U;  // t x k, rows of block i hold U_(i)
-    const double *Vt; // nb x k x c, block i holds V_(i)^T
+    const void *U;    // t x k, rows of block i hold U_(i)
+    const void *Vt;   // nb x k x c, block i holds V_(i)^T
     const double *S;  // nb x k
     int64_t t, c, b;
     int32_t k;
+    int32_t f32;
 };
+
+// Element types the storage phase reads A in (zs_dtype order).
+enum ElemType { kElemF64 = 0, kElemF32 = 1, kElemBF16 = 2 };
+
+// Loads element i of an array of type T as double (bf16 is the upper half of
+// an IEEE single).
+__device__ __forceinline__ double load_as_double(const double *p, int64_t i) { return p[i]; }
+__device__ __forceinline__ double load_as_double(const float *p, int64_t i) { return (double)p[i]; }
+__device__ __forceinline__ double load_as_double(const uint16_t *p, int64_t i)
+{
+    return (double)__uint_as_float((uint32_t)p[i] << 16);
+}
 
 // Row stride of a piece's coefficient matrix C_i (stored transposed, k_q rows
 // of prod_ld(k) values, zero beyond k): k rounded up to a size blockprod is
@@ -98,22 +113,25 @@ __host__ __device__ inline int prod_ld(int k)
 
 // ---------------------------------------------------------------- launches
 // All launches are asynchronous on `stream` and return the launch status.
-hipError_t launch_gram(const double *X, int64_t ld, int c, const Chunk *chunks, int nchunks,
-                       double *Gpart, hipStream_t stream);
+hipError_t launch_gram(const void *X, int x_type, int64_t ld, int c, const Chunk *chunks,
+                       int nchunks, double *Gpart, hipStream_t stream);
 hipError_t launch_eig(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
                       const double *const *msrc, double *Vk, int *conv_flag, hipStream_t stream);
 hipError_t launch_eig_tri(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
                           const double *const *msrc, double *Vk, hipStream_t stream);
-hipError_t launch_project(const double *X, int64_t ld, int c, const Chunk *chunks, int nchunks,
-                          int kk, const double *Vk, double *Y, double *GYpart, hipStream_t stream);
+hipError_t launch_project(const void *X, int x_type, int64_t ld, int c, const Chunk *chunks,
+                          int nchunks, int kk, const double *Vk, double *Y, double *GYpart,
+                          hipStream_t stream);
 hipError_t launch_stack_project(StoreView st, const Piece *pieces, const double *Mp,
                                 const StackChunk *chunks, int nchunks, int kq_max,
                                 const double *Vk, double *Y, double *GYpart, hipStream_t stream);
 hipError_t launch_finalize(int c, const Prob *probs, int nprob, int kk_max, const double *GYpart,
                            const double *Vk, double *F, double rank_tol, int *conv_flag,
                            hipStream_t stream);
-hipError_t launch_utransform(double *U, int k, const Chunk *chunks, int nchunks, const double *F,
-                             hipStream_t stream);
+// U <- Y F per chunk; Y is FP64, U has the store's element type (may alias Y
+// in FP64 mode).
+hipError_t launch_utransform(const double *Y, void *U, int u_f32, int k, const Chunk *chunks,
+                             int nchunks, const double *F, hipStream_t stream);
 hipError_t launch_leaf_gram(StoreView st, int64_t nleaves, double *tree, int64_t leaf0,
                             hipStream_t stream);
 hipError_t launch_tree_level(int c, double *tree, int64_t node0, int64_t nnodes,
@@ -132,7 +150,7 @@ hipError_t launch_order_pieces(const Piece *pieces, int npieces, int64_t nb, con
                                int32_t *bcount, int32_t *perm, hipStream_t stream);
 // contiguous: every query's U has leading dimension k_q (rows back to back)
 hipError_t launch_blockprod(StoreView st, const Piece *pieces, const int32_t *perm, int npieces,
-                            const double *C, double *U, bool contiguous, hipStream_t stream);
+                            const double *C, void *U, bool contiguous, hipStream_t stream);
 
 // Raises a kernel's dynamic-LDS limit to `bytes` if it is below (the limit
 // only grows; `cur` caches the value set).  Clears the error state on failure.

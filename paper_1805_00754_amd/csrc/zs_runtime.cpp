@@ -111,7 +111,13 @@ struct zs_store {
     int32_t k = 0;
     zs_mode mode = ZS_MODE_FP64;
     int device = 0;
-    double *U = nullptr, *Vt = nullptr, *S = nullptr;
+    void *U = nullptr, *Vt = nullptr;   // double in FP64 mode, float otherwise
+    double *S = nullptr;
+    int f32 = 0;                        // U and Vt hold float
+    size_t esize() const { return f32 ? sizeof(float) : sizeof(double); }
+    // numerical-rank threshold relative to sigma_1: FP32 storage rounds the
+    // factors at about 1e-7, so a tighter cut would count rounding as rank
+    double rank_tol() const { return f32 ? kRankTolF32 : kRankTolFP64; }
     int32_t *kvec = nullptr;
     double *tree = nullptr;       // Gram tree: 2 * n2 nodes of c x c (node 0 unused)
     int64_t n2 = 1;               // leaves of the Gram tree (power of two >= nb)
@@ -122,7 +128,7 @@ struct zs_store {
     StoreView view() const
     {
         StoreView v;
-        v.U = U; v.Vt = Vt; v.S = S; v.t = t; v.c = c; v.b = b; v.k = k;
+        v.U = U; v.Vt = Vt; v.S = S; v.t = t; v.c = c; v.b = b; v.k = k; v.f32 = f32;
         return v;
     }
     int64_t block_rows(int64_t i) const { return std::min(b, t - i * b); }
@@ -203,8 +209,8 @@ struct Blob {
 };
 
 zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t *te,
-                     const int32_t *kq, double *U, const int64_t *u_off, const int64_t *ldu,
-                     double *S, const int64_t *s_off, double *V, const int64_t *v_off,
+                     const int32_t *kq, void *U, const int64_t *u_off, const int64_t *ldu,
+                     double *S, const int64_t *s_off, void *V, const int64_t *v_off,
                      const int64_t *ldv, int32_t *k_out, hipStream_t stream)
 {
     const int64_t c = st->c, b = st->b;
@@ -289,7 +295,8 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
         }
         pr.ny = slot - pr.y0;
         pr.kk = kq[q];
-        pr.v_dst = V + v_off[q];
+        pr.v_dst = static_cast<char *>(V) + v_off[q] * (int64_t)st->esize();
+        pr.v_f32 = st->f32;
         pr.v_rs = ldv[q];
         pr.v_cs = 1;
         pr.s_dst = S + s_off[q];
@@ -358,14 +365,14 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
     const StoreView sv = st->view();
     // ---- launches ---------------------------------------------------------------
     HIP_TRY(launch_expand_pieces(sv, d_qds, nq, max_np, w->P.as<Piece>(), stream));
-    HIP_TRY(launch_partial(sv, d_pieces, d_pidx, npartial, Mp, w->T.as<double>(), kRankTolFP64,
+    HIP_TRY(launch_partial(sv, d_pieces, d_pidx, npartial, Mp, w->T.as<double>(), st->rank_tol(),
                            st->conv, stream));
     HIP_TRY(first_stage_eig((int)c, k, d_probs, nq, d_gsrc, d_msrc, w->Vk.as<double>(),
                             st->conv, stream));
     HIP_TRY(launch_stack_project(sv, d_pieces, Mp, d_chunks, nchunks, kq_max, w->Vk.as<double>(),
                                  w->Y.as<double>(), w->GY.as<double>(), stream));
     HIP_TRY(launch_finalize((int)c, d_probs, nq, kq_max, w->GY.as<double>(), w->Vk.as<double>(),
-                            w->F.as<double>(), kRankTolFP64, st->conv, stream));
+                            w->F.as<double>(), st->rank_tol(), st->conv, stream));
     HIP_TRY(launch_coef(k, kq_max, d_pieces, d_chunks, nchunks, w->Y.as<double>(),
                         w->F.as<double>(), w->T.as<double>(), w->C.as<double>(), stream));
     bool contiguous = true;
@@ -409,12 +416,15 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
     if (k < 1 || k > c) return fail(ZS_EINVAL, "k = %d outside [1, c = %lld]", k, (long long)c);
     if (c > ZS_MAX_C) return fail(ZS_EUNSUPPORTED, "c = %lld > %d", (long long)c, ZS_MAX_C);
     if (k > ZS_MAX_K) return fail(ZS_EUNSUPPORTED, "k = %d > %d", k, ZS_MAX_K);
-    if (mode != ZS_MODE_FP64 || a_type != ZS_F64)
-        return fail(ZS_EUNSUPPORTED, "only FP64 input in FP64 mode is built");
+    if (a_type != ZS_F64 && a_type != ZS_F32 && a_type != ZS_BF16)
+        return fail(ZS_EINVAL, "a_type %d is not a zs_dtype", (int)a_type);
+    if (mode != ZS_MODE_FP64 && mode != ZS_MODE_FP32 && mode != ZS_MODE_BF16)
+        return fail(ZS_EINVAL, "mode %d is not a zs_mode", (int)mode);
     if (b > (int64_t)1 << 30) return fail(ZS_EINVAL, "b too large");
 
     zs_store *st = new zs_store();
     st->t = t; st->c = c; st->b = b; st->k = k; st->mode = mode;
+    st->f32 = mode == ZS_MODE_FP64 ? 0 : 1;
     st->nb = (t + b - 1) / b;
     const int64_t nb = st->nb;
     auto cleanup = [&](zs_status s) {
@@ -429,8 +439,8 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
             return cleanup(fail(e_ == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "%s: %s", \
                                 #expr, hipGetErrorString(e_)));                             \
     } while (0)
-    ST_TRY(hipMalloc(&st->U, sizeof(double) * t * k));
-    ST_TRY(hipMalloc(&st->Vt, sizeof(double) * nb * k * c));
+    ST_TRY(hipMalloc(&st->U, st->esize() * t * k));
+    ST_TRY(hipMalloc(&st->Vt, st->esize() * nb * k * c));
     ST_TRY(hipMalloc(&st->S, sizeof(double) * nb * k));
     ST_TRY(hipMalloc(&st->kvec, sizeof(int32_t) * nb));
     while (st->n2 < nb) st->n2 *= 2;
@@ -461,7 +471,8 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
         pr.ng = slot - pr.g0;
         pr.ny = slot - pr.y0;
         pr.kk = k;
-        pr.v_dst = st->Vt + i * k * c;      // V_(i)^T: element (a, j) at j * c + a
+        pr.v_dst = static_cast<char *>(st->Vt) + i * k * c * (int64_t)st->esize();  // V_(i)^T
+        pr.v_f32 = st->f32;                 // element (a, j) at j * c + a
         pr.v_rs = 1;
         pr.v_cs = c;
         pr.s_dst = st->S + i * k;
@@ -469,9 +480,9 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
         probs[i] = pr;
     }
     const int nchunks = (int)chunks.size();
-    DevBuf Gpart, Vk, GY, F, desc;
+    DevBuf Gpart, Vk, GY, F, Ysc, desc;
     auto release = [&]() {
-        Gpart.release(); Vk.release(); GY.release(); F.release(); desc.release();
+        Gpart.release(); Vk.release(); GY.release(); F.release(); Ysc.release(); desc.release();
     };
 #define ST_TRY2(expr)                                                                       \
     do {                                                                                    \
@@ -486,6 +497,9 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
     ST_TRY2(Vk.ensure(sizeof(double) * (size_t)nb * c * kMaxK));
     ST_TRY2(GY.ensure(sizeof(double) * (size_t)nchunks * kSlotK));
     ST_TRY2(F.ensure(sizeof(double) * (size_t)nb * kSlotK));
+    // Y = A V_k in FP64: in place in U for an FP64 store, in scratch otherwise
+    if (st->f32) ST_TRY2(Ysc.ensure(sizeof(double) * (size_t)t * k));
+    double *Y = st->f32 ? Ysc.as<double>() : static_cast<double *>(st->U);
     std::vector<const double *> gsrc(nchunks);
     for (int s2 = 0; s2 < nchunks; ++s2) gsrc[s2] = Gpart.as<double>() + (int64_t)s2 * c * c;
     Blob blob;
@@ -496,15 +510,15 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
     const Chunk *d_chunks = (const Chunk *)(desc.as<char>() + o_chunks);
     const Prob *d_probs = (const Prob *)(desc.as<char>() + o_probs);
     const double *const *d_gsrc = (const double *const *)(desc.as<char>() + o_gsrc);
-    const double *Ad = static_cast<const double *>(A);
-    ST_TRY2(launch_gram(Ad, lda, (int)c, d_chunks, nchunks, Gpart.as<double>(), stream));
+    const int x_type = a_type == ZS_F32 ? kElemF32 : a_type == ZS_BF16 ? kElemBF16 : kElemF64;
+    ST_TRY2(launch_gram(A, x_type, lda, (int)c, d_chunks, nchunks, Gpart.as<double>(), stream));
     ST_TRY2(first_stage_eig((int)c, k, d_probs, (int)nb, d_gsrc, nullptr, Vk.as<double>(),
                             st->conv, stream));
-    ST_TRY2(launch_project(Ad, lda, (int)c, d_chunks, nchunks, k, Vk.as<double>(), st->U,
+    ST_TRY2(launch_project(A, x_type, lda, (int)c, d_chunks, nchunks, k, Vk.as<double>(), Y,
                            GY.as<double>(), stream));
     ST_TRY2(launch_finalize((int)c, d_probs, (int)nb, k, GY.as<double>(), Vk.as<double>(),
-                            F.as<double>(), kRankTolFP64, st->conv, stream));
-    ST_TRY2(launch_utransform(st->U, k, d_chunks, nchunks, F.as<double>(), stream));
+                            F.as<double>(), st->rank_tol(), st->conv, stream));
+    ST_TRY2(launch_utransform(Y, st->U, st->f32, k, d_chunks, nchunks, F.as<double>(), stream));
     // Gram tree over the stored blocks: leaves, then one launch per level.
     ST_TRY2(launch_leaf_gram(st->view(), st->n2, st->tree, st->n2, stream));
     for (int64_t lev = st->n2 / 2; lev >= 1; lev /= 2)
@@ -535,8 +549,8 @@ zs_status zs_query(const zs_store *cst, int64_t t_s, int64_t t_e, int32_t k_q, v
     if (ldu < k_q || ldv < k_q) return fail(ZS_EINVAL, "ldu/ldv < k_q");
     zs_store *st = const_cast<zs_store *>(cst);
     const int64_t zero = 0;
-    return query_impl(st, 1, &t_s, &t_e, &k_q, static_cast<double *>(U), &zero, &ldu, S, &zero,
-                      static_cast<double *>(V), &zero, &ldv, k_out, stream);
+    return query_impl(st, 1, &t_s, &t_e, &k_q, U, &zero, &ldu, S, &zero, V, &zero, &ldv, k_out,
+                      stream);
 }
 
 zs_status zs_query_batch(const zs_store *cst, int32_t nq, const int64_t *t_s, const int64_t *t_e,
@@ -558,8 +572,8 @@ zs_status zs_query_batch(const zs_store *cst, int32_t nq, const int64_t *t_s, co
     std::vector<int64_t> ld(nq);
     for (int32_t q = 0; q < nq; ++q) ld[q] = k_q[q];
     zs_store *st = const_cast<zs_store *>(cst);
-    return query_impl(st, nq, t_s, t_e, k_q, static_cast<double *>(U), u_off, ld.data(), S, s_off,
-                      static_cast<double *>(V), v_off, ld.data(), k_out, stream);
+    return query_impl(st, nq, t_s, t_e, k_q, U, u_off, ld.data(), S, s_off, V, v_off, ld.data(),
+                      k_out, stream);
 }
 
 void zs_store_free(zs_store *st)
@@ -582,8 +596,8 @@ void zs_store_free(zs_store *st)
 int64_t zs_store_bytes(const zs_store *st)
 {
     if (!st) return 0;
-    return (int64_t)sizeof(double) * (st->t * st->k + st->nb * st->k * st->c + st->nb * st->k +
-                                      2 * st->n2 * st->c * st->c) +
+    return (int64_t)st->esize() * (st->t * st->k + st->nb * st->k * st->c) +
+           (int64_t)sizeof(double) * (st->nb * st->k + 2 * st->n2 * st->c * st->c) +
            (int64_t)sizeof(int32_t) * st->nb;
 }
 
@@ -608,14 +622,15 @@ zs_status zs_store_get_block(const zs_store *st, int64_t i, void *U, double *S, 
                                           (long long)st->nb);
     if (!U || !S || !V || !k_i) return fail(ZS_EINVAL, "null output pointer");
     const int64_t rows = st->block_rows(i), k = st->k, c = st->c;
-    HIP_TRY(hipMemcpyAsync(U, st->U + i * st->b * k, sizeof(double) * rows * k,
-                           hipMemcpyDeviceToDevice, stream));
+    const size_t es = st->esize();
+    const char *Us = static_cast<const char *>(st->U), *Vs = static_cast<const char *>(st->Vt);
+    HIP_TRY(hipMemcpyAsync(U, Us + i * st->b * k * es, es * rows * k, hipMemcpyDeviceToDevice,
+                           stream));
     HIP_TRY(hipMemcpyAsync(S, st->S + i * k, sizeof(double) * k, hipMemcpyDeviceToDevice, stream));
     // V_(i) = (V_(i)^T)^T: c x k from the stored k x c rows.
     for (int64_t j = 0; j < k; ++j)
-        HIP_TRY(hipMemcpy2DAsync(static_cast<double *>(V) + j, sizeof(double) * k,
-                                 st->Vt + (i * k + j) * c, sizeof(double), sizeof(double), c,
-                                 hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(hipMemcpy2DAsync(static_cast<char *>(V) + j * es, es * k, Vs + (i * k + j) * c * es,
+                                 es, es, c, hipMemcpyDeviceToDevice, stream));
     HIP_TRY(hipMemcpyAsync(k_i, st->kvec + i, sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
     return ZS_OK;
 }

@@ -219,6 +219,20 @@ def zs_query_batch(st: Store, t_s, t_e, k_q, out: Batch | None = None, stream=No
     return out
 
 
+def zs_query_batch_into(st: Store, t_s, t_e, k_q, U, u_off, S, s_off, V, v_off, k_out,
+                        stream=None):
+    """zs_query_batch into caller-owned device buffers.  t_s, t_e, u_off, s_off,
+    v_off: int64 numpy arrays; k_q: int32 numpy array; U, S, V: float64 device
+    tensors (offsets in elements); k_out: int32 device tensor of len(t_s)."""
+    nq = len(t_s)
+    arrs = [np.ascontiguousarray(x, np.int64) for x in (t_s, t_e, u_off, s_off, v_off)]
+    kq = np.ascontiguousarray(k_q, np.int32)
+    a = lambda x: _vp(x.ctypes.data)
+    _check(load().zs_query_batch(_vp(st.handle), nq, a(arrs[0]), a(arrs[1]), a(kq), _vp(_ptr(U)),
+                                 a(arrs[2]), _vp(_ptr(S)), a(arrs[3]), _vp(_ptr(V)), a(arrs[4]),
+                                 _vp(_ptr(k_out)), _vp(_stream(stream))))
+
+
 def zs_store_get_block(st: Store, i: int, stream=None):
     """Block i's factors as device tensors: U rows_i x k, S k, V c x k, k_i."""
     dev = torch.device("cuda", torch.cuda.current_device())

@@ -1,0 +1,89 @@
+"""FP32 and BF16 modes: the store keeps U and V in FP32 and answers in FP32.
+
+Input is exactly representable in the mode's input type (synthetic data
+rounded to float32 or bfloat16), so the oracle sees the same values in FP64.
+Store parity is block by block; query parity runs the oracle's query phase on
+the store downloaded from the GPU (decoupled, as in FP64 mode)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1805_00754_amd import synth
+from paper_1805_00754_amd import zoomsvd as zs
+from tests.gpu_common import (F32_KW, RANK_TOL_F32, TOL_FP32, compare_svd, download_store, say,
+                              to_dev)
+
+pytestmark = pytest.mark.gpu
+
+MODES = [("f32", torch.float32, zs.ZS_MODE_FP32), ("bf16", torch.bfloat16, zs.ZS_MODE_BF16)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    zs.load()
+    oracle.load()
+
+
+def series(dtype_name, t, c, seed):
+    ser = synth.sinusoid_mixture(t, c, sources=min(6, c), seed=seed, noise="iid",
+                                 noise_sigma=0.1, dtype=dtype_name)
+    return ser.A          # float64 array of values exact in the input type
+
+
+@pytest.mark.parametrize("name,tdtype,mode", MODES)
+@pytest.mark.parametrize("t,c,b,k", [(4_000, 64, 250, 10), (3_100, 128, 1000, 20), (900, 33, 64, 33)])
+def test_store_and_query_parity(name, tdtype, mode, t, c, b, k):
+    A = series(name, t, c, seed=11 + c)
+    say("precision", name, (t, c, b, k))
+    st = zs.zs_store_blocks(to_dev(A, tdtype), b, k, mode=mode)
+    torch.cuda.synchronize()
+    assert st.out_dtype == torch.float32
+    U, S, V, kk = download_store(st)
+    ost = oracle.store(A, b, k, rank_tol=RANK_TOL_F32)
+    for i in range(st.nb):
+        r = st.block_rows(i)
+        compare_svd((U[i * b:i * b + r], S[i], V[i], int(kk[i])),
+                    (ost.U[i * b:i * b + r], ost.S[i], ost.V[i], int(ost.k_i[i])),
+                    TOL_FP32, c, "%s store block %d" % (name, i), **F32_KW)
+    gst = oracle.store_from_arrays(st.t, st.c, st.b, st.k, U, S, V, kk, rank_tol=RANK_TOL_F32)
+    rng = synth.rng_for(90 + c)
+    ts, te = synth.queries_uniform(rng, t, 6, 1, t)
+    for q in range(len(ts)):
+        kq = [k, 1, max(1, k // 2)][q % 3]
+        Ug, Sg, Vg, kg = zs.zs_query(st, int(ts[q]), int(te[q]), kq)
+        zs.zs_sync_status(st)
+        assert Ug.dtype == torch.float32 and Vg.dtype == torch.float32 and Sg.dtype == torch.float64
+        got = (Ug.double().cpu().numpy(), Sg.cpu().numpy(), Vg.double().cpu().numpy(), int(kg.item()))
+        ref = oracle.query(gst, int(ts[q]), int(te[q]), kq)
+        compare_svd(got, ref, TOL_FP32, c, "%s query [%d,%d) kq %d" % (name, ts[q], te[q], kq),
+                    **F32_KW)
+    st.free()
+
+
+@pytest.mark.parametrize("name,tdtype,mode", MODES)
+def test_batch_equals_single_bitwise(name, tdtype, mode):
+    A = series(name, 5_000, 48, seed=3)
+    st = zs.zs_store_blocks(to_dev(A, tdtype), 200, 12, mode=mode)
+    rng = synth.rng_for(5)
+    ts, te = synth.queries_uniform(rng, 5_000, 24, 100, 4_000)
+    kq = rng.integers(1, 13, size=24).astype(np.int32)
+    batch = zs.zs_query_batch(st, ts, te, kq)
+    torch.cuda.synchronize()
+    for q in range(len(ts)):
+        Ub, Sb, Vb, kb = [x.cpu() for x in batch.result(q)]
+        Us, Ss, Vs, ks = [x.cpu() for x in zs.zs_query(st, int(ts[q]), int(te[q]), int(kq[q]))]
+        assert int(kb[0]) == int(ks[0])
+        assert torch.equal(Ub, Us) and torch.equal(Vb, Vs) and torch.equal(Sb, Ss)
+    st.free()
+
+
+def test_fp64_mode_accepts_float32_input():
+    """FP64 mode reads FP32 input and widens it exactly: same store as FP64 input."""
+    A = series("f32", 2_000, 32, seed=8)
+    st32 = zs.zs_store_blocks(to_dev(A, torch.float32), 250, 8, mode=zs.ZS_MODE_FP64)
+    st64 = zs.zs_store_blocks(to_dev(A), 250, 8, mode=zs.ZS_MODE_FP64)
+    a, b = download_store(st32), download_store(st64)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)

@@ -1,0 +1,53 @@
+"""The serving loop on the GPU: every served query equals the same query run
+alone (bitwise), under small budgets that force several batches."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1805_00754_amd import serve, synth
+from paper_1805_00754_amd import zoomsvd as zs
+from tests.gpu_common import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("max_queries,budget,rate", [(16, 600 << 10, 20000.0), (64, 64 << 20, 4000.0)])
+def test_served_equals_single(max_queries, budget, rate):
+    zs.load()
+    ser, cfg = synth.workload("sinmix_10k_x64_f64")
+    st = zs.zs_store_blocks(to_dev(ser.A), cfg["b"], cfg["k"])
+    torch.cuda.synchronize()
+    rng = synth.rng_for(77)
+    reqs = serve.make_requests(rng, st.t, 120, rate, 150, 8000, [3, 10])
+    # one request too large for the budget is rejected, not served
+    big = serve.Request(len(reqs), 0, st.t, cfg["k"], reqs[-1].arrival + 1e-4)
+    reqs.append(big)
+    srv = serve.Server(st, max_queries=max_queries, budget_bytes=budget)
+    got = {}
+
+    def on_batch(info, arena, kout):
+        for q, r in enumerate(info["batch"]):
+            n = r.t_e - r.t_s
+            U = arena[info["u_off"][q]:info["u_off"][q] + n * r.k_q].view(n, r.k_q)
+            S = arena[info["s_off"][q]:info["s_off"][q] + r.k_q]
+            V = arena[info["v_off"][q]:info["v_off"][q] + st.c * r.k_q].view(st.c, r.k_q)
+            got[r.idx] = (U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy(), int(kout[q].item()))
+
+    say("serve", max_queries, budget, rate)
+    res = srv.run(reqs, on_batch=on_batch)
+    too_big = {r.idx for r in reqs if serve.output_bytes(r.t_e - r.t_s, r.k_q, st.c) > budget}
+    assert set(res["rejected"]) == too_big
+    assert (big.idx in too_big) == (budget < (1 << 20))
+    assert sum(res["batches"]) == len(got)
+    assert max(res["batches"]) <= max_queries
+    for r in reqs:
+        if r.idx in res["rejected"]:
+            continue
+        U, S, V, ko = zs.zs_query(st, r.t_s, r.t_e, r.k_q)
+        torch.cuda.synchronize()
+        gU, gS, gV, gk = got[r.idx]
+        assert gk == int(ko.item())
+        np.testing.assert_array_equal(gS, S.cpu().numpy())
+        np.testing.assert_array_equal(gV, V.cpu().numpy())
+        np.testing.assert_array_equal(gU, U.cpu().numpy())
+        assert res["latency"][r.idx] > 0
