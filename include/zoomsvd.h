@@ -55,7 +55,7 @@ typedef enum { ZS_MODE_FP64 = 0, ZS_MODE_FP32 = 1, ZS_MODE_BF16 = 2 } zs_mode; /
 typedef struct zs_store zs_store;   /* opaque; owns the device-resident U_(i), Sigma_(i), V_(i) */
 
 /* Limits of this build: c <= ZS_MAX_C columns and k <= ZS_MAX_K. */
-#define ZS_MAX_C 128
+#define ZS_MAX_C 1024
 #define ZS_MAX_K 64
 
 /*

@@ -1,0 +1,398 @@
+// Leading eigenvectors of a symmetric positive semi-definite c x c Gram matrix
+// for 128 < c <= 1024, one work-group of 1024 threads per matrix, with the
+// matrix in a global scratch slot (L2 / Infinity Cache resident) and the
+// vectors of each step in LDS.  Same method as the LDS solver (eig_tri.hip):
+//
+//   1. W <- the problem's Gram terms (tree nodes / block chunk Grams, then the
+//      Grams of its Partial-SVD rows), in a fixed order.
+//   2. Householder tridiagonalisation Q^T W Q = T, one reflector per step:
+//      the reflector of row j (rows are contiguous, the matrix is kept
+//      symmetric) is formed in LDS and saved over the dead part of row j;
+//      p = t W22 v with one wave per row; W22 -= v w^T + w v^T.
+//   3. The kk largest eigenvalues of T by multisection on Sturm counts.
+//   4. Eigenvectors of T by inverse iteration (tridiagonal LU with partial
+//      pivoting, two solves, one thread per cluster of eigenvalues closer
+//      than 1e-9 ||T||, Gram-Schmidt inside a cluster), arrays in scratch.
+//   5. Back-transformation x = H_0 ... H_{c-3} z, one column per wave pass.
+//   6. Two passes of classical Gram-Schmidt (a collapsed vector is replaced
+//      by the next unit vector, which only happens in a degenerate
+//      eigenspace).
+// Scratch per problem: c^2 + 5 c kk doubles (eig_big_scratch_doubles).
+#include "zs_internal.h"
+
+namespace zs {
+namespace {
+
+constexpr int NTH = 1024;
+constexpr int kWaves = NTH / 64;
+constexpr int kBigMax = 1024;             // largest c
+constexpr int kVPL = kBigMax / 64;        // vector entries per lane in phase 5
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the work-group; red holds kWaves doubles.  All threads call it.
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    v = wave_sum(v);
+    __syncthreads();                      // red is free
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += red[w];
+    return s;
+}
+
+__device__ __forceinline__ double start_value(int i, int g, int attempt)
+{
+    uint32_t x = (uint32_t)i * 2654435761u ^ (uint32_t)(g + 1 + 97 * attempt) * 2246822519u;
+    x ^= x >> 15;
+    x *= 2246822519u;
+    x ^= x >> 13;
+    x *= 3266489917u;
+    x ^= x >> 16;
+    return (double)(x & 0xFFFFFF) / 8388608.0 - 1.0;
+}
+
+__global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *__restrict__ probs,
+                                                      const double *const *__restrict__ gsrc,
+                                                      const double *const *__restrict__ msrc,
+                                                      double *__restrict__ scratch,
+                                                      double *__restrict__ Vk)
+{
+    __shared__ double d[kBigMax], e[kBigMax], e2[kBigMax], tau[kBigMax];
+    __shared__ double vsh[kBigMax], wsh[kBigMax];
+    __shared__ double xs[NTH];
+    __shared__ int cs[NTH];
+    __shared__ double lam[kMaxK], glo[kMaxK], ghi[kMaxK], red[kWaves];
+    __shared__ int cl_start[kMaxK + 1];
+    __shared__ double sh_a, sh_b, sh_tnorm, sh_pivmin;
+    __shared__ int sh_ncl, sh_done;
+
+    const Prob P = probs[blockIdx.x];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int kk = P.kk;
+    double *W = scratch + (int64_t)blockIdx.x * ((int64_t)c * c + 5 * (int64_t)c * kMaxK);
+    double *Z = W + (int64_t)c * c;                  // c x kk, row-major
+    double *LU = Z + (int64_t)c * kMaxK;            // 4 arrays of c per solver thread
+    double *out = Vk + (int64_t)blockIdx.x * c * kMaxK;
+
+    // ---- 1. W ------------------------------------------------------------------
+    for (int64_t q = tid; q < (int64_t)c * c; q += NTH) {
+        double s = 0.0;
+        for (int g = 0; g < P.ng; ++g) s += gsrc[P.g0 + g][q];
+        W[q] = s;
+    }
+    __syncthreads();
+    for (int m = 0; m < P.nm; ++m) {
+        const double *R = msrc[P.m0 + m];                       // k x c rows
+        for (int64_t q = tid; q < (int64_t)c * c; q += NTH) {
+            const int i = (int)(q / c), j = (int)(q % c);
+            double s = W[q];
+            for (int r = 0; r < k; ++r) s = fma(R[(int64_t)r * c + i], R[(int64_t)r * c + j], s);
+            W[q] = s;
+        }
+        __syncthreads();
+    }
+
+    // ---- 2. tridiagonalisation ---------------------------------------------------
+    for (int j = 0; j + 2 < c; ++j) {
+        const int n1 = c - j - 1;
+        double *rowj = W + (int64_t)j * c;
+        double part = 0.0;
+        for (int i = tid + 1; i < n1; i += NTH) part = fma(rowj[j + 1 + i], rowj[j + 1 + i], part);
+        const double s = block_sum(part, red);
+        const double alpha = rowj[j + 1];
+        double t = 0.0, beta = alpha, scal = 0.0;
+        if (s > 0.0) {
+            const double mu = sqrt(alpha * alpha + s);
+            beta = alpha <= 0.0 ? mu : -mu;
+            t = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        if (tid == 0) {
+            tau[j] = t;
+            e[j] = beta;
+            d[j] = rowj[j];
+        }
+        for (int i = tid; i < n1; i += NTH) vsh[i] = (i == 0) ? 1.0 : rowj[j + 1 + i] * scal;
+        __syncthreads();
+        // v_j replaces the dead entries of row j (read back in phase 5)
+        for (int i = tid; i < n1; i += NTH) rowj[j + 1 + i] = vsh[i];
+        if (t == 0.0) {
+            __syncthreads();
+            continue;
+        }
+        // p = t W22 v: one wave per row
+        for (int r = wave; r < n1; r += kWaves) {
+            const double *wr = W + (int64_t)(j + 1 + r) * c + j + 1;
+            double acc = 0.0;
+            for (int i = lane; i < n1; i += 64) acc = fma(wr[i], vsh[i], acc);
+            acc = wave_sum(acc);
+            if (lane == 0) wsh[r] = t * acc;
+        }
+        __syncthreads();
+        double pk = 0.0;
+        for (int i = tid; i < n1; i += NTH) pk = fma(wsh[i], vsh[i], pk);
+        const double K = 0.5 * t * block_sum(pk, red);
+        for (int i = tid; i < n1; i += NTH) wsh[i] -= K * vsh[i];      // w = p - K v
+        __syncthreads();
+        // W22 -= v w^T + w v^T, rows by waves, columns by lanes
+        for (int r = wave; r < n1; r += kWaves) {
+            double *wr = W + (int64_t)(j + 1 + r) * c + j + 1;
+            const double vr = vsh[r], wrr = wsh[r];
+            for (int i = lane; i < n1; i += 64) wr[i] -= vr * wsh[i] + wrr * vsh[i];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        d[c - 2] = W[(int64_t)(c - 2) * c + c - 2];
+        e[c - 2] = W[(int64_t)(c - 1) * c + c - 2];
+        d[c - 1] = W[(int64_t)(c - 1) * c + c - 1];
+        double gl = d[0], gu = d[0], emax2 = 0.0;
+        for (int i = 0; i < c; ++i) {
+            const double ei = i + 1 < c ? fabs(e[i]) : 0.0;
+            const double em = i > 0 ? fabs(e[i - 1]) : 0.0;
+            gl = fmin(gl, d[i] - ei - em);
+            gu = fmax(gu, d[i] + ei + em);
+            if (i + 1 < c) emax2 = fmax(emax2, e[i] * e[i]);
+        }
+        const double tn = fmax(fabs(gl), fabs(gu));
+        const double pivmin = __DBL_MIN__ * fmax(1.0, emax2);
+        sh_tnorm = tn;
+        sh_pivmin = pivmin;
+        sh_a = gl - 2.1 * tn * __DBL_EPSILON__ * c - 4.2 * pivmin;
+        sh_b = gu + 2.1 * tn * __DBL_EPSILON__ * c + 4.2 * pivmin;
+    }
+    __syncthreads();                               // d, e complete
+    for (int i = tid; i + 1 < c; i += NTH) e2[i] = e[i] * e[i];
+    __syncthreads();
+    const double tnorm = sh_tnorm, pivmin = sh_pivmin;
+    if (tnorm == 0.0) {
+        for (int q = tid; q < c * kk; q += NTH) out[q] = (q / kk == q % kk) ? 1.0 : 0.0;
+        return;
+    }
+
+    // ---- 3. the kk largest eigenvalues: multisection on Sturm counts ---------------
+    {
+        const int G = min(NTH / kk, 64);
+        const int grp = tid / G, mem = tid % G;
+        const int m = c - 1 - grp;
+        if (tid < kk) {
+            glo[tid] = sh_a;
+            ghi[tid] = sh_b;
+        }
+        const double atol = 4.0 * __DBL_EPSILON__ * tnorm + 2.0 * pivmin;
+        for (int it = 0; it < 80; ++it) {
+            if (tid == 0) sh_done = 1;
+            __syncthreads();
+            if (grp < kk) {
+                const double lo = glo[grp], hi = ghi[grp];
+                const double x = lo + (hi - lo) * (double)(mem + 1) / (double)(G + 1);
+                double q = d[0] - x;
+                if (fabs(q) < pivmin) q = -pivmin;
+                int cnt = q < 0.0;
+                for (int i = 1; i < c; ++i) {
+                    q = d[i] - x - e2[i - 1] / q;
+                    if (fabs(q) < pivmin) q = -pivmin;
+                    cnt += q < 0.0;
+                }
+                xs[tid] = x;
+                cs[tid] = cnt;
+            }
+            __syncthreads();
+            if (grp < kk && mem == 0) {
+                double lo = glo[grp], hi = ghi[grp];
+                for (int u = 0; u < G; ++u) {
+                    if (cs[grp * G + u] <= m) {
+                        lo = xs[grp * G + u];
+                    } else {
+                        hi = xs[grp * G + u];
+                        break;
+                    }
+                }
+                glo[grp] = lo;
+                ghi[grp] = hi;
+                if (hi - lo > atol) sh_done = 0;
+            }
+            __syncthreads();
+            const int done = sh_done;
+            __syncthreads();
+            if (done) break;
+        }
+        if (tid < kk) lam[tid] = 0.5 * (glo[tid] + ghi[tid]);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int n = 0;
+        cl_start[n++] = 0;
+        for (int g = 1; g < kk; ++g)
+            if (lam[g - 1] - lam[g] > 1e-9 * tnorm) cl_start[n++] = g;
+        cl_start[n] = kk;
+        sh_ncl = n;
+    }
+    __syncthreads();
+
+    // ---- 4. inverse iteration: one thread per cluster ------------------------------
+    {
+        const int ncl = sh_ncl;
+        const double pivfloor = __DBL_EPSILON__ * tnorm;
+        if (tid < ncl) {
+            const int cl = tid;
+            double *u1 = LU + (int64_t)4 * c * tid, *u2 = u1 + c, *u3 = u2 + c, *rr = u3 + c;
+            for (int g = cl_start[cl]; g < cl_start[cl + 1]; ++g) {
+                const double lmb = lam[g];
+                double *z = Z + g;                   // column g, stride kk
+                int attempt = 0;
+                for (int i = 0; i < c; ++i) z[(int64_t)i * kk] = start_value(i, g, attempt);
+                for (int it = 0; it < 2; ++it) {
+                    double p0 = d[0] - lmb, p1 = c > 1 ? e[0] : 0.0, r = z[0];
+                    for (int i = 0; i + 1 < c; ++i) {
+                        const double sv = e[i], dd = d[i + 1] - lmb;
+                        const double ee = (i + 2 < c) ? e[i + 1] : 0.0;
+                        const double zn = z[(int64_t)(i + 1) * kk];
+                        if (fabs(sv) > fabs(p0)) {
+                            const double mlt = p0 / sv;
+                            u1[i] = sv; u2[i] = dd; u3[i] = ee; rr[i] = zn;
+                            const double np0 = p1 - mlt * dd;
+                            p1 = -mlt * ee;
+                            r = r - mlt * zn;
+                            p0 = np0;
+                        } else {
+                            double piv = p0;
+                            if (fabs(piv) < pivfloor) piv = piv < 0.0 ? -pivfloor : pivfloor;
+                            const double mlt = sv / piv;
+                            u1[i] = piv; u2[i] = p1; u3[i] = 0.0; rr[i] = r;
+                            p0 = dd - mlt * p1;
+                            p1 = ee;
+                            r = zn - mlt * r;
+                        }
+                    }
+                    if (fabs(p0) < pivfloor) p0 = p0 < 0.0 ? -pivfloor : pivfloor;
+                    double y2 = 0.0, y1 = r / p0;
+                    z[(int64_t)(c - 1) * kk] = y1;
+                    for (int i = c - 2; i >= 0; --i) {
+                        const double y = (rr[i] - u2[i] * y1 - u3[i] * y2) / u1[i];
+                        z[(int64_t)i * kk] = y;
+                        y2 = y1;
+                        y1 = y;
+                    }
+                    for (int h = cl_start[cl]; h < g; ++h) {
+                        const double *zh = Z + h;
+                        double sd = 0.0;
+                        for (int i = 0; i < c; ++i) sd = fma(zh[(int64_t)i * kk], z[(int64_t)i * kk], sd);
+                        for (int i = 0; i < c; ++i) z[(int64_t)i * kk] -= sd * zh[(int64_t)i * kk];
+                    }
+                    double nrm = 0.0;
+                    for (int i = 0; i < c; ++i) nrm = fma(z[(int64_t)i * kk], z[(int64_t)i * kk], nrm);
+                    if (!(nrm > 0.0) || !isfinite(nrm)) {
+                        ++attempt;
+                        for (int i = 0; i < c; ++i) z[(int64_t)i * kk] = start_value(i, g, attempt);
+                        continue;
+                    }
+                    const double inv = 1.0 / sqrt(nrm);
+                    for (int i = 0; i < c; ++i) z[(int64_t)i * kk] *= inv;
+                }
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+
+    // ---- 5. back-transformation: one column per wave pass --------------------------
+    for (int g = wave; g < kk; g += kWaves) {
+        double z0[kVPL];
+#pragma unroll
+        for (int u = 0; u < kVPL; ++u) {
+            const int i = lane + 64 * u;
+            z0[u] = i < c ? Z[(int64_t)i * kk + g] : 0.0;
+        }
+        for (int j = c - 3; j >= 0; --j) {
+            const double t = tau[j];
+            if (t == 0.0) continue;
+            const double *vj = W + (int64_t)j * c + j + 1;   // v_j(i') at vj[i'], row j + 1 + i'
+            double s0 = 0.0;
+#pragma unroll
+            for (int u = 0; u < kVPL; ++u) {
+                const int i = lane + 64 * u;
+                const double v = (i >= j + 1 && i < c) ? vj[i - j - 1] : 0.0;
+                s0 = fma(v, z0[u], s0);
+            }
+            s0 = t * wave_sum(s0);
+#pragma unroll
+            for (int u = 0; u < kVPL; ++u) {      // v_j again (an L1 hit)
+                const int i = lane + 64 * u;
+                const double v = (i >= j + 1 && i < c) ? vj[i - j - 1] : 0.0;
+                z0[u] -= s0 * v;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kVPL; ++u) {
+            const int i = lane + 64 * u;
+            if (i < c) Z[(int64_t)i * kk + g] = z0[u];
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+
+    // ---- 6. classical Gram-Schmidt, twice -----------------------------------------
+    for (int g = 0; g < kk; ++g) {
+        int attempt = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int h = wave; h < g; h += kWaves) {
+                double sd = 0.0;
+                for (int i = lane; i < c; i += 64) sd = fma(Z[(int64_t)i * kk + h], Z[(int64_t)i * kk + g], sd);
+                sd = wave_sum(sd);
+                if (lane == 0) xs[h] = sd;
+            }
+            __threadfence_block();
+            __syncthreads();
+            double sn = 0.0;
+            for (int i = tid; i < c; i += NTH) {
+                double v = Z[(int64_t)i * kk + g];
+                for (int h = 0; h < g; ++h) v -= xs[h] * Z[(int64_t)i * kk + h];
+                Z[(int64_t)i * kk + g] = v;
+                sn = fma(v, v, sn);
+            }
+            const double nrm2 = block_sum(sn, red);
+            if (pass == 1 && nrm2 < 0.25 && attempt < c) {
+                for (int i = tid; i < c; i += NTH)
+                    Z[(int64_t)i * kk + g] = (i == (g + attempt) % c) ? 1.0 : 0.0;
+                ++attempt;
+                pass = -1;
+                __threadfence_block();
+                __syncthreads();
+                continue;
+            }
+            const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+            for (int i = tid; i < c; i += NTH) Z[(int64_t)i * kk + g] *= inv;
+            __threadfence_block();
+            __syncthreads();
+        }
+    }
+    for (int q = tid; q < c * kk; q += NTH) out[q] = Z[q];
+}
+
+}  // namespace
+
+size_t eig_big_scratch_doubles(int c) { return (size_t)c * c + 5 * (size_t)c * kMaxK; }
+
+hipError_t launch_eig_big(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
+                          const double *const *msrc, double *scratch, double *Vk, hipStream_t stream)
+{
+    if (nprob <= 0) return hipSuccess;
+    if (c > kBigMax) return hipErrorInvalidValue;
+    timing_begin("eig", stream);
+    eig_big_kernel<<<nprob, NTH, 0, stream>>>(c, k, probs, gsrc, msrc, scratch, Vk);
+    hipError_t e = hipGetLastError();
+    timing_end("eig", stream);
+    return e;
+}
+
+}  // namespace zs

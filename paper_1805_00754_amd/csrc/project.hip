@@ -10,10 +10,11 @@
 //  * utransform: U_(i) <- Y_(i) F_(i) in place (F = W Sigma^-1 with the sign
 //    rule folded in), giving the block's left singular vectors.
 //
-// project: rows are staged through LDS with coalesced loads; V_k stays in LDS
-// for the whole chunk.  Thread (rg, j) computes column j of RQ consecutive
-// rows with independent accumulators, reading two X values per 16-byte LDS
-// load.
+// project: rows are staged through LDS with coalesced loads, in panels of up
+// to 128 columns; V_k stays in LDS for the whole chunk when c <= 128 and is
+// staged panel by panel otherwise.  Thread (rg, j) computes column j of RQ
+// consecutive rows with independent accumulators, reading two X values per
+// 16-byte LDS load.
 #include "zs_internal.h"
 
 namespace zs {
@@ -21,44 +22,40 @@ namespace {
 
 constexpr int RQ = 4;        // rows per thread
 constexpr int kMaxGroups = 16;
+constexpr int kPanelCols = 128;  // columns of X and rows of V_k staged at a time
 
 struct TileGeom {
-    int kk, cpad, ldx, groups, rb;
+    int kk, cpad, pw, ldx, groups, rb;
 };
 
-__device__ __forceinline__ TileGeom tile_geom(int c, int kk)
+__host__ __device__ inline TileGeom tile_geom(int c, int kk)
 {
     TileGeom g;
     g.kk = kk;
     g.cpad = (c + 1) & ~1;
-    g.ldx = g.cpad + 2;
-    g.groups = min(kThreads / kk, kMaxGroups);
+    g.pw = g.cpad < kPanelCols ? g.cpad : kPanelCols;
+    g.ldx = g.pw + 2;
+    g.groups = (kThreads / kk) < kMaxGroups ? (kThreads / kk) : kMaxGroups;
     g.rb = g.groups * RQ;
     return g;
 }
 
 __host__ __device__ inline size_t project_lds_bytes(int c, int kk)
 {
-    const int cpad = (c + 1) & ~1;
-    const int groups = (kThreads / kk) < kMaxGroups ? (kThreads / kk) : kMaxGroups;
-    const int rb = groups * RQ;
-    return (size_t)(cpad * kk + rb * (cpad + 2) + rb * kk) * sizeof(double);
+    const TileGeom g = tile_geom(c, kk);
+    return (size_t)(g.pw * kk + g.rb * g.ldx + g.rb * kk) * sizeof(double);
 }
 
-// Y tile: Ys[rr][j] = sum_a Xs[rr][a] Vs[a][j] for rr < nr; also written to
-// Yg + rr * kk when Yg is given.
-__device__ __forceinline__ void project_tile(const TileGeom &g, const double *Xs, const double *Vs,
-                                             int nr, double *Ys, double *Yg)
+// acc[r] += sum_a Xs[rg RQ + r][a] Vs[a][j] over the panel's pw columns.
+__device__ __forceinline__ void project_panel(const TileGeom &g, const double *Xs, const double *Vs,
+                                              int pw, double *acc)
 {
     const int tid = threadIdx.x;
     const int j = tid % g.kk, rg = tid / g.kk;
     if (rg >= g.groups) return;
-    double acc[RQ];
-#pragma unroll
-    for (int r = 0; r < RQ; ++r) acc[r] = 0.0;
     const double *x0 = Xs + rg * RQ * g.ldx;
 #pragma unroll 4
-    for (int a = 0; a < g.cpad; a += 2) {
+    for (int a = 0; a < pw; a += 2) {
         const double v0 = Vs[a * g.kk + j];
         const double v1 = Vs[(a + 1) * g.kk + j];
 #pragma unroll
@@ -68,6 +65,15 @@ __device__ __forceinline__ void project_tile(const TileGeom &g, const double *Xs
             acc[r] = fma(x.y, v1, acc[r]);
         }
     }
+}
+
+// Y tile rows rr < nr: Ys[rr][j] and Yg + rr * kk.
+__device__ __forceinline__ void store_tile(const TileGeom &g, const double *acc, int nr, double *Ys,
+                                           double *Yg)
+{
+    const int tid = threadIdx.x;
+    const int j = tid % g.kk, rg = tid / g.kk;
+    if (rg >= g.groups) return;
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
         const int rr = rg * RQ + r;
@@ -101,10 +107,13 @@ __device__ __forceinline__ void gram_accumulate(const double *Ys, int kk, int nr
     }
 }
 
-__device__ __forceinline__ void load_vk(const TileGeom &g, int c, const double *vk, double *Vs)
+// Rows [p0, p0 + pw) of V_k (c x kk) into Vs, zero beyond c.
+__device__ __forceinline__ void load_vk(const TileGeom &g, int c, int p0, const double *vk, double *Vs)
 {
-    for (int e = threadIdx.x; e < g.cpad * g.kk; e += kThreads)
-        Vs[e] = (e < c * g.kk) ? vk[e] : 0.0;
+    for (int e = threadIdx.x; e < g.pw * g.kk; e += kThreads) {
+        const int a = p0 + e / g.kk;
+        Vs[e] = a < c ? vk[(int64_t)p0 * g.kk + e] : 0.0;
+    }
 }
 
 template <typename TA>
@@ -118,24 +127,33 @@ __global__ __launch_bounds__(kThreads) void project_kernel(const TA *__restrict_
     const Chunk ch = chunks[blockIdx.x];
     const TileGeom g = tile_geom(c, ch.kk);
     double *Vs = smem;
-    double *Xs = Vs + g.cpad * g.kk;
+    double *Xs = Vs + g.pw * g.kk;
     double *Ys = Xs + g.rb * g.ldx;
     const int tid = threadIdx.x;
-    load_vk(g, c, Vk + (int64_t)ch.prob * c * kMaxK, Vs);
+    const double *vk = Vk + (int64_t)ch.prob * c * kMaxK;
+    const bool one_panel = g.pw == g.cpad;        // c <= kPanelCols: V_k staged once
+    if (one_panel) load_vk(g, c, 0, vk, Vs);
     double gacc[EPT];
 #pragma unroll
     for (int x = 0; x < EPT; ++x) gacc[x] = 0.0;
     const TA *Xc = X + ch.x_off;
     for (int r0 = 0; r0 < ch.rows; r0 += g.rb) {
         const int nr = min(g.rb, ch.rows - r0);
-        __syncthreads();
-        for (int e = tid; e < g.rb * g.cpad; e += kThreads) {
-            const int rr = e / g.cpad, col = e % g.cpad;
-            Xs[rr * g.ldx + col] =
-                (rr < nr && col < c) ? load_as_double(Xc, (int64_t)(r0 + rr) * ld + col) : 0.0;
+        double acc[RQ];
+#pragma unroll
+        for (int r = 0; r < RQ; ++r) acc[r] = 0.0;
+        for (int p0 = 0; p0 < g.cpad; p0 += g.pw) {
+            __syncthreads();
+            if (!one_panel) load_vk(g, c, p0, vk, Vs);
+            for (int e = tid; e < g.rb * g.pw; e += kThreads) {
+                const int rr = e / g.pw, col = p0 + e % g.pw;
+                Xs[rr * g.ldx + e % g.pw] =
+                    (rr < nr && col < c) ? load_as_double(Xc, (int64_t)(r0 + rr) * ld + col) : 0.0;
+            }
+            __syncthreads();
+            project_panel(g, Xs, Vs, g.pw, acc);
         }
-        __syncthreads();
-        project_tile(g, Xs, Vs, nr, Ys, Y + ch.y_off + (int64_t)r0 * ch.kk);
+        store_tile(g, acc, nr, Ys, Y + ch.y_off + (int64_t)r0 * ch.kk);
         __syncthreads();
         gram_accumulate(Ys, ch.kk, nr, gacc);
     }

@@ -1,6 +1,7 @@
 // Small symmetric eigen-solves (n <= 64) and the kernels built on them:
 //
-//  * finalize: second stage of every rank-k SVD.  With Y = X V_k (the data
+//  * finalize: second stage of every rank-k SVD (V_k is overwritten by
+//    V_k W).  With Y = X V_k (the data
 //    projected on the first-stage eigenvectors), G_Y = Y^T Y is nearly
 //    diagonal with scales sigma_j^2; two-sided Jacobi on it (Demmel-Veselic
 //    stopping rule) gives singular values with high relative accuracy
@@ -128,9 +129,11 @@ __device__ int sym_jacobi(double *G, double *W, int n, int ld, double *cs_sh, do
     return -1;
 }
 
+constexpr int kFinRows = 64;   // rows of V_k staged at a time by finalize
+
 __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *__restrict__ probs,
                                                             const double *__restrict__ GYpart,
-                                                            const double *__restrict__ Vk,
+                                                            double *__restrict__ Vk,
                                                             double *__restrict__ F,
                                                             double rank_tol, int kk_max,
                                                             int *__restrict__ conv_flag)
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *_
     const int ld = kk_max + 1;                // leading dimension of the kk x kk matrices
     double *G = smem;                         // kk x kk
     double *W = G + kk_max * ld;              // kk x kk
-    double *Vn = W + kk_max * ld;             // c x kk (V_k W)
+    double *Rs = W + kk_max * ld;             // kFinRows x kk rows of V_k
     __shared__ double cs_sh[kMaxK / 2], sn_sh[kMaxK / 2], dp_sh[kMaxK / 2], dq_sh[kMaxK / 2];
     __shared__ double sig[kMaxK], flip[kMaxK];
     __shared__ int pos[kMaxK], inv[kMaxK], keep[kMaxK];
@@ -171,30 +174,37 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *_
         inv[p] = j;
         keep[j] = (sig[j] > rank_tol * smax) && (sig[j] > 0.0);
     }
-    // Vn = V_k W
-    const double *vk = Vk + (int64_t)blockIdx.x * c * kMaxK;
-    for (int e = tid; e < c * kk; e += kThreads) {
-        const int a = e / kk, j = e % kk;
-        double s = 0.0;
-        for (int l = 0; l < kk; ++l) s = fma(vk[a * kk + l], W[l * ld + j], s);
-        Vn[a * kk + j] = s;
+    // Vn = V_k W, in place over V_k (no longer needed), kFinRows rows at a time
+    double *Vn = Vk + (int64_t)blockIdx.x * c * kMaxK;
+    for (int a0 = 0; a0 < c; a0 += kFinRows) {
+        const int nr = min(kFinRows, c - a0);
+        __syncthreads();
+        for (int e = tid; e < nr * kk; e += kThreads) Rs[e] = Vn[(int64_t)a0 * kk + e];
+        __syncthreads();
+        for (int e = tid; e < nr * kk; e += kThreads) {
+            const int a = e / kk, j = e % kk;
+            double s = 0.0;
+            for (int l = 0; l < kk; ++l) s = fma(Rs[a * kk + l], W[l * ld + j], s);
+            Vn[(int64_t)a0 * kk + e] = s;
+        }
     }
+    __threadfence_block();
     __syncthreads();
     // sign rule: largest |v| entry (lowest index on ties) made positive
     for (int j = tid; j < kk; j += kThreads) {
         int am = 0;
         double vm = -1.0;
         for (int a = 0; a < c; ++a) {
-            const double v = fabs(Vn[a * kk + j]);
+            const double v = fabs(Vn[(int64_t)a * kk + j]);
             if (v > vm) { vm = v; am = a; }
         }
-        flip[j] = Vn[am * kk + j] < 0.0 ? -1.0 : 1.0;
+        flip[j] = Vn[(int64_t)am * kk + j] < 0.0 ? -1.0 : 1.0;
     }
     __syncthreads();
     for (int e = tid; e < c * kk; e += kThreads) {
         const int a = e / kk, pp = e % kk;
         const int j = inv[pp];
-        const double v = keep[j] ? flip[j] * Vn[a * kk + j] : 0.0;
+        const double v = keep[j] ? flip[j] * Vn[(int64_t)a * kk + j] : 0.0;
         if (P.v_f32)
             static_cast<float *>(P.v_dst)[a * P.v_rs + pp * P.v_cs] = (float)v;
         else
@@ -340,13 +350,13 @@ __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
 }  // namespace
 
 hipError_t launch_finalize(int c, const Prob *probs, int nprob, int kk_max, const double *GYpart,
-                           const double *Vk, double *F, double rank_tol, int *conv_flag,
+                           double *Vk, double *F, double rank_tol, int *conv_flag,
                            hipStream_t stream)
 {
     if (nprob <= 0) return hipSuccess;
     if (kk_max < 1 || kk_max > kMaxK) return hipErrorInvalidValue;
     timing_begin("finalize", stream);
-    const size_t lds = (size_t)(2 * kk_max * (kk_max + 1) + c * kk_max) * sizeof(double);
+    const size_t lds = (size_t)(2 * kk_max * (kk_max + 1) + kFinRows * kk_max) * sizeof(double);
     static size_t cur = 0;
     {
         hipError_t e = ensure_lds((const void *)finalize_kernel, lds, cur);

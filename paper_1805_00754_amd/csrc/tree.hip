@@ -10,6 +10,8 @@
 // of positive semi-definite terms, so no cancellation occurs.
 #include "zs_internal.h"
 
+#include <algorithm>
+
 namespace zs {
 namespace {
 
@@ -55,7 +57,46 @@ __global__ __launch_bounds__(kThreads) void tree_level_kernel(int c, double *__r
         D[e] = L[e] + R[e];
 }
 
+// Rows sigma_ij v_ij^T of every block in FP64 (the input of the Gram kernel
+// when c is too large for one work-group's LDS), and zero leaves past nb.
+template <typename TU>
+__global__ __launch_bounds__(kThreads) void scale_rows_kernel(StoreView st, int64_t nb,
+                                                              double *__restrict__ rows)
+{
+    const int64_t kc = (int64_t)st.k * st.c;
+    const TU *Vt = static_cast<const TU *>(st.Vt);
+    for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < nb * kc;
+         e += (int64_t)gridDim.x * kThreads)
+        rows[e] = (double)Vt[e] * st.S[e / st.c];
+}
+
+__global__ __launch_bounds__(kThreads) void zero_kernel(double *__restrict__ p, int64_t n)
+{
+    for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kThreads)
+        p[e] = 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_scale_rows(StoreView st, int64_t nb, double *rows, hipStream_t stream)
+{
+    const int64_t n = nb * st.k * st.c;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 65536);
+    if (st.f32)
+        scale_rows_kernel<float><<<grid, kThreads, 0, stream>>>(st, nb, rows);
+    else
+        scale_rows_kernel<double><<<grid, kThreads, 0, stream>>>(st, nb, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double *p, int64_t n, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 65536);
+    zero_kernel<<<grid, kThreads, 0, stream>>>(p, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_leaf_gram(StoreView st, int64_t nleaves, double *tree, int64_t leaf0,
                             hipStream_t stream)

@@ -125,8 +125,9 @@ hipError_t launch_project(const void *X, int x_type, int64_t ld, int c, const Ch
 hipError_t launch_stack_project(StoreView st, const Piece *pieces, const double *Mp,
                                 const StackChunk *chunks, int nchunks, int kq_max,
                                 const double *Vk, double *Y, double *GYpart, hipStream_t stream);
+// Overwrites V_k (no longer needed) with V_k W.
 hipError_t launch_finalize(int c, const Prob *probs, int nprob, int kk_max, const double *GYpart,
-                           const double *Vk, double *F, double rank_tol, int *conv_flag,
+                           double *Vk, double *F, double rank_tol, int *conv_flag,
                            hipStream_t stream);
 // U <- Y F per chunk; Y is FP64, U has the store's element type (may alias Y
 // in FP64 mode).
@@ -134,6 +135,13 @@ hipError_t launch_utransform(const double *Y, void *U, int u_f32, int k, const C
                              int nchunks, const double *F, hipStream_t stream);
 hipError_t launch_leaf_gram(StoreView st, int64_t nleaves, double *tree, int64_t leaf0,
                             hipStream_t stream);
+// rows[i][j][:] = sigma_ij V_(i)^T[j][:] in FP64 for every block.
+hipError_t launch_scale_rows(StoreView st, int64_t nb, double *rows, hipStream_t stream);
+hipError_t launch_zero(double *p, int64_t n, hipStream_t stream);
+// Eigen-solver for 128 < c <= 1024 with the matrix in global scratch.
+size_t eig_big_scratch_doubles(int c);
+hipError_t launch_eig_big(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
+                          const double *const *msrc, double *scratch, double *Vk, hipStream_t stream);
 hipError_t launch_tree_level(int c, double *tree, int64_t node0, int64_t nnodes,
                              hipStream_t stream);
 hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx, int npartial,

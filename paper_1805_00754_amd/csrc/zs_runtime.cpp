@@ -86,7 +86,7 @@ struct DevBuf {
 
 // Scratch of the query pipeline for one stream (grow-only).
 struct Workspace {
-    DevBuf Mp, Vk, Y, GY, F, T, C, P, perm, bcount, desc;
+    DevBuf Mp, Vk, Y, GY, F, T, C, P, perm, bcount, big, desc;
     void *host = nullptr;        // pinned staging of the descriptors
     size_t host_bytes = 0;
     hipEvent_t copied = nullptr; // the last upload from `host` has completed
@@ -94,7 +94,7 @@ struct Workspace {
     {
         Mp.release(); Vk.release(); Y.release(); GY.release();
         F.release(); T.release(); C.release(); P.release(); perm.release(); bcount.release();
-        desc.release();
+        big.release(); desc.release();
         if (host) (void)hipHostFree(host);
         if (copied) (void)hipEventDestroy(copied);
         host = nullptr;
@@ -160,11 +160,19 @@ void timing_end(const char *name, hipStream_t stream)
 
 namespace {
 
-// First-stage eigen-solver: tridiagonalisation (default) or one-sided Jacobi
-// (ZS_EIG=jacobi), both on the same Gram terms.
+// First-stage eigen-solver: tridiagonalisation in LDS (default, c <= 128) or
+// one-sided Jacobi (ZS_EIG=jacobi, c <= 128), both on the same Gram terms; for
+// c > 128 the tridiagonal solver with its matrix in global scratch (`big`,
+// eig_big_scratch_doubles(c) doubles per problem).
 hipError_t first_stage_eig(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
-                           const double *const *msrc, double *Vk, int *conv, hipStream_t stream)
+                           const double *const *msrc, double *Vk, DevBuf &big, int *conv,
+                           hipStream_t stream)
 {
+    if (c > kMaxC) {
+        hipError_t e = big.ensure(sizeof(double) * eig_big_scratch_doubles(c) * (size_t)nprob);
+        if (e != hipSuccess) return e;
+        return launch_eig_big(c, k, probs, nprob, gsrc, msrc, big.as<double>(), Vk, stream);
+    }
     static const bool use_jacobi = [] {
         const char *v = getenv("ZS_EIG");
         return v && std::strcmp(v, "jacobi") == 0;
@@ -367,7 +375,7 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
     HIP_TRY(launch_expand_pieces(sv, d_qds, nq, max_np, w->P.as<Piece>(), stream));
     HIP_TRY(launch_partial(sv, d_pieces, d_pidx, npartial, Mp, w->T.as<double>(), st->rank_tol(),
                            st->conv, stream));
-    HIP_TRY(first_stage_eig((int)c, k, d_probs, nq, d_gsrc, d_msrc, w->Vk.as<double>(),
+    HIP_TRY(first_stage_eig((int)c, k, d_probs, nq, d_gsrc, d_msrc, w->Vk.as<double>(), w->big,
                             st->conv, stream));
     HIP_TRY(launch_stack_project(sv, d_pieces, Mp, d_chunks, nchunks, kq_max, w->Vk.as<double>(),
                                  w->Y.as<double>(), w->GY.as<double>(), stream));
@@ -458,11 +466,13 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
         std::memset(&pr, 0, sizeof pr);
         pr.g0 = slot;
         pr.y0 = slot;
-        for (int64_t r = 0; r < rows; r += kStoreChunkRows) {
+        // one chunk per block for c > 128 (each chunk holds a c x c partial Gram)
+        const int64_t crows = c > kMaxC ? std::max<int64_t>(kStoreChunkRows, b) : kStoreChunkRows;
+        for (int64_t r = 0; r < rows; r += crows) {
             Chunk ch;
             ch.x_off = (i * b + r) * lda;
             ch.y_off = (i * b + r) * k;
-            ch.rows = (int32_t)std::min<int64_t>(kStoreChunkRows, rows - r);
+            ch.rows = (int32_t)std::min<int64_t>(crows, rows - r);
             ch.prob = (int32_t)i;
             ch.slot = slot++;
             ch.kk = k;
@@ -480,9 +490,10 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
         probs[i] = pr;
     }
     const int nchunks = (int)chunks.size();
-    DevBuf Gpart, Vk, GY, F, Ysc, desc;
+    DevBuf Gpart, Vk, GY, F, Ysc, Big, Rows, desc;
     auto release = [&]() {
-        Gpart.release(); Vk.release(); GY.release(); F.release(); Ysc.release(); desc.release();
+        Gpart.release(); Vk.release(); GY.release(); F.release(); Ysc.release(); Big.release();
+        Rows.release(); desc.release();
     };
 #define ST_TRY2(expr)                                                                       \
     do {                                                                                    \
@@ -502,25 +513,51 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
     double *Y = st->f32 ? Ysc.as<double>() : static_cast<double *>(st->U);
     std::vector<const double *> gsrc(nchunks);
     for (int s2 = 0; s2 < nchunks; ++s2) gsrc[s2] = Gpart.as<double>() + (int64_t)s2 * c * c;
+    std::vector<Chunk> leaf_chunks;           // c > 128: block i's k scaled rows -> leaf i
+    if (c > kMaxC) {
+        for (int64_t i = 0; i < nb; ++i) {
+            Chunk ch;
+            ch.x_off = i * k * c;
+            ch.y_off = 0;
+            ch.rows = k;
+            ch.prob = (int32_t)i;
+            ch.slot = (int32_t)i;
+            ch.kk = k;
+            leaf_chunks.push_back(ch);
+        }
+    }
     Blob blob;
     const size_t o_chunks = blob.add(chunks), o_probs = blob.add(probs), o_gsrc = blob.add(gsrc);
+    const size_t o_leaf = blob.add(leaf_chunks);
     ST_TRY2(desc.ensure(blob.bytes.size()));
     ST_TRY2(hipMemcpyAsync(desc.p, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice,
                            stream));
     const Chunk *d_chunks = (const Chunk *)(desc.as<char>() + o_chunks);
     const Prob *d_probs = (const Prob *)(desc.as<char>() + o_probs);
     const double *const *d_gsrc = (const double *const *)(desc.as<char>() + o_gsrc);
+    const Chunk *d_leaf_chunks = (const Chunk *)(desc.as<char>() + o_leaf);
     const int x_type = a_type == ZS_F32 ? kElemF32 : a_type == ZS_BF16 ? kElemBF16 : kElemF64;
     ST_TRY2(launch_gram(A, x_type, lda, (int)c, d_chunks, nchunks, Gpart.as<double>(), stream));
-    ST_TRY2(first_stage_eig((int)c, k, d_probs, (int)nb, d_gsrc, nullptr, Vk.as<double>(),
+    ST_TRY2(first_stage_eig((int)c, k, d_probs, (int)nb, d_gsrc, nullptr, Vk.as<double>(), Big,
                             st->conv, stream));
     ST_TRY2(launch_project(A, x_type, lda, (int)c, d_chunks, nchunks, k, Vk.as<double>(), Y,
                            GY.as<double>(), stream));
     ST_TRY2(launch_finalize((int)c, d_probs, (int)nb, k, GY.as<double>(), Vk.as<double>(),
                             F.as<double>(), st->rank_tol(), st->conv, stream));
     ST_TRY2(launch_utransform(Y, st->U, st->f32, k, d_chunks, nchunks, F.as<double>(), stream));
-    // Gram tree over the stored blocks: leaves, then one launch per level.
-    ST_TRY2(launch_leaf_gram(st->view(), st->n2, st->tree, st->n2, stream));
+    // Gram tree over the stored blocks: leaves, then one launch per level.  For
+    // c > 128 a leaf is the Gram of the block's rows sigma_ij v_ij^T, formed by
+    // the Gram kernel (one chunk of k rows per block); leaves past nb are zero.
+    if (c <= kMaxC) {
+        ST_TRY2(launch_leaf_gram(st->view(), st->n2, st->tree, st->n2, stream));
+    } else {
+        ST_TRY2(Rows.ensure(sizeof(double) * (size_t)nb * k * c));
+        ST_TRY2(launch_scale_rows(st->view(), nb, Rows.as<double>(), stream));
+        double *leaves = st->tree + st->n2 * c * c;
+        ST_TRY2(launch_gram(Rows.as<double>(), kElemF64, c, (int)c, d_leaf_chunks, (int)nb, leaves,
+                            stream));
+        ST_TRY2(launch_zero(leaves + nb * c * c, (st->n2 - nb) * c * c, stream));
+    }
     for (int64_t lev = st->n2 / 2; lev >= 1; lev /= 2)
         ST_TRY2(launch_tree_level((int)c, st->tree, lev, lev, stream));
     ST_TRY2(hipStreamSynchronize(stream));

@@ -115,6 +115,27 @@ def test_query_parity_other_widths(t, c, b, k):
         compare_svd(got, ref, TOL_FP64, c, "c %d k %d [%d,%d) kq %d" % (c, k, ts[q], te[q], kq))
 
 
+# c above 128: the eigen-solver keeps its matrix in global scratch and the
+# leaf Grams go through the Gram kernel.
+LARGE_C = [(3_000, 200, 600, 24), (4_000, 256, 1000, 32), (2_600, 512, 1300, 48),
+           (2_100, 1024, 1050, 64)]
+
+
+@pytest.mark.parametrize("t,c,b,k", LARGE_C)
+def test_large_c_store_and_query_parity(t, c, b, k):
+    ser = synth.sinusoid_mixture(t, c, sources=12, seed=5 + c, noise="iid", noise_sigma=0.1)
+    st, (U, S, V, kk) = check_store(ser.A, b, k, "large c %d" % c)
+    gst = oracle.store_from_arrays(st.t, st.c, st.b, st.k, U, S, V, kk)
+    rng = synth.rng_for(c)
+    ts, te = synth.queries_uniform(rng, t, 4, 1, t)
+    for q in range(4):
+        kq = [k, 5][q % 2]
+        say("large c query", c, int(ts[q]), int(te[q]), kq)
+        got = gpu_query(st, int(ts[q]), int(te[q]), kq)
+        ref = oracle.query(gst, int(ts[q]), int(te[q]), kq)
+        compare_svd(got, ref, TOL_FP64, c, "c %d [%d,%d) kq %d" % (c, ts[q], te[q], kq))
+
+
 def test_query_exact_on_block_low_rank():
     """Block rank <= k: the stitched SVD equals the direct SVD of A[t_s:t_e)."""
     t, c, b, k = 5_300, 40, 100, 6

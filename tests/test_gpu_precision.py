@@ -33,7 +33,8 @@ def series(dtype_name, t, c, seed):
 
 
 @pytest.mark.parametrize("name,tdtype,mode", MODES)
-@pytest.mark.parametrize("t,c,b,k", [(4_000, 64, 250, 10), (3_100, 128, 1000, 20), (900, 33, 64, 33)])
+@pytest.mark.parametrize("t,c,b,k", [(4_000, 64, 250, 10), (3_100, 128, 1000, 20), (900, 33, 64, 33),
+                                     (4_000, 256, 1000, 32)])
 def test_store_and_query_parity(name, tdtype, mode, t, c, b, k):
     A = series(name, t, c, seed=11 + c)
     say("precision", name, (t, c, b, k))
