@@ -47,6 +47,10 @@ def main():
     ap.add_argument("--serve-rates", default="500,2000,8000",
                     help="arrival rates (queries/s) of the serving runs; empty to skip")
     ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="named synthetic workload (synth.WORKLOADS); the default is the one "
+                         "the headline metric is quoted on")
+    ap.add_argument("--query-len", type=int, default=QUERY_LEN)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -64,18 +68,24 @@ def main():
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream()
 
-    log("generating %s" % WORKLOAD)
-    ser, cfg = synth.workload(WORKLOAD)
+    wl = args.workload
+    log("generating %s" % wl)
+    ser, cfg = synth.workload(wl)
     A_host = ser.A
     t, c = A_host.shape
     b, k = cfg["b"], cfg["k"]
-    ts, te = synth.queries_fixed(ser.rng, t, args.queries, QUERY_LEN)
+    tdtype, mode, esize = {"f64": (torch.float64, zs.ZS_MODE_FP64, 8),
+                           "f32": (torch.float32, zs.ZS_MODE_FP32, 4),
+                           "bf16": (torch.bfloat16, zs.ZS_MODE_BF16, 2)}[cfg["dtype"]]
+    usize = 8 if mode == zs.ZS_MODE_FP64 else 4       # stored U / V element size
+    qlen = min(args.query_len, t)
+    ts, te = synth.queries_fixed(ser.rng, t, args.queries, qlen)
     kq = np.full(args.queries, k, np.int32)
-    A = torch.from_numpy(A_host).to(dev)
+    A = torch.from_numpy(A_host).to(dev).to(tdtype)
     torch.cuda.synchronize()
 
     # Output buffers of the batch are allocated once, outside the timed region.
-    st0 = zs.zs_store_blocks(A, b, k)
+    st0 = zs.zs_store_blocks(A, b, k, mode=mode)
     out = zs.Batch(st0, ts, te, kq, dev)
     st0.free()
 
@@ -84,7 +94,7 @@ def main():
         e1 = torch.cuda.Event(enable_timing=True)
         e2 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        st = zs.zs_store_blocks(A, b, k)        # synchronises the stream at its end
+        st = zs.zs_store_blocks(A, b, k, mode=mode)   # synchronises the stream at its end
         e1.record(stream)
         zs.zs_query_batch(st, ts, te, kq, out=out)
         e2.record(stream)
@@ -122,9 +132,9 @@ def main():
 
     # Single-query latency (queries issued one at a time).
     lat = []
-    U1 = torch.empty((QUERY_LEN, k), dtype=torch.float64, device=dev)
+    U1 = torch.empty((qlen, k), dtype=st.out_dtype, device=dev)
     S1 = torch.empty(k, dtype=torch.float64, device=dev)
-    V1 = torch.empty((c, k), dtype=torch.float64, device=dev)
+    V1 = torch.empty((c, k), dtype=st.out_dtype, device=dev)
     ko = torch.empty(1, dtype=torch.int32, device=dev)
     for q in range(min(args.latency_samples + 4, args.queries)):
         torch.cuda.synchronize()
@@ -133,13 +143,13 @@ def main():
         torch.cuda.synchronize()
         if q >= 4:
             lat.append((time.perf_counter() - a) * 1e3)
-    serving = serve_runs(st, args) if args.serve_rates else None
+    serving = serve_runs(st, args) if (args.serve_rates and wl == WORKLOAD) else None
     st.free()
 
     q_ms = float(np.mean(query_ms))
     s_ms = float(np.mean(store_ms))
     value = args.queries / (q_ms / 1e3)
-    store_gbps = t * c * 8 / (s_ms / 1e3) / 1e9
+    store_gbps = t * c * esize / (s_ms / 1e3) / 1e9
 
     # Roofline of the dominant kernel (largest share of the timed region).
     n_rows = int((te - ts).sum())
@@ -148,10 +158,10 @@ def main():
     algo = {
         # per query: its U rows read (k values each) and written (k_q each), plus
         # one k x k_q coefficient block per touched block (stored k_q x prod_ld(k))
-        "blockprod": ("hbm", 8.0 * (n_rows * k + n_rows * k + pieces * kp * k), "GB/s"),
+        "blockprod": ("hbm", usize * 2.0 * n_rows * k + 8.0 * pieces * kp * k, "GB/s"),
         # A read once
-        "gram": ("hbm", 8.0 * t * c, "GB/s"),
-        "project": ("hbm", 8.0 * (t * c + t * k), "GB/s"),
+        "gram": ("hbm", esize * t * c, "GB/s"),
+        "project": ("hbm", esize * t * c + 8.0 * t * k, "GB/s"),
     }
     dom = max(kernels, key=lambda n: kernels[n]["total_ms"])
     if dom in algo:
@@ -160,12 +170,12 @@ def main():
         achieved = amount / avg_s / 1e9
         roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBPS,
                 "unit": unit, "frac": achieved / HBM_PEAK_GBPS,
-                "traffic": profiled_traffic(dom), "algorithmic_bytes_per_launch": amount,
+                "traffic": profiled_traffic(dom, wl), "algorithmic_bytes_per_launch": amount,
                 "avg_launch_ms": avg_s * 1e3}
         if dom == "blockprod":
             # bytes that must cross HBM at least once: U (each stored row once),
             # the coefficient blocks and the output
-            unique = 8.0 * (t * k + pieces * kp * k + n_rows * k)
+            unique = usize * (t * k + n_rows * k) + 8.0 * pieces * kp * k
             roof["unique_bytes_per_launch"] = unique
             roof["unique_frac"] = unique / avg_s / 1e9 / HBM_PEAK_GBPS
     else:
@@ -173,7 +183,7 @@ def main():
                 "unit": "TFLOP/s", "frac": None, "traffic": None}
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and wl == WORKLOAD:
         cpu = cpu_baseline(A_host, b, k, ts, te, args.cpu_queries)
 
     res = {
@@ -188,9 +198,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
+        "storage": "f64" if usize == 8 else "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "t": t, "c": c, "b": b, "k": k,
-                   "queries": args.queries, "query_rows": QUERY_LEN, "k_q": k,
+        "config": {"workload": wl, "t": t, "c": c, "b": b, "k": k, "input": cfg["dtype"],
+                   "queries": args.queries, "query_rows": qlen, "k_q": k,
                    "parallelism": "single-gpu"},
         "query_batch_ms": q_ms,
         "store_ms": s_ms,
@@ -237,13 +248,13 @@ def prod_ld(k):
     return (k + 3) & ~3 if k <= 32 else (k + 15) & ~15
 
 
-def profiled_traffic(kernel):
+def profiled_traffic(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 counter summary of this
     kernel on this workload (FETCH_SIZE and WRITE_SIZE scaled by a plain copy),
     or None when there is none or the kernel source has changed since."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "%s_%s.md" % (kernel, WORKLOAD))
+    path = os.path.join(ROOT, "profiles", "%s_%s.md" % (kernel, workload))
     if not os.path.exists(path):
         return None
     fields = {}
