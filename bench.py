@@ -44,8 +44,9 @@ def main():
     ap.add_argument("--latency-samples", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=32)
-    ap.add_argument("--serve-rates", default="500,2000,8000",
-                    help="arrival rates (queries/s) of the serving runs; empty to skip")
+    ap.add_argument("--serve-rates", default=None,
+                    help="arrival rates (queries/s) of the serving runs; empty to skip "
+                         "(default 500,2000,8000 on the default workload, none on others)")
     ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--workload", default=WORKLOAD,
                     help="named synthetic workload (synth.WORKLOADS); the default is the one "
@@ -143,7 +144,9 @@ def main():
         torch.cuda.synchronize()
         if q >= 4:
             lat.append((time.perf_counter() - a) * 1e3)
-    serving = serve_runs(st, args) if (args.serve_rates and wl == WORKLOAD) else None
+    if args.serve_rates is None:
+        args.serve_rates = "500,2000,8000" if wl == WORKLOAD else ""
+    serving = serve_runs(st, args) if args.serve_rates else None
     st.free()
 
     q_ms = float(np.mean(query_ms))

@@ -21,19 +21,13 @@
 // The total work is O(c^3) with a small constant, against O(50 c^3) for
 // one-sided Jacobi.
 #include "zs_internal.h"
+#include "wave.h"
 
 namespace zs {
 namespace {
 
 constexpr int NTH = 1024;                 // threads of the eigen-solver work-group
 constexpr int kWaves = NTH / 64;
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 // Deterministic start vector in (-1, 1) for inverse iteration.
 __device__ __forceinline__ double start_value(int i, int g, int attempt)
@@ -48,19 +42,22 @@ __device__ __forceinline__ double start_value(int i, int g, int attempt)
 }
 
 // LDS layout of the solver (doubles): d, e, e2, tau (NMAX each), lam (kMaxK),
-// then one region of REGION doubles.  The region holds the matrix during the
-// tridiagonal reduction; the reduction packs each Householder vector into rows
-// it no longer needs, so that afterwards the region holds, in order: the
-// packed vectors, the eigenvector block Z (c x kk) and the inverse-iteration
-// arrays.  All data stays in LDS between phases; global memory is written once.
+// then one region of REGION doubles.  The matrix itself never enters LDS: each
+// thread keeps its elements in registers during the tridiagonal reduction.
+// The region holds, in order: the packed Householder vectors (HPMAX), then a
+// scratch area that the reduction and the multisection use and that later
+// holds the eigenvector block Z (c x kk) and the inverse-iteration arrays.
 template <int NMAX>
 struct TriLayout {
-    static constexpr int LDA = NMAX + 1;
-    static constexpr int AREA = NMAX * LDA;
     static constexpr int HPMAX = (NMAX - 1) * NMAX / 2;             // packed vectors
     static constexpr int KZ = NMAX < kMaxK ? NMAX : kMaxK;           // largest kk
-    static constexpr int NEED = HPMAX + NMAX * KZ + 4 * NMAX * 4;     // >= 4 solver threads
-    static constexpr int R0 = AREA + 1536;
+    static constexpr int NEED = HPMAX + NMAX * KZ + 3 * NMAX * 8;     // >= 8 solver lanes
+    // reduction: wave partials (16 NMAX), two v buffers, p, wave dot partials;
+    // multisection: NTH points and NTH counts
+    static constexpr int SCR_TRI = 16 * NMAX + 3 * NMAX + 16;
+    static constexpr int SCR_MS = NTH + NTH / 2;
+    static constexpr int SCR = SCR_TRI > SCR_MS ? SCR_TRI : SCR_MS;
+    static constexpr int R0 = HPMAX + SCR;
     static constexpr int REGION = R0 > NEED ? R0 : NEED;
     static constexpr size_t bytes() { return (size_t)(4 * NMAX + kMaxK + REGION) * sizeof(double); }
 };
@@ -72,134 +69,237 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
                                                       double *__restrict__ Vk)
 {
     using L = TriLayout<NMAX>;
-    constexpr int LDA = L::LDA;
-    constexpr int MR = 8;
+    constexpr int RPW = NMAX / kWaves;             // matrix rows per wave
+    constexpr int CPL = (NMAX + 63) / 64;          // matrix columns per lane
+    constexpr int MR = 8;                          // rows of a Partial-SVD term staged at once
     extern __shared__ __align__(16) double smem[];
     double *d = smem;
     double *e = d + NMAX;
     double *e2 = e + NMAX;
     double *tau = e2 + NMAX;
     double *lam = tau + NMAX;                      // kMaxK
-    double *A = lam + kMaxK;                       // region: matrix, row-major A[i * LDA + j]
-    double *scr = A + L::AREA;                     // tail of the region (phases 1-3)
+    double *A = lam + kMaxK;                       // region: packed vectors first
+    double *scr = A + L::HPMAX;                    // scratch (phases 1-3), later Z
     __shared__ double sh_a, sh_b, sh_tnorm, sh_pivmin;
-    __shared__ double glo[kMaxK], ghi[kMaxK];
     __shared__ int cl_start[kMaxK + 1];
-    __shared__ int sh_ncl, sh_done;
+    __shared__ int sh_ncl;
 
     const Prob P = probs[blockIdx.x];
     const int tid = threadIdx.x;
-    const int wave = tid / 64, lane = tid % 64;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
     const int kk = P.kk;
     double *out = Vk + (int64_t)blockIdx.x * c * kMaxK;   // c x kk, row-major
     // packed Householder vector j starts at hoff(j); its entry 0 is 1
     auto hoff = [c](int j) { return j * (c - 1) - j * (j - 1) / 2; };
 
+    // Matrix element (R, C), R = wave + 16 m, C = lane + 64 s, lives in a[m][s]
+    // of this thread; elements outside c x c are zero.
+    double a[RPW][CPL];
+
     // ---- 1. G ------------------------------------------------------------------
-    for (int q = tid; q < c * c; q += NTH) {
-        double s = 0.0;
-        for (int g = 0; g < P.ng; ++g) s += gsrc[P.g0 + g][q];
-        A[(q / c) * LDA + q % c] = s;
-    }
-    for (int m = 0; m < P.nm; ++m) {
-        const double *R = msrc[P.m0 + m];
+#pragma unroll
+    for (int m = 0; m < RPW; ++m)
+#pragma unroll
+        for (int s = 0; s < CPL; ++s) {
+            const int R = wave + kWaves * m, C = lane + 64 * s;
+            double v = 0.0;
+            if (R < c && C < c)
+                for (int g = 0; g < P.ng; ++g) v += gsrc[P.g0 + g][R * c + C];
+            a[m][s] = v;
+        }
+    for (int mm = 0; mm < P.nm; ++mm) {
+        const double *Rm = msrc[P.m0 + mm];
         double *Rs = scr;                          // MR x c
         for (int r0 = 0; r0 < k; r0 += MR) {
             const int nr = min(MR, k - r0);
             __syncthreads();
-            for (int q = tid; q < nr * c; q += NTH) Rs[q] = R[(int64_t)r0 * c + q];
+            for (int q = tid; q < nr * c; q += NTH) Rs[q] = Rm[(int64_t)r0 * c + q];
             __syncthreads();
-            for (int q = tid; q < c * c; q += NTH) {
-                const int i = q / c, j = q % c;
-                double s2 = A[i * LDA + j];
-                for (int r = 0; r < nr; ++r) s2 = fma(Rs[r * c + i], Rs[r * c + j], s2);
-                A[i * LDA + j] = s2;
+#pragma unroll
+            for (int m = 0; m < RPW; ++m) {
+                const int R = wave + kWaves * m;
+                if (R >= c) continue;
+#pragma unroll
+                for (int s = 0; s < CPL; ++s) {
+                    const int C = lane + 64 * s;
+                    if (C >= c) continue;
+                    double v = a[m][s];
+                    for (int r = 0; r < nr; ++r) v = fma(Rs[r * c + R], Rs[r * c + C], v);
+                    a[m][s] = v;
+                }
             }
+        }
+    }
+
+    // ---- 2. tridiagonalisation Q^T G Q = T ---------------------------------------
+    // Step j annihilates row / column j beyond j+1 with H_j = I - tau_j v_j v_j^T
+    // (v_j(j+1) = 1) and applies H_j to the trailing block from both sides:
+    //   p = tau A v,  w = p - (tau/2)(p.v) v,  A <- A - v w^T - w v^T.
+    // Row j+1 is final after step j; the wave that holds it derives d, e and the
+    // next reflector from its registers while the other waves go on, so each
+    // step has three barriers.  Reflectors are kept in absolute indexing (zero
+    // outside (j, c)) in two alternating buffers.
+    double *part = scr;                            // 16 x NMAX wave partials of A v
+    double *vbuf = part + kWaves * NMAX;           // 2 x NMAX
+    double *psh = vbuf + 2 * NMAX;                 // NMAX
+    double *kpart = psh + NMAX;                    // 16
+    // Called by the wave that holds row jj once that row is final: x[s] is its
+    // element (jj, lane + 64 s).  Sets d_jj and, below the last two rows, the
+    // reflector of row jj (tau, e and the vector, also packed for later).
+    auto row_final = [&](int jj, const double (&x)[CPL]) {
+        double ss = 0.0;
+#pragma unroll
+        for (int s = 0; s < CPL; ++s) {
+            const int C = lane + 64 * s;
+            if (C > jj + 1 && C < c) ss = fma(x[s], x[s], ss);
+        }
+        ss = wave_sum64(ss);
+        auto elem = [&](int C) {                   // x at column C (C uniform), from its lane
+            double v = x[0];
+#pragma unroll
+            for (int s = 1; s < CPL; ++s)
+                if ((C >> 6) == s) v = x[s];
+            return readlane_d(v, C & 63);
+        };
+        const double alpha = jj + 1 < c ? elem(jj + 1) : 0.0;
+        const double dj = elem(jj);
+        if (lane == 0) d[jj] = dj;
+        if (jj + 2 < c) {
+            double t = 0.0, beta = alpha, scal = 0.0;
+            if (ss > 0.0) {
+                const double mu = sqrt(alpha * alpha + ss);
+                beta = alpha <= 0.0 ? mu : -mu;
+                t = (beta - alpha) / beta;
+                scal = 1.0 / (alpha - beta);
+            }
+            double *vn = vbuf + ((jj & 1) * NMAX);
+#pragma unroll
+            for (int s = 0; s < CPL; ++s) {
+                const int C = lane + 64 * s;
+                if (C >= NMAX) continue;
+                const double v = C == jj + 1 ? 1.0 : (C > jj + 1 && C < c ? x[s] * scal : 0.0);
+                vn[C] = v;
+                if (C > jj && C < c) A[hoff(jj) + C - jj - 1] = v;
+            }
+            if (lane == 0) {
+                tau[jj] = t;
+                e[jj] = beta;
+            }
+        } else if (jj + 2 == c) {
+            if (lane == 0) e[jj] = alpha;          // the last off-diagonal entry
+        }
+    };
+    // the wave holding row jj copies it out of its registers (unrolled selects)
+    auto take_row = [&](int jj, double (&x)[CPL]) {
+#pragma unroll
+        for (int s = 0; s < CPL; ++s) x[s] = 0.0;
+#pragma unroll
+        for (int m = 0; m < RPW; ++m)
+            if (wave + kWaves * m == jj)
+#pragma unroll
+                for (int s = 0; s < CPL; ++s) x[s] = a[m][s];
+    };
+
+    if (wave == 0) {
+        double x[CPL];
+        take_row(0, x);
+        row_final(0, x);
+    }
+    if (c == 2 && wave == 1) {
+        double x[CPL];
+        take_row(1, x);
+        const double d1 = readlane_d(x[0], 1);
+        if (lane == 0) d[1] = d1;
+    }
+    for (int j = 0; j + 2 < c; ++j) {
+        __syncthreads();                           // v_j and tau_j are visible
+        const double *vc = vbuf + (j & 1) * NMAX;
+        const double t = tau[j];
+        // v is zero outside (j, c), so rows and columns outside the live block
+        // contribute nothing and need no tests.
+        double vr[RPW], vcl[CPL];
+#pragma unroll
+        for (int m = 0; m < RPW; ++m) vr[m] = vc[wave + kWaves * m];
+#pragma unroll
+        for (int s = 0; s < CPL; ++s) vcl[s] = vc[min(lane + 64 * s, NMAX - 1)];
+        // partial A v over this wave's rows (A symmetric: column sums = row sums)
+        // and this wave's share of v^T A v
+        double pp[CPL];
+#pragma unroll
+        for (int s = 0; s < CPL; ++s) pp[s] = 0.0;
+#pragma unroll
+        for (int m = 0; m < RPW; ++m)
+#pragma unroll
+            for (int s = 0; s < CPL; ++s) pp[s] = fma(a[m][s], vr[m], pp[s]);
+        double vav = 0.0;
+#pragma unroll
+        for (int s = 0; s < CPL; ++s) {
+            if (lane + 64 * s < NMAX) part[wave * NMAX + lane + 64 * s] = pp[s];
+            if (lane + 64 * s < c) vav = fma(pp[s], vcl[s], vav);
+        }
+        vav = wave_sum64(vav);
+        if (lane == 0) kpart[wave] = vav;
+        __syncthreads();
+        // p = tau A v (pairwise sum of the 16 wave partials)
+        if (tid < c) {
+            double h[kWaves];
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) h[w] = part[w * NMAX + tid];
+#pragma unroll
+            for (int st = kWaves / 2; st >= 1; st /= 2)
+#pragma unroll
+                for (int w = 0; w < st; ++w) h[w] += h[w + st];
+            psh[tid] = t * h[0];
+        }
+        double kv[kWaves];
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) kv[w] = kpart[w];
+#pragma unroll
+        for (int st = kWaves / 2; st >= 1; st /= 2)
+#pragma unroll
+            for (int w = 0; w < st; ++w) kv[w] += kv[w + st];
+        const double K = 0.5 * t * t * kv[0];      // (tau/2) p.v with p.v = tau v^T A v
+        __syncthreads();
+        // A <- A - v w^T - w v^T, w = p - K v (zero outside the live block)
+        double wr[RPW], wcol[CPL];
+#pragma unroll
+        for (int m = 0; m < RPW; ++m) {
+            const int R = wave + kWaves * m;
+            const double pr = psh[R];
+            wr[m] = (R > j && R < c) ? pr - K * vr[m] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < CPL; ++s) {
+            const int C = lane + 64 * s;
+            const double pc = psh[min(C, NMAX - 1)];
+            wcol[s] = (C > j && C < c) ? pc - K * vcl[s] : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < RPW; ++m)
+#pragma unroll
+            for (int s = 0; s < CPL; ++s) {
+                a[m][s] = fma(-vr[m], wcol[s], a[m][s]);
+                a[m][s] = fma(-wr[m], vcl[s], a[m][s]);
+            }
+        // row j+1 is final: its holder prepares step j+1
+        if (wave == (j + 1) % kWaves) {
+            double x[CPL];
+            take_row(j + 1, x);
+            row_final(j + 1, x);
+        }
+        if (j + 3 == c && wave == (c - 1) % kWaves) {   // last step: row c-1 is final too
+            double x[CPL];
+            take_row(c - 1, x);
+            double v = x[0];
+#pragma unroll
+            for (int s = 1; s < CPL; ++s)
+                if (((c - 1) >> 6) == s) v = x[s];
+            const double xd = readlane_d(v, (c - 1) & 63);
+            if (lane == 0) d[c - 1] = xd;
         }
     }
     __syncthreads();
-
-    // ---- 2. tridiagonalisation (three barriers per reflector) -----------------------
-    double *vsh = scr;
-    double *psh = scr + NMAX;
-    for (int j = 0; j + 2 < c; ++j) {
-        const int n1 = c - j - 1;
-        // Householder vector of A[j+1:, j]; every wave computes the scalars itself.
-        double s = 0.0;
-        for (int i = j + 2 + lane; i < c; i += 64) s = fma(A[i * LDA + j], A[i * LDA + j], s);
-        s = wave_sum(s);
-        const double alpha = A[(j + 1) * LDA + j];
-        double t = 0.0, beta = alpha, scal = 0.0;
-        if (s > 0.0) {
-            const double mu = sqrt(alpha * alpha + s);
-            beta = alpha <= 0.0 ? mu : -mu;
-            t = (beta - alpha) / beta;
-            scal = 1.0 / (alpha - beta);
-        }
-        if (tid == 0) {
-            tau[j] = t;
-            e[j] = beta;
-            d[j] = A[j * LDA + j];
-        }
-        for (int i = tid; i < n1; i += NTH) vsh[i] = (i == 0) ? 1.0 : A[(j + 1 + i) * LDA + j] * scal;
-        __syncthreads();
-        // Pack v_j into rows <= j, which are no longer read (row j's diagonal was
-        // taken above); the packed range ends before row j+1.
-        for (int i = tid; i < n1; i += NTH) A[hoff(j) + i] = vsh[i];
-        if (t == 0.0) {                            // uniform: nothing to annihilate
-            __syncthreads();
-            continue;
-        }
-        // p = t * A22 v: eight threads per row (all rows in one pass)
-        {
-            const int row = tid / 8, sub = tid % 8;
-            double s0 = 0.0, s1 = 0.0;
-            if (row < n1) {
-                const double *ar = A + (j + 1 + row) * LDA + j + 1;
-                int col = sub;
-                for (; col + 8 < n1; col += 16) {
-                    s0 = fma(ar[col], vsh[col], s0);
-                    s1 = fma(ar[col + 8], vsh[col + 8], s1);
-                }
-                if (col < n1) s0 = fma(ar[col], vsh[col], s0);
-            }
-            double sum = s0 + s1;
-            sum += __shfl_xor(sum, 4, 64);
-            sum += __shfl_xor(sum, 2, 64);
-            sum += __shfl_xor(sum, 1, 64);
-            if (sub == 0 && row < n1) psh[row] = t * sum;
-        }
-        __syncthreads();
-        // K = t/2 p.v, computed by every wave; A22 -= v w^T + w v^T with w = p - K v.
-        // Thread (tr, ts) of a 32 x 32 grid keeps the v, w entries of its columns.
-        double sk = 0.0;
-        for (int i = lane; i < n1; i += 64) sk = fma(psh[i], vsh[i], sk);
-        const double K = 0.5 * t * wave_sum(sk);
-        const int tr = tid / 32, ts = tid % 32;
-        double vc[4], wc[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int s2 = ts + 32 * u;
-            vc[u] = s2 < n1 ? vsh[s2] : 0.0;
-            wc[u] = s2 < n1 ? psh[s2] - K * vc[u] : 0.0;
-        }
-        for (int r = tr; r < n1; r += 32) {
-            const double vr = vsh[r], wr = psh[r] - K * vr;
-            double *ar = A + (j + 1 + r) * LDA + j + 1;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int s2 = ts + 32 * u;
-                if (s2 < n1) ar[s2] -= vr * wc[u] + wr * vc[u];
-            }
-        }
-        __syncthreads();
-    }
     if (tid == 0) {
-        if (c >= 2) {
-            d[c - 2] = A[(c - 2) * LDA + c - 2];
-            e[c - 2] = A[(c - 1) * LDA + c - 2];
-        }
-        d[c - 1] = A[(c - 1) * LDA + c - 1];
         double gl = d[0], gu = d[0], emax2 = 0.0;
         for (int i = 0; i < c; ++i) {
             const double ei = i + 1 < c ? fabs(e[i]) : 0.0;
@@ -215,7 +315,6 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
         sh_a = gl - 2.1 * tn * __DBL_EPSILON__ * c - 4.2 * pivmin;
         sh_b = gu + 2.1 * tn * __DBL_EPSILON__ * c + 4.2 * pivmin;
     }
-    __syncthreads();                               // e[c - 2] was written by thread 0
     for (int i = tid; i + 1 < c; i += NTH) e2[i] = e[i] * e[i];
     __syncthreads();
     const double tnorm = sh_tnorm, pivmin = sh_pivmin;
@@ -226,55 +325,50 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
     }
 
     // ---- 3. the kk largest eigenvalues: multisection on Sturm counts ---------------
+    // Groups of G lanes inside one wave share an eigenvalue: each lane counts
+    // the eigenvalues below its point, a ballot finds the first point whose
+    // count exceeds the wanted index, and the interval shrinks G+1 times per
+    // round.  Waves run their rounds independently.
     {
-        const int G = min(NTH / kk, 64);
-        const int grp = tid / G, mem = tid % G;
-        const int m = c - 1 - grp;                 // ascending index of the wanted eigenvalue
-        double *xs = scr;                          // G * kk <= NTH
-        int *cs = reinterpret_cast<int *>(scr + NTH);
-        if (tid < kk) {
-            glo[tid] = sh_a;
-            ghi[tid] = sh_b;
-        }
+        const int G = kk <= 16 ? 64 : (kk <= 32 ? 32 : 16);
+        const int gpw = 64 / G;                    // groups per wave
+        const int gb = (lane / G) * G;             // first lane of this lane's group
+        const int grp = wave * gpw + lane / G;     // eigenvalue, largest first
+        const int mem = lane - gb;
+        const int m = c - 1 - grp;                 // its ascending index
         const double atol = 4.0 * __DBL_EPSILON__ * tnorm + 2.0 * pivmin;
+        double lo = sh_a, hi = sh_b;
+        bool live = grp < kk;
         for (int it = 0; it < 80; ++it) {
-            if (tid == 0) sh_done = 1;
-            __syncthreads();
-            if (grp < kk) {
-                const double lo = glo[grp], hi = ghi[grp];
-                const double x = lo + (hi - lo) * (double)(mem + 1) / (double)(G + 1);
-                double q = d[0] - x;
+            if (!__any(live)) break;               // wave-uniform exit
+            const double x = lo + (hi - lo) * (double)(mem + 1) / (double)(G + 1);
+            double q = d[0] - x;
+            if (fabs(q) < pivmin) q = -pivmin;
+            int cnt = q < 0.0;
+            // the next row's d and e^2 are loaded one step ahead, so that the LDS
+            // latency stays off the recurrence
+            double dn = d[min(1, c - 1)], en = e2[0];
+            for (int i = 1; i < c; ++i) {
+                const double di = dn, ei = en;
+                dn = d[min(i + 1, c - 1)];
+                en = e2[min(i, c - 2)];
+                q = (di - x) - ei / q;
                 if (fabs(q) < pivmin) q = -pivmin;
-                int cnt = q < 0.0;
-                for (int i = 1; i < c; ++i) {
-                    q = d[i] - x - e2[i - 1] / q;
-                    if (fabs(q) < pivmin) q = -pivmin;
-                    cnt += q < 0.0;
-                }
-                xs[tid] = x;
-                cs[tid] = cnt;
+                cnt += q < 0.0;
             }
-            __syncthreads();
-            if (grp < kk && mem == 0) {
-                double lo = glo[grp], hi = ghi[grp];
-                for (int u = 0; u < G; ++u) {
-                    if (cs[grp * G + u] <= m) {
-                        lo = xs[grp * G + u];
-                    } else {
-                        hi = xs[grp * G + u];
-                        break;
-                    }
-                }
-                glo[grp] = lo;
-                ghi[grp] = hi;
-                if (hi - lo > atol) sh_done = 0;
+            const uint64_t above = __ballot(cnt > m);
+            const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+            const uint64_t bits = (above >> gb) & gmask;
+            const int f = bits ? __builtin_ctzll(bits) : G;   // first point above
+            const double xf = __shfl(x, gb + min(f, G - 1), 64);
+            const double xp = __shfl(x, gb + max(f - 1, 0), 64);
+            if (live) {
+                if (f < G) hi = xf;
+                if (f > 0) lo = xp;
+                if (hi - lo <= atol) live = false;
             }
-            __syncthreads();
-            const int done = sh_done;
-            __syncthreads();
-            if (done) break;
         }
-        if (tid < kk) lam[tid] = 0.5 * (glo[tid] + ghi[tid]);
+        if (grp < kk && mem == 0) lam[grp] = 0.5 * (lo + hi);
     }
     __syncthreads();
     // clusters of consecutive eigenvalues closer than 1e-9 ||T||
@@ -288,80 +382,106 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
     }
     __syncthreads();
 
-    // ---- 4. inverse iteration: one thread per cluster, members in order ----------
-    //      Z (c x kk) follows the packed vectors; each solver thread keeps four
-    //      length-c arrays after Z, interleaved by thread (element i at i * NT + t).
+    // ---- 4. inverse iteration: one lane of wave 0 per cluster, members in order ----
+    //      Z (c x kk) follows the packed vectors.  Each solver lane keeps the U
+    //      factor of T - lambda I (reciprocal diagonal and two superdiagonals) in
+    //      three length-c arrays after Z, interleaved by lane (element i at
+    //      i * NT + lane); the eliminated right-hand side overwrites z in place.
+    //      The recurrences load the next row of T and of z one step ahead, so
+    //      that LDS latency stays off the dependence chain.
     const int hp = c >= 3 ? hoff(c - 2) : 0;        // packed length
     double *Z = A + hp;
-    {
+    if (wave == 0) {
         double *lu = Z + c * kk;
-        const int NT = min((int)((A + L::REGION - lu) / (4 * c)), NTH);
+        const int NT = min((int)((A + L::REGION - lu) / (3 * c)), 64);
         const int ncl = sh_ncl;
         const double pivfloor = __DBL_EPSILON__ * tnorm;
         for (int cb = 0; cb < ncl; cb += NT) {
-            const int cl = cb + tid;
-            if (tid < NT && cl < ncl) {
-                double *u1 = lu + tid, *u2 = u1 + c * NT, *u3 = u2 + c * NT, *rr = u3 + c * NT;
-                for (int g = cl_start[cl]; g < cl_start[cl + 1]; ++g) {
-                    const double lmb = lam[g];
-                    double *z = Z + g;                 // column g, stride kk
-                    int attempt = 0;
+            const int cl = cb + lane;
+            const bool act = lane < NT && cl < ncl;
+            double *u1 = lu + min(lane, NT - 1), *u2 = u1 + c * NT, *u3 = u2 + c * NT;
+            const int g0 = act ? cl_start[cl] : 0, g1 = act ? cl_start[cl + 1] : 0;
+            // members of every lane's cluster in step (lanes with fewer idle)
+            int gmax = g1 - g0;
+            for (int off = 32; off >= 1; off >>= 1) gmax = max(gmax, __shfl_xor(gmax, off, 64));
+            for (int gi = 0; gi < gmax; ++gi) {
+                const bool on = gi < g1 - g0;
+                const int g = on ? g0 + gi : 0;
+                const double lmb = on ? lam[g] : 0.0;
+                double *z = Z + g;                 // column g, stride kk
+                int attempt = 0;
+                if (on)
                     for (int i = 0; i < c; ++i) z[i * kk] = start_value(i, g, attempt);
-                    for (int it = 0; it < 2; ++it) {
-                        // LU with partial pivoting of T - lmb I, applied to z.
+                for (int it = 0; it < 2; ++it) {
+                    if (on) {
+                        // LU with partial pivoting of T - lmb I, applied to z.  The
+                        // next row of T and of z is loaded one step ahead.
                         double p0 = d[0] - lmb, p1 = c > 1 ? e[0] : 0.0, r = z[0];
+                        double svn = e[0], ddn = d[min(1, c - 1)], een = e[min(1, c - 1)];
+                        double znn = z[min(1, c - 1) * kk];
                         for (int i = 0; i + 1 < c; ++i) {
-                            const double sv = e[i], dd = d[i + 1] - lmb;
-                            const double ee = (i + 2 < c) ? e[i + 1] : 0.0;
-                            const double zn = z[(i + 1) * kk];
-                            if (fabs(sv) > fabs(p0)) {       // swap rows i and i+1
-                                const double mlt = p0 / sv;
-                                u1[i * NT] = sv; u2[i * NT] = dd; u3[i * NT] = ee; rr[i * NT] = zn;
-                                const double np0 = p1 - mlt * dd;
-                                p1 = -mlt * ee;
-                                r = r - mlt * zn;
-                                p0 = np0;
-                            } else {
-                                double piv = p0;
-                                if (fabs(piv) < pivfloor) piv = piv < 0.0 ? -pivfloor : pivfloor;
-                                const double mlt = sv / piv;
-                                u1[i * NT] = piv; u2[i * NT] = p1; u3[i * NT] = 0.0; rr[i * NT] = r;
-                                p0 = dd - mlt * p1;
-                                p1 = ee;
-                                r = zn - mlt * r;
-                            }
+                            const double sv = svn, dd = ddn - lmb, ee = (i + 2 < c) ? een : 0.0;
+                            const double zn = znn;
+                            const int i2 = min(i + 2, c - 1);
+                            svn = e[i + 1];
+                            ddn = d[i2];
+                            een = e[i2];
+                            znn = z[i2 * kk];
+                            // pivot on the larger of p0 and the subdiagonal entry
+                            const bool swap = fabs(sv) > fabs(p0);
+                            double piv = p0;
+                            if (fabs(piv) < pivfloor) piv = piv < 0.0 ? -pivfloor : pivfloor;
+                            const double den = swap ? sv : piv;
+                            const double inv = 1.0 / den;
+                            const double mlt = (swap ? p0 : sv) * inv;
+                            u1[i * NT] = inv;
+                            u2[i * NT] = swap ? dd : p1;
+                            u3[i * NT] = swap ? ee : 0.0;
+                            z[i * kk] = swap ? zn : r;
+                            const double np0 = swap ? p1 - mlt * dd : dd - mlt * p1;
+                            const double np1 = swap ? -mlt * ee : ee;
+                            r = swap ? r - mlt * zn : zn - mlt * r;
+                            p0 = np0;
+                            p1 = np1;
                         }
                         if (fabs(p0) < pivfloor) p0 = p0 < 0.0 ? -pivfloor : pivfloor;
                         double y2 = 0.0, y1 = r / p0;
                         z[(c - 1) * kk] = y1;
+#pragma unroll 4
                         for (int i = c - 2; i >= 0; --i) {
-                            const double y = (rr[i * NT] - u2[i * NT] * y1 - u3[i * NT] * y2) / u1[i * NT];
+                            const double y = (z[i * kk] - u2[i * NT] * y1 - u3[i * NT] * y2) * u1[i * NT];
                             z[i * kk] = y;
                             y2 = y1;
                             y1 = y;
                         }
                         // Gram-Schmidt against earlier members of the cluster, normalise
-                        for (int h = cl_start[cl]; h < g; ++h) {
+                        for (int h = g0; h < g; ++h) {
                             const double *zh = Z + h;
                             double sd = 0.0;
                             for (int i = 0; i < c; ++i) sd = fma(zh[i * kk], z[i * kk], sd);
                             for (int i = 0; i < c; ++i) z[i * kk] -= sd * zh[i * kk];
                         }
-                        double nrm = 0.0;
-                        for (int i = 0; i < c; ++i) nrm = fma(z[i * kk], z[i * kk], nrm);
+                        double n0 = 0.0, n1 = 0.0;
+#pragma unroll 4
+                        for (int i = 0; i + 1 < c; i += 2) {
+                            n0 = fma(z[i * kk], z[i * kk], n0);
+                            n1 = fma(z[(i + 1) * kk], z[(i + 1) * kk], n1);
+                        }
+                        if (c & 1) n0 = fma(z[(c - 1) * kk], z[(c - 1) * kk], n0);
+                        const double nrm = n0 + n1;
                         if (!(nrm > 0.0) || !isfinite(nrm)) {
                             ++attempt;               // restart from another vector
                             for (int i = 0; i < c; ++i) z[i * kk] = start_value(i, g, attempt);
                             continue;
                         }
-                        const double inv = 1.0 / sqrt(nrm);
-                        for (int i = 0; i < c; ++i) z[i * kk] *= inv;
+                        const double sc = 1.0 / sqrt(nrm);
+                        for (int i = 0; i < c; ++i) z[i * kk] *= sc;
                     }
                 }
             }
-            __syncthreads();
         }
     }
+    __syncthreads();
 
     // ---- 5. back-transformation x = H_0 H_1 ... H_{c-3} z, columns in registers ----
     {
@@ -386,10 +506,8 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
 #pragma unroll
                 for (int u = 0; u < CPW; ++u) sv[u] = fma(v0, z0[u], v1 * z1[u]);
 #pragma unroll
-                for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-                    for (int u = 0; u < CPW; ++u)
-                        if (u < ncol) sv[u] += __shfl_xor(sv[u], off, 64);
+                for (int u = 0; u < CPW; ++u)
+                    if (u < ncol) sv[u] = wave_sum64(sv[u]);
 #pragma unroll
                 for (int u = 0; u < CPW; ++u) {
                     z0[u] -= t * sv[u] * v0;
@@ -418,7 +536,7 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
                 for (int h = wave; h < g; h += kWaves) {
                     double sd = 0.0;
                     for (int i = lane; i < c; i += 64) sd = fma(Z[i * kk + h], Z[i * kk + g], sd);
-                    sd = wave_sum(sd);
+                    sd = wave_sum64(sd);
                     if (lane == 0) dots[h] = sd;
                 }
                 __syncthreads();
@@ -430,7 +548,7 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
                 __syncthreads();
                 double sn = 0.0;
                 for (int i = lane; i < c; i += 64) sn = fma(Z[i * kk + g], Z[i * kk + g], sn);
-                const double nrm2 = wave_sum(sn);  // every wave computes the same norm
+                const double nrm2 = wave_sum64(sn);  // every wave computes the same norm
                 __syncthreads();
                 if (pass == 1 && nrm2 < 0.25 && attempt < c) {
                     // collapsed inside a degenerate eigenspace: try the next unit vector

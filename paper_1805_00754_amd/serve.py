@@ -5,8 +5,8 @@ HBM and answers the queries in batches through ``zs_query_batch``:
 
 * admission: a batch takes pending requests first-come first-served while it
   stays within ``max_queries`` and an HBM byte budget for its outputs
-  (U n x k_q, Sigma k_q, V c x k_q in FP64, k_out); a request whose outputs
-  alone exceed the budget is rejected;
+  (U n x k_q and V c x k_q in the store's output type, Sigma k_q in FP64,
+  k_out); a request whose outputs alone exceed the budget is rejected;
 * continuous batching: up to ``depth`` batches are in flight on one stream, so
   the host plans and enqueues the next batch while the GPU runs the current
   one; a new batch is formed as soon as a slot is free and requests wait;
@@ -27,9 +27,10 @@ import time
 import numpy as np
 
 
-def output_bytes(n: int, kq: int, c: int) -> int:
-    """Device bytes of one query's outputs: U, Sigma, V (FP64) and k_out."""
-    return 8 * (n * kq + kq + c * kq) + 4
+def output_bytes(n: int, kq: int, c: int, esize: int = 8) -> int:
+    """Device bytes of one query's outputs: U and V with `esize`-byte elements
+    (8 for FP64 stores, 4 for FP32-stored factors), Sigma in FP64, k_out."""
+    return esize * (n * kq + c * kq) + 8 * kq + 4
 
 
 @dataclasses.dataclass
@@ -44,22 +45,26 @@ class Request:
 class BatchPolicy:
     """First-come first-served packing under a query count and a byte budget."""
 
-    def __init__(self, c: int, max_queries: int, budget_bytes: int):
+    def __init__(self, c: int, max_queries: int, budget_bytes: int, esize: int = 8):
         if max_queries < 1 or budget_bytes < 1:
             raise ValueError("max_queries and budget_bytes must be positive")
         self.c = c
         self.max_queries = max_queries
         self.budget_bytes = budget_bytes
+        self.esize = esize
+
+    def bytes_of(self, r: Request) -> int:
+        return output_bytes(r.t_e - r.t_s, r.k_q, self.c, self.esize)
 
     def fits_alone(self, r: Request) -> bool:
-        return output_bytes(r.t_e - r.t_s, r.k_q, self.c) <= self.budget_bytes
+        return self.bytes_of(r) <= self.budget_bytes
 
     def take(self, pending: collections.deque) -> list:
         """Removes and returns the next batch from the head of `pending`."""
         batch, used = [], 0
         while pending and len(batch) < self.max_queries:
             r = pending[0]
-            b = output_bytes(r.t_e - r.t_s, r.k_q, self.c)
+            b = self.bytes_of(r)
             if used + b > self.budget_bytes:
                 break
             batch.append(pending.popleft())
@@ -84,13 +89,17 @@ class Server:
         self.zs = zs
         self.torch = torch
         self.st = st
-        self.policy = BatchPolicy(st.c, max_queries, budget_bytes)
+        esize = torch.empty((), dtype=st.out_dtype).element_size()
+        self.policy = BatchPolicy(st.c, max_queries, budget_bytes, esize)
         self.depth = depth
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         dev = torch.device("cuda", torch.cuda.current_device())
-        # one output arena per in-flight slot: U, S and V share a flat FP64 buffer
-        self.arena = [torch.empty(budget_bytes // 8, dtype=torch.float64, device=dev)
+        # one output arena per in-flight slot: U and V share a flat buffer of the
+        # store's output type, Sigma has an FP64 one
+        self.arena = [torch.empty(budget_bytes // esize, dtype=st.out_dtype, device=dev)
                       for _ in range(depth)]
+        self.sarena = [torch.empty(max_queries * st.k, dtype=torch.float64, device=dev)
+                       for _ in range(depth)]
         self.kout = [torch.empty(max_queries, dtype=torch.int32, device=dev) for _ in range(depth)]
 
     def _launch(self, slot: int, batch: list):
@@ -100,13 +109,12 @@ class Server:
         sizes_u = n * kq
         u_off = np.zeros(len(batch), np.int64)
         u_off[1:] = np.cumsum(sizes_u)[:-1]
-        s_base = int(sizes_u.sum())
-        s_off = s_base + np.concatenate(([0], np.cumsum(kq)[:-1])).astype(np.int64)
-        v_base = s_base + int(kq.sum())
+        s_off = np.concatenate(([0], np.cumsum(kq)[:-1])).astype(np.int64)
+        v_base = int(sizes_u.sum())
         v_off = v_base + np.concatenate(([0], np.cumsum(c * kq.astype(np.int64))[:-1])).astype(np.int64)
         a = self.arena[slot]
         self.zs.zs_query_batch_into(self.st, [r.t_s for r in batch], [r.t_e for r in batch], kq,
-                                    a, u_off, a, s_off, a, v_off, self.kout[slot],
+                                    a, u_off, self.sarena[slot], s_off, a, v_off, self.kout[slot],
                                     stream=self.stream)
         done = self.torch.cuda.Event(enable_timing=True)
         done.record(self.stream)
@@ -115,7 +123,8 @@ class Server:
     def run(self, requests: list, on_batch=None) -> dict:
         """Serves `requests` (sorted by arrival) in real time.  Returns per-request
         completion times and latencies (seconds) and batch statistics.
-        `on_batch(info, arena, kout)` is called after a batch completes (tests)."""
+        `on_batch(info, arena, sarena, kout)` is called after a batch completes
+        (tests): U and V of the batch are in `arena`, Sigma in `sarena`."""
         torch = self.torch
         n = len(requests)
         completion = np.full(n, np.nan)
@@ -140,7 +149,8 @@ class Server:
                 completion[r.idx] = t_done
             finished += len(info["batch"])
             if on_batch is not None:
-                on_batch(info, self.arena[info["slot"]], self.kout[info["slot"]])
+                on_batch(info, self.arena[info["slot"]], self.sarena[info["slot"]],
+                         self.kout[info["slot"]])
             free.append(info["slot"])
 
         while finished + len(rejected) < n:

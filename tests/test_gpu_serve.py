@@ -11,11 +11,20 @@ from tests.gpu_common import say, to_dev
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("max_queries,budget,rate", [(16, 600 << 10, 20000.0), (64, 64 << 20, 4000.0)])
-def test_served_equals_single(max_queries, budget, rate):
+@pytest.mark.parametrize("max_queries,budget,rate,mode", [
+    (16, 600 << 10, 20000.0, "fp64"),
+    (64, 64 << 20, 4000.0, "fp64"),
+    (16, 300 << 10, 20000.0, "fp32"),
+])
+def test_served_equals_single(max_queries, budget, rate, mode):
     zs.load()
     ser, cfg = synth.workload("sinmix_10k_x64_f64")
-    st = zs.zs_store_blocks(to_dev(ser.A), cfg["b"], cfg["k"])
+    if mode == "fp64":
+        st = zs.zs_store_blocks(to_dev(ser.A), cfg["b"], cfg["k"])
+    else:
+        st = zs.zs_store_blocks(to_dev(ser.A, torch.float32), cfg["b"], cfg["k"],
+                                mode=zs.ZS_MODE_FP32)
+    esize = 8 if mode == "fp64" else 4
     torch.cuda.synchronize()
     rng = synth.rng_for(77)
     reqs = serve.make_requests(rng, st.t, 120, rate, 150, 8000, [3, 10])
@@ -25,19 +34,20 @@ def test_served_equals_single(max_queries, budget, rate):
     srv = serve.Server(st, max_queries=max_queries, budget_bytes=budget)
     got = {}
 
-    def on_batch(info, arena, kout):
+    def on_batch(info, arena, sarena, kout):
         for q, r in enumerate(info["batch"]):
             n = r.t_e - r.t_s
             U = arena[info["u_off"][q]:info["u_off"][q] + n * r.k_q].view(n, r.k_q)
-            S = arena[info["s_off"][q]:info["s_off"][q] + r.k_q]
+            S = sarena[info["s_off"][q]:info["s_off"][q] + r.k_q]
             V = arena[info["v_off"][q]:info["v_off"][q] + st.c * r.k_q].view(st.c, r.k_q)
             got[r.idx] = (U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy(), int(kout[q].item()))
 
     say("serve", max_queries, budget, rate)
     res = srv.run(reqs, on_batch=on_batch)
-    too_big = {r.idx for r in reqs if serve.output_bytes(r.t_e - r.t_s, r.k_q, st.c) > budget}
+    too_big = {r.idx for r in reqs
+               if serve.output_bytes(r.t_e - r.t_s, r.k_q, st.c, esize) > budget}
     assert set(res["rejected"]) == too_big
-    assert (big.idx in too_big) == (budget < (1 << 20))
+    assert big.idx in too_big or budget > (1 << 20)
     assert sum(res["batches"]) == len(got)
     assert max(res["batches"]) <= max_queries
     for r in reqs:

@@ -14,6 +14,18 @@ def req(i, n, kq, arrival=0.0):
 def test_output_bytes():
     # U n x kq, Sigma kq, V c x kq in FP64 plus the int32 rank
     assert serve.output_bytes(100, 4, 10) == 8 * (400 + 4 + 40) + 4
+    # FP32-stored factors: U and V in FP32, Sigma still FP64
+    assert serve.output_bytes(100, 4, 10, esize=4) == 4 * (400 + 40) + 8 * 4 + 4
+
+
+def test_budget_counts_the_output_element_size():
+    one32 = serve.output_bytes(100, 2, 4, esize=4)
+    pol = serve.BatchPolicy(c=4, max_queries=100, budget_bytes=2 * one32, esize=4)
+    pending = collections.deque([req(i, 100, 2) for i in range(3)])
+    assert [r.idx for r in pol.take(pending)] == [0, 1]
+    pol64 = serve.BatchPolicy(c=4, max_queries=100, budget_bytes=2 * one32, esize=8)
+    pending = collections.deque([req(i, 100, 2) for i in range(3)])
+    assert [r.idx for r in pol64.take(pending)] == [0]
 
 
 def test_fifo_order_and_query_cap():
