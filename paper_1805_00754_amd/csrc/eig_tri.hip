@@ -328,9 +328,12 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
     // Groups of G lanes inside one wave share an eigenvalue: each lane counts
     // the eigenvalues below its point, a ballot finds the first point whose
     // count exceeds the wanted index, and the interval shrinks G+1 times per
-    // round.  Waves run their rounds independently.
+    // round.  Waves run their rounds independently.  A Sturm count is a chain
+    // of c divisions, so G is chosen to keep about 256 lanes busy (one wave per
+    // SIMD): more lanes would make the rounds issue-bound, fewer would add
+    // rounds of the same latency.
     {
-        const int G = kk <= 16 ? 64 : (kk <= 32 ? 32 : 16);
+        const int G = kk <= 4 ? 64 : (kk <= 8 ? 32 : (kk <= 16 ? 16 : (kk <= 32 ? 8 : 4)));
         const int gpw = 64 / G;                    // groups per wave
         const int gb = (lane / G) * G;             // first lane of this lane's group
         const int grp = wave * gpw + lane / G;     // eigenvalue, largest first
