@@ -175,52 +175,52 @@ __device__ __forceinline__ void wave_sync()
 
 // stack_project: one wave per chunk of pieces, tiles of 64 stack rows.  Row r
 // of a tile is s_r x_r with x_r = V_(i)^T row j of the store (s_r = sigma_ij)
-// for a whole block, or Partial-SVD row j (s_r = 1); lane r holds its row
-// pointer.  Rows come into LDS in 16-column panels (coalesced loads through
-// the lanes' row pointers) and the tile product X V_k runs on the matrix
-// cores (FP64 MFMA 16x16x4; A fragments from the LDS panel, B fragments of
-// V_k loaded per panel), four row blocks times ceil(kq / 16) column blocks.
-// Operand layout: A(i, s) in lane i + 16 s, B(s, j) in lane j + 16 s, D(i, j)
-// in register i / 4 of lane j + 16 (i mod 4).  Rows are scaled by s_r on the
-// way to LDS; the Y tile is stored with coalesced stores, and its Gram
-// Y^T Y is accumulated from LDS: lane g owns entries (a, b0..b0+3) of group
-// g = a * nb4 + b0 / 4.
+// for a whole block, or Partial-SVD row j (s_r = 1).  Lane r loads its own
+// row, 16 columns at a time (128 contiguous bytes), into an LDS panel, and the
+// tile product X V_k runs on the matrix cores (FP64 MFMA 16x16x4; A fragments
+// from the LDS panel, B fragments of V_k loaded per panel), four row blocks
+// times ceil(kq / 16) column blocks.  Operand layout: A(i, s) in lane i + 16 s,
+// B(s, j) in lane j + 16 s, D(i, j) in register i / 4 of lane j + 16 (i mod 4).
+// The scaled tile Y = S X V_k goes out through LDS with coalesced stores.  Its
+// Gram Y^T Y is accumulated on the matrix cores straight from the D
+// fragments: register v of block (rb, cb) holds Y(16 rb + 4 v + s, 16 cb + i)
+// in lane i + 16 s, which is the A layout of (Y^T)(16 cb + i, s) and the B
+// layout of Y(s, 16 cb' + j), so each pair of column blocks takes 16 MFMAs
+// per tile and no LDS traffic.
 constexpr int kPanel = 16;
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef const double __attribute__((address_space(1))) gdouble;
 typedef const float __attribute__((address_space(1))) gfloat;
 
 template <int KQM>
-__global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const Piece *__restrict__ pieces,
-                                                           const double *__restrict__ Mp,
-                                                           const StackChunk *__restrict__ chunks,
-                                                           const double *__restrict__ Vk,
-                                                           double *__restrict__ Y,
-                                                           double *__restrict__ GYpart)
+__device__ __forceinline__ void stack_project_body(StoreView st, const Piece *__restrict__ pieces,
+                                                   const double *__restrict__ Mp,
+                                                   const StackChunk *__restrict__ chunks,
+                                                   const double *__restrict__ Vk,
+                                                   double *__restrict__ Y,
+                                                   double *__restrict__ GYpart)
 {
     extern __shared__ __align__(16) double sm[];
-    constexpr int NB4 = (KQM + 3) / 4;
-    constexpr int NPASS = (KQM * NB4 + 63) / 64;
     constexpr int NCB = (KQM + 15) / 16;           // 16-column blocks of Y
     const StackChunk ch = chunks[blockIdx.x];
     const int c = (int)st.c, k = st.k, kq = ch.kk;
     const int lane = threadIdx.x;
     const double *__restrict__ V = Vk + (int64_t)ch.prob * c * kMaxK;   // c x kq, row-major
     const int rows = ch.npieces * k;
-    const int nb4 = (kq + 3) / 4;
     const int ldy = kq + 1;
-    double gy[NPASS][4];
+    v4d gacc[NCB][NCB];
 #pragma unroll
-    for (int p = 0; p < NPASS; ++p)
+    for (int ci = 0; ci < NCB; ++ci)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) gy[p][u] = 0.0;
+        for (int cj = 0; cj < NCB; ++cj) gacc[ci][cj] = (v4d){0.0, 0.0, 0.0, 0.0};
 
     for (int r0 = 0; r0 < rows; r0 += 64) {
         const int nr = min(64, rows - r0);
-        // the lane's stack row: FP64 Partial-SVD rows, or store rows of the
-        // store's element type (xf = 1: float)
+        // the lane's stack row: an FP64 Partial-SVD row, or a store row of the
+        // store's element type (xf: float); rows past the tile read row 0 of
+        // the store with scale 0
         const char *xp = static_cast<const char *>(st.Vt);
-        int xf = st.f32;
+        bool xf = st.f32 != 0;
         double scale = 0.0;
         if (lane < nr) {
             const int r = r0 + lane;
@@ -228,37 +228,30 @@ __global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const P
             const int j = r % k;
             if (pc.t_idx >= 0) {
                 xp = reinterpret_cast<const char *>(Mp + ((int64_t)pc.t_idx * k + j) * c);
-                xf = 0;
+                xf = false;
                 scale = 1.0;
             } else {
                 xp += (pc.blk * k + j) * c * (st.f32 ? sizeof(float) : sizeof(double));
                 scale = st.S[pc.blk * k + j];
             }
         }
-        const uint64_t xa = reinterpret_cast<uint64_t>(xp);
+        const gdouble *xd = reinterpret_cast<const gdouble *>(reinterpret_cast<uintptr_t>(xp));
+        const gfloat *xs = reinterpret_cast<const gfloat *>(reinterpret_cast<uintptr_t>(xp));
         v4d acc[4][NCB];
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = (v4d){0.0, 0.0, 0.0, 0.0};
-        for (int a0 = 0; a0 < c; a0 += kPanel) {
-            wave_sync();
-            // panel: 64 rows x 16 columns, 16 lanes per row, 4 rows per step;
-            // all 16 loads are issued before the first LDS write
-            const int col = a0 + lane % 16;
-            const int colc = min(col, c - 1);          // in bounds for every lane
-            double v[16];
+        // this lane's row, columns a0 .. a0 + 15 (zero past c), and the B
+        // fragments B(s, j) = V_k(a0 + 4 t + s, 16 cb + j), zero outside c x kq
+        auto load_panel = [&](int a0, double (&v)[kPanel], double (&bf)[NCB][4]) {
+            if (xf) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int row = i * 4 + lane / 16;
-                const uint32_t lo = __shfl((uint32_t)xa, row, 64);
-                const uint32_t hi = __shfl((uint32_t)(xa >> 32), row, 64);
-                const uint64_t ra = ((uint64_t)hi << 32) | lo;
-                v[i] = __shfl(xf, row, 64) ? (double)reinterpret_cast<gfloat *>(ra)[colc]
-                                           : reinterpret_cast<gdouble *>(ra)[colc];
+                for (int i = 0; i < kPanel; ++i) v[i] = a0 + i < c ? (double)xs[a0 + i] : 0.0;
+            } else {
+#pragma unroll
+                for (int i = 0; i < kPanel; ++i) v[i] = a0 + i < c ? xd[a0 + i] : 0.0;
             }
-            // B fragments: B(s, j) = V_k(a0 + 4 t + s, 16 cb + j), zero outside c x kq
-            double bf[NCB][4];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -267,9 +260,23 @@ __global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const P
                     const double x = V[min(vr, c - 1) * kq + min(vc, kq - 1)];
                     bf[cb][t] = (vr < c && vc < kq) ? x : 0.0;
                 }
+        };
+        // up to 32 columns one panel is in flight ahead of the matrix-core
+        // work; wider tiles have no registers to spare for it
+        constexpr bool kAhead = KQM <= 32;
+        double v[kPanel], bn[NCB][4];
+        if (kAhead) load_panel(0, v, bn);
+        for (int a0 = 0; a0 < c; a0 += kPanel) {
+            if (!kAhead) load_panel(a0, v, bn);
+            wave_sync();
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                sm[(i * 4 + lane / 16) * (kPanel + 1) + lane % 16] = col < c ? v[i] : 0.0;
+            for (int i = 0; i < kPanel; ++i) sm[lane * (kPanel + 1) + i] = v[i];
+            double bf[NCB][4];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) bf[cb][t] = bn[cb][t];
+            if (kAhead && a0 + kPanel < c) load_panel(a0 + kPanel, v, bn);
             wave_sync();
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
@@ -281,18 +288,37 @@ __global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const P
                         acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[cb][t], acc[rb][cb], 0, 0, 0);
                 }
         }
+        // scale the rows: D(i, j) of a 16 x 16 block sits in register i / 4 of
+        // lane j + 16 (i mod 4)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double sc = __shfl(scale, 16 * rb + 4 * v + lane / 16, 64);
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) acc[rb][cb][v] *= sc;
+            }
+        // Gram of the tile on the matrix cores
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int ci = 0; ci < NCB; ++ci)
+#pragma unroll
+                    for (int cj = 0; cj < NCB; ++cj)
+                        gacc[ci][cj] = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[rb][ci][v], acc[rb][cj][v],
+                                                                            gacc[ci][cj], 0, 0, 0);
         wave_sync();
-        // D(i, j) of a 16 x 16 block sits in register i / 4 of lane j + 16 (i mod 4)
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = 16 * rb + 4 * v + lane / 16;
-                const double sc = __shfl(scale, row, 64);
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) {
                     const int col = 16 * cb + lane % 16;
-                    if (col < kq) sm[row * ldy + col] = sc * acc[rb][cb][v];
+                    if (col < kq) sm[row * ldy + col] = acc[rb][cb][v];
                 }
             }
         wave_sync();
@@ -304,32 +330,37 @@ __global__ __launch_bounds__(64) void stack_project_kernel(StoreView st, const P
                 Yt[e] = sm[rr * ldy + (e - rr * kq)];
             }
         }
-        // Gram of the tile: entries (a, b0..b0+3) per lane and pass
-#pragma unroll
-        for (int p = 0; p < NPASS; ++p) {
-            const int g = lane + 64 * p;
-            if (g < kq * nb4) {
-                const int a = g / nb4, b0 = 4 * (g - a * nb4);
-                for (int rr = 0; rr < nr; ++rr) {
-                    const double *yr = sm + rr * ldy;
-                    const double ya = yr[a];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) gy[p][u] = fma(ya, yr[b0 + u], gy[p][u]);
-                }
-            }
-        }
     }
     double *G = GYpart + (int64_t)ch.slot * kSlotK;
 #pragma unroll
-    for (int p = 0; p < NPASS; ++p) {
-        const int g = lane + 64 * p;
-        if (g < kq * nb4) {
-            const int a = g / nb4, b0 = 4 * (g - a * nb4);
+    for (int ci = 0; ci < NCB; ++ci)
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (b0 + u < kq) G[a * kq + b0 + u] = gy[p][u];
-        }
-    }
+        for (int cj = 0; cj < NCB; ++cj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = 16 * ci + 4 * v + lane / 16, b2 = 16 * cj + lane % 16;
+                if (a < kq && b2 < kq) G[a * kq + b2] = gacc[ci][cj][v];
+            }
+}
+
+// Up to 32 columns the kernel fits two waves per SIMD in registers; wider
+// tiles keep the compiler's choice (more registers, no spills).
+template <int KQM>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void stack_project_kernel(
+    StoreView st, const Piece *__restrict__ pieces, const double *__restrict__ Mp,
+    const StackChunk *__restrict__ chunks, const double *__restrict__ Vk, double *__restrict__ Y,
+    double *__restrict__ GYpart)
+{
+    stack_project_body<KQM>(st, pieces, Mp, chunks, Vk, Y, GYpart);
+}
+
+template <int KQM>
+__global__ __launch_bounds__(64) void stack_project_wide_kernel(
+    StoreView st, const Piece *__restrict__ pieces, const double *__restrict__ Mp,
+    const StackChunk *__restrict__ chunks, const double *__restrict__ Vk, double *__restrict__ Y,
+    double *__restrict__ GYpart)
+{
+    stack_project_body<KQM>(st, pieces, Mp, chunks, Vk, Y, GYpart);
 }
 
 template <typename TU>
@@ -398,11 +429,13 @@ hipError_t run_stack_project(StoreView st, const Piece *pieces, const double *Mp
                              const StackChunk *chunks, int nchunks, int kq_max, const double *Vk,
                              double *Y, double *GYpart, hipStream_t stream)
 {
-    // panel (64 x 17) or Y tile (64 x (kq + 1)), plus 4 doubles read past the
-    // last row by the Gram groups
+    // panel (64 x 17) or Y tile (64 x (kq + 1))
     const int w = kq_max + 1 > kPanel + 1 ? kq_max + 1 : kPanel + 1;
-    const size_t lds = (size_t)(64 * w + 4) * sizeof(double);
-    stack_project_kernel<KQM><<<nchunks, 64, lds, stream>>>(st, pieces, Mp, chunks, Vk, Y, GYpart);
+    const size_t lds = (size_t)(64 * w) * sizeof(double);
+    if constexpr (KQM <= 32)
+        stack_project_kernel<KQM><<<nchunks, 64, lds, stream>>>(st, pieces, Mp, chunks, Vk, Y, GYpart);
+    else
+        stack_project_wide_kernel<KQM><<<nchunks, 64, lds, stream>>>(st, pieces, Mp, chunks, Vk, Y, GYpart);
     return hipGetLastError();
 }
 

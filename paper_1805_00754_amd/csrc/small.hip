@@ -227,15 +227,23 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *_
     }
 }
 
-template <typename TU>
-__global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
+constexpr int kPartialRows = 16;   // rows of P staged in LDS at a time
+
+// Up to two Gram entries per thread the kernel is held to 64 registers, so
+// that eight blocks (32 waves) share a CU and a batch's boundary blocks run in
+// one round.
+template <int EPT> struct PartialOcc { static constexpr int waves = EPT <= 2 ? 8 : 1; };
+
+template <typename TU, int EPT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PartialOcc<EPT>::waves)))
+void partial_kernel(StoreView st,
                                                            const Piece *__restrict__ pieces,
                                                            const int32_t *__restrict__ pidx,
                                                            double *__restrict__ Mp,
                                                            double *__restrict__ T, double rank_tol,
                                                            int *__restrict__ conv_flag)
 {
-    constexpr int RB = 32;
+    constexpr int RB = kPartialRows;
     extern __shared__ __align__(16) double smem[];
     const int k = st.k;
     const int ld = k + 1;                     // leading dimension of the k x k matrices
@@ -256,7 +264,8 @@ __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
     const int m = pc.r1 - pc.r0;
     for (int j = tid; j < k; j += kThreads) sblk[j] = st.S[pc.blk * k + j];
 
-    constexpr int EPT = (kMaxK * kMaxK + kThreads - 1) / kThreads;
+    // EPT >= ceil(k^2 / kThreads) Gram entries per thread (a template
+    // parameter, so small k keeps few registers and many blocks per CU)
     double acc[EPT];
     // Two passes over the kept rows.  Pass 0: G_P = P^T P.  Pass 1, after the
     // first eigen-solve: G_Y = Y^T Y with Y = P W1 recomputed from the rows,
@@ -310,20 +319,13 @@ __global__ __launch_bounds__(kThreads) void partial_kernel(StoreView st,
         if (sweeps < 0 && tid == 0) atomicOr(conv_flag, 1);
     }
     for (int j = tid; j < k; j += kThreads) sig[j] = sqrt(fmax(G[j * ld + j], 0.0));
-    // V~ = W1 W2, kept in G (no longer needed).  The k x k product is staged in
-    // the row buffers Us and Ys, which are contiguous and hold 2 RB k >= k^2 values.
-    double *Vs = Us;
-    static_assert(2 * RB >= kMaxK, "row buffers must hold a k x k matrix");
+    __syncthreads();                          // sig holds G's diagonal
+    // V~ = W1 W2, written over G (no longer needed)
     for (int e = tid; e < k * k; e += kThreads) {
         const int a = e / k, j = e % k;
         double s = 0.0;
         for (int l = 0; l < k; ++l) s = fma(W1[a * ld + l], W2[l * ld + j], s);
-        Vs[e] = s;
-    }
-    __syncthreads();
-    for (int e = tid; e < k * k; e += kThreads) {
-        const int a = e / k, j = e % k;
-        G[a * ld + j] = Vs[e];
+        G[a * ld + j] = s;
     }
     __syncthreads();
     double smax = 0.0;
@@ -369,26 +371,43 @@ hipError_t launch_finalize(int c, const Prob *probs, int nprob, int kk_max, cons
     return e;
 }
 
+namespace {
+
+template <int EPT>
+hipError_t run_partial(StoreView st, const Piece *pieces, const int32_t *pidx, int npartial,
+                       double *Mp, double *T, double rank_tol, int *conv_flag, size_t lds,
+                       hipStream_t stream)
+{
+    static size_t cur_f = 0, cur_d = 0;   // one limit per instantiation
+    hipError_t e = st.f32 ? ensure_lds((const void *)partial_kernel<float, EPT>, lds, cur_f)
+                          : ensure_lds((const void *)partial_kernel<double, EPT>, lds, cur_d);
+    if (e != hipSuccess) return e;
+    if (st.f32)
+        partial_kernel<float, EPT><<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T,
+                                                                        rank_tol, conv_flag);
+    else
+        partial_kernel<double, EPT><<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T,
+                                                                         rank_tol, conv_flag);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx, int npartial,
                           double *Mp, double *T, double rank_tol, int *conv_flag,
                           hipStream_t stream)
 {
     if (npartial <= 0) return hipSuccess;
+    if (st.k < 1 || st.k > kMaxK) return hipErrorInvalidValue;
     timing_begin("partial", stream);
-    const size_t lds = (size_t)(3 * st.k * (st.k + 1) + 2 * 32 * st.k) * sizeof(double);
-    static size_t cur_f = 0, cur_d = 0;   // one limit per instantiation
-    {
-        hipError_t e = st.f32 ? ensure_lds((const void *)partial_kernel<float>, lds, cur_f)
-                              : ensure_lds((const void *)partial_kernel<double>, lds, cur_d);
-        if (e != hipSuccess) return e;
-    }
-    if (st.f32)
-        partial_kernel<float><<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T, rank_tol,
-                                                                   conv_flag);
-    else
-        partial_kernel<double><<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T, rank_tol,
-                                                                    conv_flag);
-    hipError_t e = hipGetLastError();
+    const size_t lds = (size_t)(3 * st.k * (st.k + 1) + 2 * kPartialRows * st.k) * sizeof(double);
+    const int need = (st.k * st.k + kThreads - 1) / kThreads;
+    hipError_t e;
+    if (need <= 1) e = run_partial<1>(st, pieces, pidx, npartial, Mp, T, rank_tol, conv_flag, lds, stream);
+    else if (need <= 2) e = run_partial<2>(st, pieces, pidx, npartial, Mp, T, rank_tol, conv_flag, lds, stream);
+    else if (need <= 4) e = run_partial<4>(st, pieces, pidx, npartial, Mp, T, rank_tol, conv_flag, lds, stream);
+    else if (need <= 8) e = run_partial<8>(st, pieces, pidx, npartial, Mp, T, rank_tol, conv_flag, lds, stream);
+    else e = run_partial<16>(st, pieces, pidx, npartial, Mp, T, rank_tol, conv_flag, lds, stream);
     timing_end("partial", stream);
     return e;
 }

@@ -104,6 +104,24 @@ struct Workspace {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Scratch of the storage phase, one per (device, stream), grow-only and kept
+// for the life of the process, so that repeated stores do not allocate.  A
+// store call holds its entry's lock until the stream has synchronised.
+struct StoreWork {
+    std::mutex mu;
+    DevBuf Gpart, Vk, GY, F, Ysc, Big, Rows, desc;
+};
+std::mutex g_swmu;
+std::map<std::pair<int, hipStream_t>, StoreWork *> g_sw;
+
+StoreWork *store_work(int device, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lk(g_swmu);
+    StoreWork *&w = g_sw[{device, stream}];
+    if (!w) w = new StoreWork();
+    return w;
+}
+
 }  // namespace
 
 struct zs_store {
@@ -490,11 +508,13 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
         probs[i] = pr;
     }
     const int nchunks = (int)chunks.size();
-    DevBuf Gpart, Vk, GY, F, Ysc, Big, Rows, desc;
-    auto release = [&]() {
-        Gpart.release(); Vk.release(); GY.release(); F.release(); Ysc.release(); Big.release();
-        Rows.release(); desc.release();
-    };
+    StoreWork *sw = store_work(st->device, stream);
+    std::lock_guard<std::mutex> swlk(sw->mu);
+    DevBuf &Gpart = sw->Gpart, &Vk = sw->Vk, &GY = sw->GY, &F = sw->F, &Ysc = sw->Ysc,
+           &Big = sw->Big, &Rows = sw->Rows, &desc = sw->desc;
+    // the workspace stays allocated; on an error the stream is drained so that
+    // no kernel of this call still uses it when the next call reuses it
+    auto release = [&]() { (void)hipStreamSynchronize(stream); };
 #define ST_TRY2(expr)                                                                       \
     do {                                                                                    \
         hipError_t e_ = (expr);                                                             \
