@@ -202,6 +202,14 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
 {
     constexpr int KS = KM / 4;                     // MFMA steps over l
     constexpr int NCB = (KM + 15) / 16;            // 16-column blocks (k_q <= k <= KM)
+    // When the last block holds 4 columns (KM = 16 m + 4) it runs on the 4x4x4
+    // matrix-core shape: four independent 4 x 4 blocks per instruction at a
+    // quarter of the 16x16x4 cost.  Its A operand is the 16x16x4 A fragment
+    // unchanged (A(b, i, s) in lane 16 s + 4 b + i); B(s, j) sits in lane
+    // 16 s + 4 b + j for every block b, and D(b, i, j) in lane 16 i + 4 b + j.
+    constexpr bool TAIL = KM % 16 == 4;
+    constexpr int NF = TAIL ? NCB - 1 : NCB;       // full 16-column blocks
+    constexpr int NFA = NF > 0 ? NF : 1;
     extern __shared__ __align__(16) double tile[];    // 64 x KM
     const int per = (npieces + kXcds - 1) / kXcds;
     const int pos = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
@@ -212,14 +220,20 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
     const int lane = threadIdx.x;
     const double *__restrict__ Cp = C + pc.c_off;
     // B fragments: B(s, j) = C(4 t + s, 16 cb + j) for step t, zero beyond k_q
-    double bf[NCB][KS];
+    double bf[NFA][KS];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
+    for (int cb = 0; cb < NF; ++cb)
 #pragma unroll
         for (int t = 0; t < KS; ++t) {
             const int j = 16 * cb + lane % 16, l = 4 * t + lane / 16;
             bf[cb][t] = j < kq ? Cp[j * KM + l] : 0.0;
         }
+    double bt[KS];                                 // tail: B(s, j) = C(4 t + s, 16 NF + j)
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+        const int j = 16 * NF + lane % 4, l = 4 * t + lane / 16;
+        bt[t] = (TAIL && j < kq) ? Cp[j * KM + l] : 0.0;
+    }
     const TU *Ub = static_cast<const TU *>(st.U) + (pc.blk * st.b + pc.r0) * k;
     TU *out = Uout + pc.out_off;
     const int64_t ldu = pc.ldu;
@@ -251,31 +265,40 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
             for (int i = 0; i < KM; ++i) pre[i] = buf_elem<TU, true>(r, lane + i * kProdRows);
         }
         wave_sync();
-        v4d acc[4][NCB];
+        v4d acc[4][NFA];
+        double acct[4];
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+            for (int cb = 0; cb < NF; ++cb) acc[rb][cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+            acct[rb] = 0.0;
 #pragma unroll
             for (int s2 = 0; s2 < KS; ++s2) {
                 const int col = 4 * s2 + lane / 16;
                 const double x = tile[(16 * rb + lane % 16) * k + col];
                 const double a = col < k ? x : 0.0;
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb)
+                for (int cb = 0; cb < NF; ++cb)
                     acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[cb][s2], acc[rb][cb], 0, 0, 0);
+                if constexpr (TAIL)
+                    acct[rb] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, bt[s2], acct[rb], 0, 0, 0);
             }
         }
         wave_sync();                               // every lane has read its A fragments
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int rb = 0; rb < 4; ++rb) {
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb)
+            for (int cb = 0; cb < NF; ++cb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = 16 * rb + 4 * v + lane / 16, col = 16 * cb + lane % 16;
                     if (col < kq) tile[row * kq + col] = acc[rb][cb][v];
                 }
+            if constexpr (TAIL) {
+                const int row = 16 * rb + 4 * ((lane % 16) / 4) + lane / 16, col = 16 * NF + lane % 4;
+                if (col < kq) tile[row * kq + col] = acct[rb];
+            }
+        }
         wave_sync();
         if (CONTIG) {                              // the tile is contiguous in the output
             const __amdgpu_buffer_rsrc_t r = buf(out + (int64_t)row0 * kq, nr * kq * (int)sizeof(TU));
