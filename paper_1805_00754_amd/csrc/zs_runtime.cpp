@@ -201,6 +201,7 @@ hipError_t first_stage_eig(int c, int k, const Prob *probs, int nprob, const dou
 
 // Chunking of tall-skinny row runs for the Gram / projection kernels.
 constexpr int kStoreChunkRows = 2048;
+constexpr int kProjChunkRows = 256;   // rows per projection wave (storage phase)
 constexpr int kQueryChunkPieces = 32;   // whole pieces per projection work-group
 
 // Upload `bytes` of host data through the workspace's pinned staging buffer.
@@ -474,16 +475,19 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
     ST_TRY(hipMalloc(&st->conv, sizeof(int)));
     ST_TRY(hipMemsetAsync(st->conv, 0, sizeof(int), stream));
 
-    // Work lists: one problem per block, chunks of at most kStoreChunkRows rows.
-    std::vector<Chunk> chunks;
+    // Work lists: one problem per block.  The Gram works on chunks of at most
+    // kStoreChunkRows rows (one c x c partial Gram each); the projection and the
+    // U formation on chunks of kProjChunkRows rows (one wave each, one k x k
+    // partial G_Y each).
+    std::vector<Chunk> chunks, pchunks;
     std::vector<Prob> probs(nb);
-    int32_t slot = 0;
+    int32_t slot = 0, pslot = 0;
     for (int64_t i = 0; i < nb; ++i) {
         const int64_t rows = st->block_rows(i);
         Prob pr;
         std::memset(&pr, 0, sizeof pr);
         pr.g0 = slot;
-        pr.y0 = slot;
+        pr.y0 = pslot;
         // one chunk per block for c > 128 (each chunk holds a c x c partial Gram)
         const int64_t crows = c > kMaxC ? std::max<int64_t>(kStoreChunkRows, b) : kStoreChunkRows;
         for (int64_t r = 0; r < rows; r += crows) {
@@ -496,8 +500,18 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
             ch.kk = k;
             chunks.push_back(ch);
         }
+        for (int64_t r = 0; r < rows; r += kProjChunkRows) {
+            Chunk ch;
+            ch.x_off = (i * b + r) * lda;
+            ch.y_off = (i * b + r) * k;
+            ch.rows = (int32_t)std::min<int64_t>(kProjChunkRows, rows - r);
+            ch.prob = (int32_t)i;
+            ch.slot = pslot++;
+            ch.kk = k;
+            pchunks.push_back(ch);
+        }
         pr.ng = slot - pr.g0;
-        pr.ny = slot - pr.y0;
+        pr.ny = pslot - pr.y0;
         pr.kk = k;
         pr.v_dst = static_cast<char *>(st->Vt) + i * k * c * (int64_t)st->esize();  // V_(i)^T
         pr.v_f32 = st->f32;                 // element (a, j) at j * c + a
@@ -508,6 +522,7 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
         probs[i] = pr;
     }
     const int nchunks = (int)chunks.size();
+    const int npchunks = (int)pchunks.size();
     StoreWork *sw = store_work(st->device, stream);
     std::lock_guard<std::mutex> swlk(sw->mu);
     DevBuf &Gpart = sw->Gpart, &Vk = sw->Vk, &GY = sw->GY, &F = sw->F, &Ysc = sw->Ysc,
@@ -526,7 +541,7 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
     } while (0)
     ST_TRY2(Gpart.ensure(sizeof(double) * (size_t)nchunks * c * c));
     ST_TRY2(Vk.ensure(sizeof(double) * (size_t)nb * c * kMaxK));
-    ST_TRY2(GY.ensure(sizeof(double) * (size_t)nchunks * kSlotK));
+    ST_TRY2(GY.ensure(sizeof(double) * (size_t)npchunks * kSlotK));
     ST_TRY2(F.ensure(sizeof(double) * (size_t)nb * kSlotK));
     // Y = A V_k in FP64: in place in U for an FP64 store, in scratch otherwise
     if (st->f32) ST_TRY2(Ysc.ensure(sizeof(double) * (size_t)t * k));
@@ -548,7 +563,7 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
     }
     Blob blob;
     const size_t o_chunks = blob.add(chunks), o_probs = blob.add(probs), o_gsrc = blob.add(gsrc);
-    const size_t o_leaf = blob.add(leaf_chunks);
+    const size_t o_leaf = blob.add(leaf_chunks), o_pchunks = blob.add(pchunks);
     ST_TRY2(desc.ensure(blob.bytes.size()));
     ST_TRY2(hipMemcpyAsync(desc.p, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice,
                            stream));
@@ -556,15 +571,16 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
     const Prob *d_probs = (const Prob *)(desc.as<char>() + o_probs);
     const double *const *d_gsrc = (const double *const *)(desc.as<char>() + o_gsrc);
     const Chunk *d_leaf_chunks = (const Chunk *)(desc.as<char>() + o_leaf);
+    const Chunk *d_pchunks = (const Chunk *)(desc.as<char>() + o_pchunks);
     const int x_type = a_type == ZS_F32 ? kElemF32 : a_type == ZS_BF16 ? kElemBF16 : kElemF64;
     ST_TRY2(launch_gram(A, x_type, lda, (int)c, d_chunks, nchunks, Gpart.as<double>(), stream));
     ST_TRY2(first_stage_eig((int)c, k, d_probs, (int)nb, d_gsrc, nullptr, Vk.as<double>(), Big,
                             st->conv, stream));
-    ST_TRY2(launch_project(A, x_type, lda, (int)c, d_chunks, nchunks, k, Vk.as<double>(), Y,
+    ST_TRY2(launch_project(A, x_type, lda, (int)c, d_pchunks, npchunks, k, Vk.as<double>(), Y,
                            GY.as<double>(), stream));
     ST_TRY2(launch_finalize((int)c, d_probs, (int)nb, k, GY.as<double>(), Vk.as<double>(),
                             F.as<double>(), st->rank_tol(), st->conv, stream));
-    ST_TRY2(launch_utransform(Y, st->U, st->f32, k, d_chunks, nchunks, F.as<double>(), stream));
+    ST_TRY2(launch_utransform(Y, st->U, st->f32, k, d_pchunks, npchunks, F.as<double>(), stream));
     // Gram tree over the stored blocks: leaves, then one launch per level.  For
     // c > 128 a leaf is the Gram of the block's rows sigma_ij v_ij^T, formed by
     // the Gram kernel (one chunk of k rows per block); leaves past nb are zero.
