@@ -86,10 +86,97 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const TA *__restrict__ X
 
 }  // namespace
 
+// Matrix-core form for c <= 256 (at most 16 blocks of 16 columns): one chunk
+// per work-group column, G = sum over 4-row steps of F_i^T F_j, where F_b is
+// the step's 4 x 16 slice of column block b.  With FP64 MFMA 16x16x4 the A
+// operand A(i, s) = X(s, 16 ci + i) and the B operand B(s, j) = X(s, 16 cj + j)
+// have the same lane layout (element (s, e) of a slice in lane e + 16 s), so
+// one load per column block and step feeds every block product of the step.
+// Only blocks ci <= cj are formed (the result is symmetric); wave w owns the
+// block columns w and NB - 1 - w, which balances the work: NB + 1 blocks per
+// wave for even NB.  D(i, j) sits in register i / 4 of lane j + 16 (i mod 4).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int NBM, typename TA>
+__global__ __launch_bounds__(kThreads) void gram_mfma_kernel(const TA *__restrict__ X, int64_t ld,
+                                                             int c, const Chunk *__restrict__ chunks,
+                                                             double *__restrict__ Gpart)
+{
+    const Chunk ch = chunks[blockIdx.x];
+    const int nb = (c + 15) / 16;
+    const int lane = threadIdx.x % 64;
+    const int w = (int)blockIdx.y * (kThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    if (2 * w > nb - 1) return;                    // no block column for this wave
+    const int ca = w, cb = nb - 1 - w;             // owned block columns (ca <= cb)
+    const bool two = cb != ca;
+    const TA *Xc = X + ch.x_off;
+    const int e = lane % 16, s4 = lane / 16;
+    v4d acc_a[NBM], acc_b[NBM];
+#pragma unroll
+    for (int b = 0; b < NBM; ++b) {
+        acc_a[b] = (v4d){0.0, 0.0, 0.0, 0.0};
+        acc_b[b] = (v4d){0.0, 0.0, 0.0, 0.0};
+    }
+    auto slice = [&](int r, int b) {               // X(r, 16 b + e), zero outside
+        const int col = 16 * b + e;
+        return (r < ch.rows && col < c) ? load_as_double(Xc, (int64_t)r * ld + col) : 0.0;
+    };
+    // four 4-row steps per iteration, all of their loads issued first
+    constexpr int ST = NBM <= 8 ? 4 : 2;
+    for (int r0 = 0; r0 < ch.rows; r0 += 4 * ST) {
+        double f[ST][NBM];
+#pragma unroll
+        for (int q = 0; q < ST; ++q)
+#pragma unroll
+            for (int b = 0; b < NBM; ++b) f[q][b] = b < nb ? slice(r0 + 4 * q + s4, b) : 0.0;
+#pragma unroll
+        for (int q = 0; q < ST; ++q) {
+            double fa = f[q][0], fb = f[q][0];
+#pragma unroll
+            for (int b = 1; b < NBM; ++b) {
+                if (b == ca) fa = f[q][b];
+                if (b == cb) fb = f[q][b];
+            }
+#pragma unroll
+            for (int b = 0; b < NBM; ++b) {
+                if (b <= ca) acc_a[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[q][b], fa, acc_a[b], 0, 0, 0);
+                if (two && b <= cb)
+                    acc_b[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[q][b], fb, acc_b[b], 0, 0, 0);
+            }
+        }
+    }
+    double *G = Gpart + (int64_t)ch.slot * c * c;
+    auto put = [&](int bi, int bj, const v4d &d) {  // block (bi, bj) and its transpose
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * bi + 4 * v + lane / 16, j = 16 * bj + lane % 16;
+            if (i < c && j < c) {
+                G[(int64_t)i * c + j] = d[v];
+                if (bi != bj) G[(int64_t)j * c + i] = d[v];
+            }
+        }
+    };
+#pragma unroll
+    for (int b = 0; b < NBM; ++b) {
+        if (b <= ca) put(b, ca, acc_a[b]);
+        if (two && b <= cb) put(b, cb, acc_b[b]);
+    }
+}
+
 template <typename TA>
 void run_gram(const TA *X, int64_t ld, int c, const Chunk *chunks, int nchunks, double *Gpart,
               hipStream_t stream)
 {
+    if (c <= 256) {
+        const int nb = (c + 15) / 16;
+        const int waves = (nb + 1) / 2;            // two block columns per wave
+        dim3 grid(nchunks, (waves + kThreads / 64 - 1) / (kThreads / 64));
+        if (nb <= 8)
+            gram_mfma_kernel<8, TA><<<grid, kThreads, 0, stream>>>(X, ld, c, chunks, Gpart);
+        else
+            gram_mfma_kernel<16, TA><<<grid, kThreads, 0, stream>>>(X, ld, c, chunks, Gpart);
+        return;
+    }
     const int tm = c <= 16 ? 1 : c <= 32 ? 2 : c <= 64 ? 4 : 8;
     const int tile = 16 * tm;
     const int ntile = (c + tile - 1) / tile;

@@ -200,7 +200,8 @@ hipError_t first_stage_eig(int c, int k, const Prob *probs, int nprob, const dou
 }
 
 // Chunking of tall-skinny row runs for the Gram / projection kernels.
-constexpr int kStoreChunkRows = 2048;
+constexpr int kStoreChunkRows = 512;       // Gram chunk rows, c <= 128
+constexpr int kStoreChunkRowsWide = 2048;  // c > 128: at least a whole block
 constexpr int kProjChunkRows = 256;   // rows per projection wave (storage phase)
 constexpr int kQueryChunkPieces = 32;   // whole pieces per projection work-group
 
@@ -489,7 +490,7 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
         pr.g0 = slot;
         pr.y0 = pslot;
         // one chunk per block for c > 128 (each chunk holds a c x c partial Gram)
-        const int64_t crows = c > kMaxC ? std::max<int64_t>(kStoreChunkRows, b) : kStoreChunkRows;
+        const int64_t crows = c > kMaxC ? std::max<int64_t>(kStoreChunkRowsWide, b) : kStoreChunkRows;
         for (int64_t r = 0; r < rows; r += crows) {
             Chunk ch;
             ch.x_off = (i * b + r) * lda;
