@@ -131,6 +131,22 @@ def main():
             kernels[name] = {"launches": n, "total_ms": ms, "avg_ms": ms / n}
     zs.zs_sync_status(st)
 
+    # The same batch replayed from a captured HIP graph: no host planning or
+    # descriptor upload inside the timed replays.
+    g = zs.zs_query_batch_graph(st, ts, te, kq, out=out)
+    torch.cuda.synchronize()
+    graph_ms = []
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.launch(stream)
+        e1.record(stream)
+        e1.synchronize()
+        graph_ms.append(e0.elapsed_time(e1))
+    g.free()
+    log("graph replay %.2f ms" % float(np.mean(graph_ms)))
+
     # Single-query latency (queries issued one at a time).
     lat = []
     U1 = torch.empty((qlen, k), dtype=st.out_dtype, device=dev)
@@ -207,6 +223,8 @@ def main():
                    "queries": args.queries, "query_rows": qlen, "k_q": k,
                    "parallelism": "single-gpu"},
         "query_batch_ms": q_ms,
+        "graph_batch_ms": float(np.mean(graph_ms)),
+        "graph_svds_per_s": args.queries / (float(np.mean(graph_ms)) / 1e3),
         "store_ms": s_ms,
         "store_gbps": store_gbps,
         "store_frac_hbm": store_gbps / HBM_PEAK_GBPS,

@@ -115,6 +115,36 @@ zs_status zs_query_batch(const zs_store *st, int32_t nq, const int64_t *t_s, con
                          hipStream_t stream);
 
 /* Releases the store's device memory (synchronises the device first). */
+/*
+ * zs_query_batch_graph -- the batched query form captured into a HIP graph
+ * for repeated replay of one fixed batch (the same ranges, ranks and output
+ * buffers every time), e.g. a dashboard that re-reads a set of windows.
+ *   Arguments as in zs_query_batch; `stream` runs one eager pass of the batch
+ *   (it also writes the outputs) and is synchronised before the capture.
+ *   out   receives the graph.  It owns private scratch (descriptors, pieces,
+ *         intermediate factors) sized for this batch and keeps pointers to
+ *         `st` and to the output buffers: both must outlive the graph, and
+ *         the store must not be freed first.
+ *   Replays plan nothing on the host and allocate nothing; their results
+ *   are bitwise those of zs_query_batch on the same batch.  Errors as in
+ *   zs_query_batch, plus ZS_EDEVICE when capture or instantiation fails
+ *   (*out is then NULL).
+ */
+typedef struct zs_batch_graph zs_batch_graph;
+zs_status zs_query_batch_graph(const zs_store *st, int32_t nq, const int64_t *t_s,
+                               const int64_t *t_e, const int32_t *k_q, void *U,
+                               const int64_t *u_off, double *S, const int64_t *s_off, void *V,
+                               const int64_t *v_off, int32_t *k_out, hipStream_t stream,
+                               zs_batch_graph **out);
+
+/* zs_batch_graph_launch -- replays the batch on `stream` (asynchronous).
+ * Replays on one graph must not overlap (they share the graph's scratch). */
+zs_status zs_batch_graph_launch(zs_batch_graph *g, hipStream_t stream);
+
+/* zs_batch_graph_free -- releases the graph and its scratch; NULL is a no-op.
+ * Every replay must have completed. */
+void zs_batch_graph_free(zs_batch_graph *g);
+
 void zs_store_free(zs_store *st);
 
 /* Device bytes held by the store: the block factors (8 or 4 bytes per element

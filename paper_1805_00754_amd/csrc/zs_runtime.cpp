@@ -44,6 +44,7 @@ zs_status fail(zs_status s, const char *fmt, ...)
 // ------------------------------------------------------------------ timing
 std::mutex g_tmu;
 bool g_timing = false;
+thread_local bool t_capturing = false;   // a graph capture is in progress on this thread
 struct TimedLaunch {
     std::string name;
     hipEvent_t a, b;
@@ -155,7 +156,7 @@ struct zs_store {
 namespace zs {
 void timing_begin(const char *name, hipStream_t stream)
 {
-    if (!g_timing) return;
+    if (!g_timing || t_capturing) return;
     hipEvent_t a;
     if (hipEventCreate(&a) != hipSuccess) return;
     (void)hipEventRecord(a, stream);
@@ -164,7 +165,7 @@ void timing_begin(const char *name, hipStream_t stream)
 
 void timing_end(const char *name, hipStream_t stream)
 {
-    if (!g_timing) return;
+    if (!g_timing || t_capturing) return;
     auto it = t_open.find(name);
     if (it == t_open.end()) return;
     hipEvent_t b;
@@ -236,10 +237,24 @@ struct Blob {
     }
 };
 
-zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t *te,
+// What the launches of a planned batch need besides the workspace: sizes and
+// the offsets of the descriptor arrays in the workspace's descriptor buffer.
+struct QueryPlan {
+    int32_t nq = 0, max_np = 0, kq_max = 1;
+    int nchunks = 0, npieces = 0, npartial = 0;
+    bool contiguous = true;
+    size_t o_chunks = 0, o_probs = 0, o_qds = 0, o_pidx = 0, o_boff = 0, o_gsrc = 0, o_msrc = 0;
+    void *U = nullptr;
+};
+
+// Plans a batch (Alg. 3 index math, host side), sizes workspace `w` and uploads
+// the descriptors to it: through the pinned staging buffer on `stream`, or
+// synchronously when `sync_upload` (graphs, whose descriptors must stay put).
+zs_status query_plan(zs_store *st, int32_t nq, const int64_t *ts, const int64_t *te,
                      const int32_t *kq, void *U, const int64_t *u_off, const int64_t *ldu,
                      double *S, const int64_t *s_off, void *V, const int64_t *v_off,
-                     const int64_t *ldv, int32_t *k_out, hipStream_t stream)
+                     const int64_t *ldv, int32_t *k_out, hipStream_t stream, Workspace *w,
+                     bool sync_upload, QueryPlan &pl)
 {
     const int64_t c = st->c, b = st->b;
     const int32_t k = st->k;
@@ -352,13 +367,6 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
         return fail(ZS_EUNSUPPORTED, "batch touches %lld blocks (limit %d)", (long long)npieces64,
                     INT32_MAX);
     // ---- workspace ---------------------------------------------------------------
-    Workspace *w;
-    {
-        std::lock_guard<std::mutex> lk(st->mu);
-        auto it = st->ws.find(stream);
-        if (it == st->ws.end()) it = st->ws.emplace(stream, new Workspace()).first;
-        w = it->second;
-    }
     const int nchunks = (int)chunks.size(), npieces = (int)npieces64;
     const int npartial = (int)pidx.size();
     HIP_TRY(w->Mp.ensure(sizeof(double) * std::max<int64_t>(1, (int64_t)npartial * k * c)));
@@ -379,36 +387,85 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
     const size_t o_chunks = blob.add(chunks), o_probs = blob.add(probs);
     const size_t o_qds = blob.add(qds), o_pidx = blob.add(pidx), o_boff = blob.add(boff);
     const size_t o_gsrc = blob.add(gsrc), o_msrc = blob.add(msrc);
-    zs_status s = upload(*w, blob.bytes.data(), blob.bytes.size(), stream);
-    if (s != ZS_OK) return s;
+    if (sync_upload) {
+        HIP_TRY(w->desc.ensure(blob.bytes.size()));
+        HIP_TRY(hipMemcpy(w->desc.p, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice));
+    } else {
+        zs_status s = upload(*w, blob.bytes.data(), blob.bytes.size(), stream);
+        if (s != ZS_OK) return s;
+    }
+    pl.nq = nq;
+    pl.max_np = max_np;
+    pl.kq_max = kq_max;
+    pl.nchunks = nchunks;
+    pl.npieces = npieces;
+    pl.npartial = npartial;
+    pl.contiguous = true;
+    for (int32_t q = 0; q < nq; ++q) pl.contiguous = pl.contiguous && ldu[q] == kq[q];
+    pl.o_chunks = o_chunks;
+    pl.o_probs = o_probs;
+    pl.o_qds = o_qds;
+    pl.o_pidx = o_pidx;
+    pl.o_boff = o_boff;
+    pl.o_gsrc = o_gsrc;
+    pl.o_msrc = o_msrc;
+    pl.U = U;
+    return ZS_OK;
+}
+
+// Enqueues the kernels of a planned batch on `stream` (no host synchronisation
+// and, once the workspace is sized, no allocation, so the sequence can be
+// captured into a graph).
+zs_status query_launch(zs_store *st, const QueryPlan &pl, Workspace *w, hipStream_t stream)
+{
+    const int64_t c = st->c;
+    const int32_t k = st->k;
     char *d = w->desc.as<char>();
-    const StackChunk *d_chunks = (const StackChunk *)(d + o_chunks);
-    const Prob *d_probs = (const Prob *)(d + o_probs);
-    const QueryDesc *d_qds = (const QueryDesc *)(d + o_qds);
+    const StackChunk *d_chunks = (const StackChunk *)(d + pl.o_chunks);
+    const Prob *d_probs = (const Prob *)(d + pl.o_probs);
+    const QueryDesc *d_qds = (const QueryDesc *)(d + pl.o_qds);
     const Piece *d_pieces = w->P.as<Piece>();
-    const int32_t *d_boff = (const int32_t *)(d + o_boff);
-    const int32_t *d_pidx = (const int32_t *)(d + o_pidx);
-    const double *const *d_gsrc = (const double *const *)(d + o_gsrc);
-    const double *const *d_msrc = (const double *const *)(d + o_msrc);
+    const int32_t *d_boff = (const int32_t *)(d + pl.o_boff);
+    const int32_t *d_pidx = (const int32_t *)(d + pl.o_pidx);
+    const double *const *d_gsrc = (const double *const *)(d + pl.o_gsrc);
+    const double *const *d_msrc = (const double *const *)(d + pl.o_msrc);
+    double *Mp = w->Mp.as<double>();
     const StoreView sv = st->view();
-    // ---- launches ---------------------------------------------------------------
-    HIP_TRY(launch_expand_pieces(sv, d_qds, nq, max_np, w->P.as<Piece>(), stream));
-    HIP_TRY(launch_partial(sv, d_pieces, d_pidx, npartial, Mp, w->T.as<double>(), st->rank_tol(),
+    HIP_TRY(launch_expand_pieces(sv, d_qds, pl.nq, pl.max_np, w->P.as<Piece>(), stream));
+    HIP_TRY(launch_partial(sv, d_pieces, d_pidx, pl.npartial, Mp, w->T.as<double>(), st->rank_tol(),
                            st->conv, stream));
-    HIP_TRY(first_stage_eig((int)c, k, d_probs, nq, d_gsrc, d_msrc, w->Vk.as<double>(), w->big,
+    HIP_TRY(first_stage_eig((int)c, k, d_probs, pl.nq, d_gsrc, d_msrc, w->Vk.as<double>(), w->big,
                             st->conv, stream));
-    HIP_TRY(launch_stack_project(sv, d_pieces, Mp, d_chunks, nchunks, kq_max, w->Vk.as<double>(),
-                                 w->Y.as<double>(), w->GY.as<double>(), stream));
-    HIP_TRY(launch_finalize((int)c, d_probs, nq, kq_max, w->GY.as<double>(), w->Vk.as<double>(),
+    HIP_TRY(launch_stack_project(sv, d_pieces, Mp, d_chunks, pl.nchunks, pl.kq_max,
+                                 w->Vk.as<double>(), w->Y.as<double>(), w->GY.as<double>(), stream));
+    HIP_TRY(launch_finalize((int)c, d_probs, pl.nq, pl.kq_max, w->GY.as<double>(), w->Vk.as<double>(),
                             w->F.as<double>(), st->rank_tol(), st->conv, stream));
-    HIP_TRY(launch_coef(k, kq_max, d_pieces, d_chunks, nchunks, w->Y.as<double>(),
+    HIP_TRY(launch_coef(k, pl.kq_max, d_pieces, d_chunks, pl.nchunks, w->Y.as<double>(),
                         w->F.as<double>(), w->T.as<double>(), w->C.as<double>(), stream));
-    bool contiguous = true;
-    for (int32_t q = 0; q < nq; ++q) contiguous = contiguous && ldu[q] == kq[q];
-    HIP_TRY(launch_order_pieces(d_pieces, npieces, st->nb, d_boff, w->bcount.as<int32_t>(),
+    HIP_TRY(launch_order_pieces(d_pieces, pl.npieces, st->nb, d_boff, w->bcount.as<int32_t>(),
                                 w->perm.as<int32_t>(), stream));
-    HIP_TRY(launch_blockprod(sv, d_pieces, w->perm.as<int32_t>(), npieces, w->C.as<double>(), U,
-                             contiguous, stream));
+    HIP_TRY(launch_blockprod(sv, d_pieces, w->perm.as<int32_t>(), pl.npieces, w->C.as<double>(), pl.U,
+                             pl.contiguous, stream));
+    return ZS_OK;
+}
+
+zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t *te,
+                     const int32_t *kq, void *U, const int64_t *u_off, const int64_t *ldu,
+                     double *S, const int64_t *s_off, void *V, const int64_t *v_off,
+                     const int64_t *ldv, int32_t *k_out, hipStream_t stream)
+{
+    Workspace *w;
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        auto it = st->ws.find(stream);
+        if (it == st->ws.end()) it = st->ws.emplace(stream, new Workspace()).first;
+        w = it->second;
+    }
+    QueryPlan pl;
+    zs_status s = query_plan(st, nq, ts, te, kq, U, u_off, ldu, S, s_off, V, v_off, ldv, k_out,
+                             stream, w, false, pl);
+    if (s != ZS_OK) return s;
+    return query_launch(st, pl, w, stream);
     return ZS_OK;
 }
 
@@ -627,6 +684,24 @@ zs_status zs_query(const zs_store *cst, int64_t t_s, int64_t t_e, int32_t k_q, v
                       stream);
 }
 
+static zs_status check_batch(const zs_store *cst, int32_t nq, const int64_t *t_s, const int64_t *t_e,
+                      const int32_t *k_q, void *U, const int64_t *u_off, double *S,
+                      const int64_t *s_off, void *V, const int64_t *v_off, int32_t *k_out)
+{
+    if (!cst) return fail(ZS_EINVAL, "store is null");
+    if (nq < 1) return fail(ZS_EINVAL, "nq = %d < 1", nq);
+    if (!t_s || !t_e || !k_q || !u_off || !s_off || !v_off)
+        return fail(ZS_EINVAL, "null host array");
+    if (!U || !S || !V || !k_out) return fail(ZS_EINVAL, "null output pointer");
+    for (int32_t q = 0; q < nq; ++q) {
+        zs_status s = check_query(cst, t_s[q], t_e[q], k_q[q]);
+        if (s != ZS_OK) return s;
+        if (u_off[q] < 0 || s_off[q] < 0 || v_off[q] < 0)
+            return fail(ZS_EINVAL, "negative output offset for query %d", q);
+    }
+    return ZS_OK;
+}
+
 zs_status zs_query_batch(const zs_store *cst, int32_t nq, const int64_t *t_s, const int64_t *t_e,
                          const int32_t *k_q, void *U, const int64_t *u_off, double *S,
                          const int64_t *s_off, void *V, const int64_t *v_off, int32_t *k_out,
@@ -648,6 +723,88 @@ zs_status zs_query_batch(const zs_store *cst, int32_t nq, const int64_t *t_s, co
     zs_store *st = const_cast<zs_store *>(cst);
     return query_impl(st, nq, t_s, t_e, k_q, U, u_off, ld.data(), S, s_off, V, v_off, ld.data(),
                       k_out, stream);
+}
+
+struct zs_batch_graph {
+    zs_store *st = nullptr;
+    Workspace *w = nullptr;            // private: the graph's buffers stay put
+    QueryPlan pl;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+void zs_batch_graph_free(zs_batch_graph *g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->w) {
+        g->w->release();
+        delete g->w;
+    }
+    delete g;
+}
+
+zs_status zs_query_batch_graph(const zs_store *cst, int32_t nq, const int64_t *t_s,
+                               const int64_t *t_e, const int32_t *k_q, void *U,
+                               const int64_t *u_off, double *S, const int64_t *s_off, void *V,
+                               const int64_t *v_off, int32_t *k_out, hipStream_t stream,
+                               zs_batch_graph **out)
+{
+    if (!out) return fail(ZS_EINVAL, "null graph pointer");
+    *out = nullptr;
+    zs_status s = check_batch(cst, nq, t_s, t_e, k_q, U, u_off, S, s_off, V, v_off, k_out);
+    if (s != ZS_OK) return s;
+    std::vector<int64_t> ld(nq);
+    for (int32_t q = 0; q < nq; ++q) ld[q] = k_q[q];
+    zs_batch_graph *g = new zs_batch_graph();
+    g->st = const_cast<zs_store *>(cst);
+    g->w = new Workspace();
+    auto bail = [&](zs_status e) {
+        zs_batch_graph_free(g);
+        return e;
+    };
+#define GR_TRY(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return bail(fail(e_ == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "%s: %s",    \
+                             #expr, hipGetErrorString(e_)));                                \
+    } while (0)
+    s = query_plan(g->st, nq, t_s, t_e, k_q, U, u_off, ld.data(), S, s_off, V, v_off, ld.data(),
+                   k_out, stream, g->w, true, g->pl);
+    if (s != ZS_OK) return bail(s);
+    // One eager run sizes every lazily grown buffer and sets the kernels' LDS
+    // limits, so that the captured launches allocate nothing.
+    s = query_launch(g->st, g->pl, g->w, stream);
+    if (s != ZS_OK) return bail(s);
+    GR_TRY(hipStreamSynchronize(stream));
+    hipStream_t cs = nullptr;
+    GR_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    t_capturing = true;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        s = query_launch(g->st, g->pl, g->w, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        g->graph = graph;
+        if (e == hipSuccess) e = e2;
+    }
+    t_capturing = false;
+    (void)hipStreamDestroy(cs);
+    if (s != ZS_OK) return bail(s);
+    GR_TRY(e);
+    GR_TRY(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+#undef GR_TRY
+    *out = g;
+    return ZS_OK;
+}
+
+zs_status zs_batch_graph_launch(zs_batch_graph *g, hipStream_t stream)
+{
+    if (!g || !g->exec) return fail(ZS_EINVAL, "graph is null");
+    HIP_TRY(hipGraphLaunch(g->exec, stream));
+    return ZS_OK;
 }
 
 void zs_store_free(zs_store *st)

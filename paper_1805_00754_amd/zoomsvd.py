@@ -6,7 +6,8 @@ streams.  If the library is missing this module raises on first use; there is
 no fallback path.
 
 Names follow the C ABI: ``zs_store_blocks``, ``zs_query``, ``zs_query_batch``,
-``zs_store_get_block``, ``zs_store_bytes``, ``zs_sync_status``, ...
+``zs_query_batch_graph``, ``zs_store_get_block``, ``zs_store_bytes``,
+``zs_sync_status``, ...
 Time ranges are 0-based half-open ``[t_s, t_e)``.
 """
 from __future__ import annotations
@@ -28,7 +29,8 @@ STATUS_NAMES = {0: "ZS_OK", -1: "ZS_EINVAL", -2: "ZS_ERANGE", -3: "ZS_ENOMEM", -
                 -5: "ZS_EDEVICE", -6: "ZS_EUNSUPPORTED"}
 
 # Symbols the header declares (the CPU test checks the library exports all).
-EXPORTED = ["zs_store_blocks", "zs_query", "zs_query_batch", "zs_store_free", "zs_store_bytes",
+EXPORTED = ["zs_store_blocks", "zs_query", "zs_query_batch", "zs_query_batch_graph",
+            "zs_batch_graph_launch", "zs_batch_graph_free", "zs_store_free", "zs_store_bytes",
             "zs_store_info", "zs_store_get_block", "zs_sync_status", "zs_last_error", "zs_version",
             "zs_timing_enable", "zs_timing_reset", "zs_timing_get"]
 
@@ -62,6 +64,11 @@ def load(path: str | None = None):
         lib.zs_query.argtypes = [_vp, _i64, _i64, _i32, _vp, _i64, _vp, _vp, _i64, _vp, _vp]
         lib.zs_query_batch.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                        _vp, _vp]
+        lib.zs_query_batch_graph.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                             _vp, _vp, _vp, ctypes.POINTER(_vp)]
+        lib.zs_batch_graph_launch.argtypes = [_vp, _vp]
+        lib.zs_batch_graph_free.argtypes = [_vp]
+        lib.zs_batch_graph_free.restype = None
         lib.zs_store_free.argtypes = [_vp]
         lib.zs_store_free.restype = None
         lib.zs_store_bytes.argtypes = [_vp]
@@ -76,7 +83,8 @@ def load(path: str | None = None):
         lib.zs_timing_reset.restype = None
         lib.zs_timing_get.argtypes = [ctypes.c_char_p, _vp, _vp]
         for name in ("zs_store_blocks", "zs_query", "zs_query_batch", "zs_store_info",
-                     "zs_store_get_block", "zs_sync_status", "zs_timing_get"):
+                     "zs_store_get_block", "zs_sync_status", "zs_timing_get",
+                     "zs_query_batch_graph", "zs_batch_graph_launch"):
             getattr(lib, name).restype = ctypes.c_int
         if path is None:
             _lib = lib
@@ -217,6 +225,48 @@ def zs_query_batch(st: Store, t_s, t_e, k_q, out: Batch | None = None, stream=No
                                  _vp(_ptr(out.V)), a(out.v_off), _vp(_ptr(out.k_out)),
                                  _vp(_stream(stream))))
     return out
+
+
+class BatchGraph:
+    """A fixed batch captured into a HIP graph (zs_query_batch_graph).  Holds
+    the store and the output Batch, which must outlive it."""
+
+    def __init__(self, st: Store, out: Batch, handle):
+        self.st = st
+        self.out = out
+        self.handle = handle
+
+    def launch(self, stream=None):
+        _check(load().zs_batch_graph_launch(_vp(self.handle), _vp(_stream(stream))))
+
+    def free(self):
+        if self.handle:
+            load().zs_batch_graph_free(_vp(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def zs_query_batch_graph(st: Store, t_s, t_e, k_q, out: Batch | None = None,
+                         stream=None) -> BatchGraph:
+    """Plans the batch once, runs it eagerly (filling `out`) and captures its
+    launches into a graph that replays them with BatchGraph.launch()."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if out is None:
+        out = Batch(st, t_s, t_e, k_q, dev)
+    nq = len(out)
+    a = lambda x: _vp(x.ctypes.data)
+    h = _vp()
+    _check(load().zs_query_batch_graph(_vp(st.handle), nq, a(out.t_s), a(out.t_e), a(out.k_q),
+                                       _vp(_ptr(out.U)), a(out.u_off), _vp(_ptr(out.S)),
+                                       a(out.s_off), _vp(_ptr(out.V)), a(out.v_off),
+                                       _vp(_ptr(out.k_out)), _vp(_stream(stream)),
+                                       ctypes.byref(h)))
+    return BatchGraph(st, out, h.value)
 
 
 def zs_query_batch_into(st: Store, t_s, t_e, k_q, U, u_off, S, s_off, V, v_off, k_out,
