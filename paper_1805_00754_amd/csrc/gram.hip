@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const TA *__restrict__ X
 
 }  // namespace
 
-// Matrix-core form for c <= 256 (at most 16 blocks of 16 columns): one chunk
+// Matrix-core form for c <= 128 (at most 8 blocks of 16 columns): one chunk
 // per work-group column, G = sum over 4-row steps of F_i^T F_j, where F_b is
 // the step's 4 x 16 slice of column block b.  With FP64 MFMA 16x16x4 the A
 // operand A(i, s) = X(s, 16 ci + i) and the B operand B(s, j) = X(s, 16 cj + j)
@@ -167,14 +167,14 @@ template <typename TA>
 void run_gram(const TA *X, int64_t ld, int c, const Chunk *chunks, int nchunks, double *Gpart,
               hipStream_t stream)
 {
-    if (c <= 256) {
+    // The matrix-core form for c <= 128.  Wider matrices need 16 block columns
+    // of accumulators per wave, which leaves one wave per SIMD and exposes the
+    // load latency (measured 3x slower than the register-tiled form at c = 256).
+    if (c <= 128) {
         const int nb = (c + 15) / 16;
         const int waves = (nb + 1) / 2;            // two block columns per wave
         dim3 grid(nchunks, (waves + kThreads / 64 - 1) / (kThreads / 64));
-        if (nb <= 8)
-            gram_mfma_kernel<8, TA><<<grid, kThreads, 0, stream>>>(X, ld, c, chunks, Gpart);
-        else
-            gram_mfma_kernel<16, TA><<<grid, kThreads, 0, stream>>>(X, ld, c, chunks, Gpart);
+        gram_mfma_kernel<8, TA><<<grid, kThreads, 0, stream>>>(X, ld, c, chunks, Gpart);
         return;
     }
     const int tm = c <= 16 ? 1 : c <= 32 ? 2 : c <= 64 ? 4 : 8;
