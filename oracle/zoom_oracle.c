@@ -394,7 +394,7 @@ int zo_query(const double *Uall, const double *S, const double *V, int64_t t, in
         }
         K += pc[p].rows_m;
     }
-    /* Alg. 2 lines 3-4: SVD of the stacked matrix (K x c). */
+    /* Alg. 2, the SVD of the stacked matrix (K x c), truncated to k_q. */
     const int64_t r = K < c ? K : c;
     double *Ur = (double *)malloc(sizeof(double) * (size_t)(K * r));
     double *sr = (double *)malloc(sizeof(double) * (size_t)r);
@@ -406,7 +406,7 @@ int zo_query(const double *Uall, const double *S, const double *V, int64_t t, in
     for (int64_t j = 0; j < kq; ++j) so[j] = j < ko ? sr[j] : 0.0;
     for (int64_t row = 0; row < c; ++row)
         for (int64_t j = 0; j < kq; ++j) Vo[row * kq + j] = j < ko ? Vr[row * r + j] : 0.0;
-    /* Alg. 2 line 5 / Eq. (9): U = [U'_S U'_r(S); U_(S+1) U_r(S+1); ...]. */
+    /* Alg. 2, the block-diagonal product, Eq. (9): U = [U'_S U'_r(S); U_(S+1) U_r(S+1); ...]. */
     int64_t krow = 0, orow = 0;
     for (int64_t p = 0; p < npieces; ++p) {
         const int64_t m = pc[p].r1 - pc[p].r0;

@@ -3,7 +3,7 @@
 //
 // Used for the block Gram G_i = A_(i)^T A_(i) of the storage phase and for the
 // Gram of each query's stacked matrix M = [Sigma'_S V'_S^T; ...; Sigma'_E V'_E^T]
-// (Alg. 2, line 3).  Each work-group owns one chunk of rows and one
+// (the stacked SVD of Alg. 2).  Each work-group owns one chunk of rows and one
 // (16*TM) x (16*TM) output tile; rows are staged through LDS in panels of RB
 // rows with coalesced loads, every thread accumulates a TM x TM register tile.
 // Partial Grams of the chunks of one problem go to separate slots and are

@@ -5,7 +5,7 @@
 //    written out) and the partial Gram Y^T Y (kk x kk, one slot per chunk).
 //  * stack_project: the same for a query's stacked matrix M, whose rows are
 //    read where they live: Sigma_(i) V_(i)^T rows of the store for whole
-//    blocks, the Partial-SVD rows for boundary blocks (Alg. 2 line 2).  M is
+//    blocks, the Partial-SVD rows for boundary blocks (the stack of Alg. 2).  M is
 //    never materialised.
 //  * utransform: U_(i) <- Y_(i) F_(i) in place (F = W Sigma^-1 with the sign
 //    rule folded in), giving the block's left singular vectors.
@@ -44,6 +44,13 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef const double __attribute__((address_space(1))) gdouble;
 typedef const float __attribute__((address_space(1))) gfloat;
 typedef const uint16_t __attribute__((address_space(1))) gushort;
+// vectors of consecutive row elements; rows are only element-aligned
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef uint16_t ush4 __attribute__((ext_vector_type(4)));
+typedef const dbl2 __attribute__((address_space(1), aligned(8))) gdouble2;
+typedef const flt4 __attribute__((address_space(1), aligned(4))) gfloat4;
+typedef const ush4 __attribute__((address_space(1), aligned(2))) gushort4;
 
 // A row of a tile: where it starts, its element type (ElemType) and its scale.
 struct RowRef {
@@ -60,9 +67,23 @@ __device__ __forceinline__ double row_elem(const char *p, int type, int i)
     return (double)__uint_as_float((uint32_t)reinterpret_cast<const gushort *>(a)[i] << 16);
 }
 
+// Rows of one element type known at compile time (kMixed: per row, at run time).
+constexpr int kMixed = -1;
+
+template <int TYPE>
+__device__ __forceinline__ double typed_elem(const char *p, int type, int i)
+{
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    if constexpr (TYPE == kElemF64) return reinterpret_cast<const gdouble *>(a)[i];
+    else if constexpr (TYPE == kElemF32) return (double)reinterpret_cast<const gfloat *>(a)[i];
+    else if constexpr (TYPE == kElemBF16)
+        return (double)__uint_as_float((uint32_t)reinterpret_cast<const gushort *>(a)[i] << 16);
+    else return row_elem(p, type, i);
+}
+
 // rows rows of the chunk (row r from row(r)), V_k c x kq row-major; Y rows of
 // kq values from Yout, the kq x kq Gram to G.  sm holds 64 x max(17, kq + 1).
-template <int KQM, class RowFn>
+template <int KQM, int TYPE, class RowFn>
 __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, int kq,
                                              const double *__restrict__ V, double *__restrict__ Yout,
                                              double *__restrict__ G, RowRef fallback, double *sm)
@@ -103,39 +124,76 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
             }
         }
         const int sc4 = lane / 16;
-        // A fragments of the panel at a0 (from HBM), and its B fragments
-        // B(s, j) = V_k(a0 + 4 t + s, 16 cb + j) (small, cache resident), zero
-        // outside c x kq
-        auto load_a = [&](int a0, double (&af)[4][4]) {
+        // A fragments of the panel at a0 (from HBM), and its B fragments (from
+        // cache).  MFMA t of a panel takes panel column kcol(t, s) as its
+        // contraction index s: the order of the 16 columns over the four
+        // MFMAs is free as long as A and B agree, and this one gives each lane
+        // four consecutive columns of its row, so that without CLAMP (c a
+        // multiple of the panel width) a lane reads its row's part of a panel
+        // with 16-byte loads (two for FP64, one for FP32, one 8-byte for BF16).
+        // With CLAMP every element load is issued at a clamped address: no
+        // load sits under a branch, so the wait for a panel does not also wait
+        // for the next one.  Past column c the A fragments repeat column c - 1,
+        // a real element, and meet rows of B that are zeroed by an exact
+        // multiply.
+        // (one order for every element type: FP32 or BF16 input widened to
+        // FP64 gives the same sums, bit for bit, as the widened input itself)
+        auto kcol = [&](int t) { return 4 * sc4 + t; };
+        auto load_a = [&](auto clamp, int a0, double (&af)[4][4]) {
+            if constexpr (!decltype(clamp)::value && TYPE != kMixed) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int col = a0 + 4 * t + sc4;
+                for (int rb = 0; rb < 4; ++rb) {
+                    const uintptr_t ra = reinterpret_cast<uintptr_t>(rp[rb]);
+                    if constexpr (TYPE == kElemF64) {
+                        const gdouble2 *q = reinterpret_cast<const gdouble2 *>(ra + 8 * (a0 + 4 * sc4));
+                        const dbl2 lo = q[0], hi = q[1];
+                        af[rb][0] = lo.x;
+                        af[rb][1] = lo.y;
+                        af[rb][2] = hi.x;
+                        af[rb][3] = hi.y;
+                    } else if constexpr (TYPE == kElemF32) {
+                        const flt4 v = *reinterpret_cast<const gfloat4 *>(ra + 4 * (a0 + 4 * sc4));
+                        af[rb][0] = v.x;
+                        af[rb][1] = v.y;
+                        af[rb][2] = v.z;
+                        af[rb][3] = v.w;
+                    } else {
+                        const ush4 v = *reinterpret_cast<const gushort4 *>(ra + 2 * (a0 + 4 * sc4));
+                        af[rb][0] = __uint_as_float((uint32_t)v.x << 16);
+                        af[rb][1] = __uint_as_float((uint32_t)v.y << 16);
+                        af[rb][2] = __uint_as_float((uint32_t)v.z << 16);
+                        af[rb][3] = __uint_as_float((uint32_t)v.w << 16);
+                    }
+                }
+            } else {
 #pragma unroll
-                for (int rb = 0; rb < 4; ++rb)
-                    af[rb][t] = col < c ? row_elem(rp[rb], rt[rb], col) : 0.0;
+                for (int t = 0; t < 4; ++t) {
+                    const int col = a0 + kcol(t);
+                    const int colc = decltype(clamp)::value ? min(col, c - 1) : col;
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb) af[rb][t] = typed_elem<TYPE>(rp[rb], rt[rb], colc);
+                }
             }
         };
-        // up to 32 columns the A fragments of the next panel are in flight
-        // during the matrix-core work; wider tiles have no registers to spare
-        constexpr bool kAhead = KQM <= 32;
-        double an[4][4];
-        if (kAhead) load_a(0, an);
-        for (int a0 = 0; a0 < c; a0 += kPanel) {
-            if (!kAhead) load_a(a0, an);
-            double af[4][4], bf[NCB][4];
-#pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) af[rb][t] = an[rb][t];
+        auto load_b = [&](int a0, double (&bq)[NCB][4]) {
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int vr = a0 + 4 * t + sc4, vc = 16 * cb + lane % 16;
-                    const double x = V[min(vr, c - 1) * kq + min(vc, kq - 1)];
-                    bf[cb][t] = (vr < c && vc < kq) ? x : 0.0;
-                }
-            if (kAhead && a0 + kPanel < c) load_a(a0 + kPanel, an);
+                for (int t = 0; t < 4; ++t)
+                    bq[cb][t] = V[min(a0 + kcol(t), c - 1) * kq + min(16 * cb + lane % 16, kq - 1)];
+        };
+        // the products of one panel: its B fragments are loaded here (from
+        // cache), after the loads already in flight, and their rows past c and
+        // columns past kq are zeroed by an exact multiply
+        auto panel = [&](int a0, const double (&af)[4][4]) {
+            double bf[NCB][4];
+            load_b(a0, bf);
+            if constexpr (KQM <= 32) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    bf[cb][t] *= (a0 + kcol(t) < c && 16 * cb + lane % 16 < kq) ? 1.0 : 0.0;
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
@@ -143,7 +201,37 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
 #pragma unroll
                     for (int cb = 0; cb < NCB; ++cb)
                         acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[rb][t], bf[cb][t], acc[rb][cb], 0, 0, 0);
-        }
+        };
+        auto panels = [&](auto clamp) {
+            if constexpr (KQM <= 32) {
+                // two sets of A registers in turn: the next panel's A loads are
+                // in flight during this panel's products, and no register copy
+                // between the sets waits for them
+                double a1[4][4], a2[4][4];
+                load_a(clamp, 0, a1);
+                for (int a0 = 0; a0 < c; a0 += 2 * kPanel) {
+                    // past c: a clamped panel that is not used, or none
+                    if (decltype(clamp)::value || a0 + kPanel < c) load_a(clamp, a0 + kPanel, a2);
+                    __builtin_amdgcn_sched_barrier(0);
+                    panel(a0, a1);
+                    if (a0 + kPanel >= c) break;
+                    if (decltype(clamp)::value || a0 + 2 * kPanel < c) load_a(clamp, a0 + 2 * kPanel, a1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    panel(a0 + kPanel, a2);
+                }
+            } else {
+                // wider tiles have no registers to spare for a second set
+                for (int a0 = 0; a0 < c; a0 += kPanel) {
+                    double af[4][4];
+                    load_a(clamp, a0, af);
+                    panel(a0, af);
+                }
+            }
+        };
+        if (c % kPanel == 0)
+            panels(std::false_type{});
+        else
+            panels(std::true_type{});
         // scale the rows: D(i, j) of a 16 x 16 block sits in register i / 4 of
         // lane j + 16 (i mod 4)
 #pragma unroll
@@ -222,13 +310,19 @@ __device__ __forceinline__ void stack_project_body(StoreView st, const Piece *__
                       st.S[pc.blk * k + j]};
     };
     const RowRef fallback{static_cast<const char *>(st.Vt), vt_type, 0.0};
-    tile_project<KQM>(row, ch.npieces * k, c, ch.kk, Vk + (int64_t)ch.prob * c * kMaxK, Y + ch.y_off,
-                      GYpart + (int64_t)ch.slot * kSlotK, fallback, sm);
+    // FP64 stores: every stack row is FP64; FP32 stores mix FP32 store rows
+    // with FP64 Partial-SVD rows
+    if (st.f32)
+        tile_project<KQM, kMixed>(row, ch.npieces * k, c, ch.kk, Vk + (int64_t)ch.prob * c * kMaxK,
+                                  Y + ch.y_off, GYpart + (int64_t)ch.slot * kSlotK, fallback, sm);
+    else
+        tile_project<KQM, kElemF64>(row, ch.npieces * k, c, ch.kk, Vk + (int64_t)ch.prob * c * kMaxK,
+                                    Y + ch.y_off, GYpart + (int64_t)ch.slot * kSlotK, fallback, sm);
 }
 
 // project (storage phase): rows of A of the chunk, scale 1.
 template <int KQM, typename TA>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KQM <= 32 ? 2 : 1)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KQM <= 16 ? 2 : 1)))
 void project_kernel(const TA *__restrict__ X, int64_t ld, int c, const Chunk *__restrict__ chunks,
                     const double *__restrict__ Vk, double *__restrict__ Y, double *__restrict__ GYpart)
 {
@@ -240,14 +334,14 @@ void project_kernel(const TA *__restrict__ X, int64_t ld, int c, const Chunk *__
         return RowRef{reinterpret_cast<const char *>(Xc + (int64_t)r * ld), type, 1.0};
     };
     const RowRef fallback{reinterpret_cast<const char *>(Xc), type, 0.0};
-    tile_project<KQM>(row, ch.rows, c, ch.kk, Vk + (int64_t)ch.prob * c * kMaxK, Y + ch.y_off,
-                      GYpart + (int64_t)ch.slot * kSlotK, fallback, sm);
+    tile_project<KQM, type>(row, ch.rows, c, ch.kk, Vk + (int64_t)ch.prob * c * kMaxK, Y + ch.y_off,
+                            GYpart + (int64_t)ch.slot * kSlotK, fallback, sm);
 }
 
 // Up to 32 columns the kernel fits two waves per SIMD in registers; wider
 // tiles keep the compiler's choice (more registers, no spills).
 template <int KQM>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void stack_project_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KQM <= 16 ? 2 : 1))) void stack_project_kernel(
     StoreView st, const Piece *__restrict__ pieces, const double *__restrict__ Mp,
     const StackChunk *__restrict__ chunks, const double *__restrict__ Vk, double *__restrict__ Y,
     double *__restrict__ GYpart)

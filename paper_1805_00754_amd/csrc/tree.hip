@@ -1,6 +1,6 @@
 // Gram tree of the stored blocks.
 //
-// The stacked matrix of a query (Alg. 2 line 2) holds the rows Sigma_(i) V_(i)^T
+// The stacked matrix of a query (Alg. 2) holds the rows Sigma_(i) V_(i)^T
 // of every whole block in the range, so its Gram M^T M contains
 // sum_i V_(i) Sigma_(i)^2 V_(i)^T over those blocks.  The storage phase keeps
 // these c x c block Grams in a binary tree over the blocks (leaf i = block i,

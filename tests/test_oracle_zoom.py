@@ -26,7 +26,8 @@ def reconstruct(st, i):
 
 # ---------------------------------------------------------------- index math
 def test_index_math_brute_force(orc):
-    """Alg. 3 lines 1-2 against a row-by-row enumeration for all ranges."""
+    """The boundary-block index math of Alg. 3 against a row-by-row enumeration
+    for all ranges."""
     for t in (1, 7, 23, 40):
         for b in range(1, 9):
             for ts in range(t):
