@@ -147,6 +147,30 @@ def main():
     g.free()
     log("graph replay %.2f ms" % float(np.mean(graph_ms)))
 
+    # Write ceiling of this very output allocation: a plain fill of the batch's
+    # U buffer.  Sustained write bandwidth into a large allocation depends on
+    # where it landed in physical memory (5.5 to 6.9 TB/s seen for the same
+    # 52 GB size), so blockprod is also judged against this figure.
+    # Two plain writers, torch's fill and zeroing (a runtime memset); the faster
+    # one's mean over three passes is the ceiling.
+    fills = {}
+    for name, fn in (("fill", lambda: out.U.fill_(1.0)), ("zero", lambda: out.U.zero_())):
+        ms = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        fills[name] = float(np.mean(ms))
+    fill_ms = min(fills.values())
+    out_bytes = out.U.numel() * out.U.element_size()
+    fill_gbps = out_bytes / (fill_ms / 1e3) / 1e9
+    log("writers of the output buffer: %s; ceiling %.0f GB/s"
+        % (", ".join("%s %.2f ms" % kv for kv in fills.items()), fill_gbps))
+
     # Single-query latency (queries issued one at a time).
     lat = []
     U1 = torch.empty((qlen, k), dtype=st.out_dtype, device=dev)
@@ -197,6 +221,10 @@ def main():
             unique = usize * (t * k + n_rows * k) + 8.0 * pieces * kp * k
             roof["unique_bytes_per_launch"] = unique
             roof["unique_frac"] = unique / avg_s / 1e9 / HBM_PEAK_GBPS
+            # the output alone against a plain fill of the same allocation
+            roof["output_write_gbps"] = out_bytes / avg_s / 1e9
+            roof["fill_gbps_same_buffer"] = fill_gbps
+            roof["output_frac_of_fill"] = out_bytes / avg_s / 1e9 / fill_gbps
     else:
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": None, "traffic": None}
