@@ -117,20 +117,26 @@ __global__ __launch_bounds__(kThreads) void gram_mfma_kernel(const TA *__restric
         acc_a[b] = (v4d){0.0, 0.0, 0.0, 0.0};
         acc_b[b] = (v4d){0.0, 0.0, 0.0, 0.0};
     }
-    auto slice = [&](int r, int b) {               // X(r, 16 b + e), zero outside
-        const int col = 16 * b + e;
-        return (r < ch.rows && col < c) ? load_as_double(Xc, (int64_t)r * ld + col) : 0.0;
-    };
-    // four 4-row steps per iteration, all of their loads issued first
-    constexpr int ST = NBM <= 8 ? 4 : 2;
-    for (int r0 = 0; r0 < ch.rows; r0 += 4 * ST) {
-        double f[ST][NBM];
-#pragma unroll
-        for (int q = 0; q < ST; ++q)
-#pragma unroll
-            for (int b = 0; b < NBM; ++b) f[q][b] = b < nb ? slice(r0 + 4 * q + s4, b) : 0.0;
+    // Steps of 4 rows, ST per half-iteration, in two register sets used in
+    // turn: one set's loads are in flight while the other feeds the matrix
+    // cores.  Every load is issued (row and column clamped, so no load sits
+    // under a branch and no wait drains the other set); rows past the chunk
+    // are zeroed by an exact multiply when they are used.
+    constexpr int ST = NBM <= 8 ? 2 : 1;
+    auto load = [&](int r0, double (&f)[ST][NBM]) {
 #pragma unroll
         for (int q = 0; q < ST; ++q) {
+            const int64_t r = min(r0 + 4 * q + s4, ch.rows - 1);
+#pragma unroll
+            for (int b = 0; b < NBM; ++b) f[q][b] = load_as_double(Xc, r * ld + min(16 * b + e, c - 1));
+        }
+    };
+    auto steps = [&](int r0, double (&f)[ST][NBM]) {
+#pragma unroll
+        for (int q = 0; q < ST; ++q) {
+            const double keep = r0 + 4 * q + s4 < ch.rows ? 1.0 : 0.0;
+#pragma unroll
+            for (int b = 0; b < NBM; ++b) f[q][b] *= keep;
             double fa = f[q][0], fb = f[q][0];
 #pragma unroll
             for (int b = 1; b < NBM; ++b) {
@@ -144,6 +150,18 @@ __global__ __launch_bounds__(kThreads) void gram_mfma_kernel(const TA *__restric
                     acc_b[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[q][b], fb, acc_b[b], 0, 0, 0);
             }
         }
+    };
+    constexpr int H = 4 * ST;                      // rows per half-iteration
+    double f1[ST][NBM], f2[ST][NBM];
+    load(0, f1);
+    for (int r0 = 0; r0 < ch.rows; r0 += 2 * H) {
+        load(r0 + H, f2);                          // past the chunk: clamped, unused
+        __builtin_amdgcn_sched_barrier(0);
+        steps(r0, f1);
+        if (r0 + H >= ch.rows) break;
+        load(r0 + 2 * H, f1);
+        __builtin_amdgcn_sched_barrier(0);
+        steps(r0 + H, f2);
     }
     double *G = Gpart + (int64_t)ch.slot * c * c;
     auto put = [&](int bi, int bj, const v4d &d) {  // block (bi, bj) and its transpose
