@@ -67,16 +67,16 @@ def load(path: str | None = None):
 def _bind(lib):
     lib.zo_svd.argtypes = [_i64, _i64, _pd, _i64, _dbl, _i64, _pd, _i64, _pd, _pd, _i64, _pi32]
     lib.zo_svd.restype = ctypes.c_int
-    lib.zo_store.argtypes = [_pd, _i64, _i64, _i64, _i64, _i32, _dbl, _pd, _pd, _pd, _pi32]
+    lib.zo_store.argtypes = [_pd, _i64, _i64, _i64, _i64, _i32, _dbl, _dbl, _pd, _pd, _pd, _pi32]
     lib.zo_store.restype = ctypes.c_int
     lib.zo_partial_svd.argtypes = [_pd, _pd, _pd, _i64, _i64, _i32, _i64, _i64, _i64, _dbl,
-                                   _pd, _pd, _pd, _pi32]
+                                   _dbl, _pd, _pd, _pd, _pi32]
     lib.zo_partial_svd.restype = ctypes.c_int
     lib.zo_query.argtypes = [_pd, _pd, _pd, _i64, _i64, _i64, _i32, _i64, _i64, _i32, _dbl,
-                             _pd, _pd, _pd, _pi32]
+                             _dbl, _pd, _pd, _pd, _pi32]
     lib.zo_query.restype = ctypes.c_int
     lib.zo_query_batch.argtypes = [_pd, _pd, _pd, _i64, _i64, _i64, _i32, _i32, _pi64, _pi64,
-                                   _pi32, _dbl, _pd, _pi64, _pd, _pi64, _pd, _pi64, _pi32]
+                                   _pi32, _dbl, _dbl, _pd, _pi64, _pd, _pi64, _pd, _pi64, _pi32]
     lib.zo_query_batch.restype = ctypes.c_int
     lib.zo_direct.argtypes = [_pd, _i64, _i64, _i64, _i64, _i32, _dbl, _pd, _pd, _pd, _pi32]
     lib.zo_direct.restype = ctypes.c_int
@@ -86,6 +86,8 @@ def _bind(lib):
     lib.zo_num_blocks.restype = _i64
     lib.zo_block_rows.argtypes = [_i64, _i64, _i64]
     lib.zo_block_rows.restype = _i64
+    lib.zo_xi_rank.argtypes = [_pd, _i64, _dbl]
+    lib.zo_xi_rank.restype = _i64
     lib.zo_max_threads.argtypes = []
     lib.zo_max_threads.restype = ctypes.c_int
     return lib
@@ -129,12 +131,15 @@ class Store:
     """Blocks compressed by the oracle's storage phase (Def. 2 sets U, S, V).
 
     U: t x k (rows of block i hold U_(i)), S: nb x k, V: nb x c x k, k_i: nb.
+    xi: the energy threshold of Eq. (1) (0: none), also applied by the query
+    phase to the Partial-SVD and to the stacked SVD.
     """
 
-    def __init__(self, t, c, b, k, U, S, V, k_i, rank_tol):
+    def __init__(self, t, c, b, k, U, S, V, k_i, rank_tol, xi=0.0):
         self.t, self.c, self.b, self.k = int(t), int(c), int(b), int(k)
         self.U, self.S, self.V, self.k_i = U, S, V, k_i
         self.rank_tol = rank_tol
+        self.xi = float(xi)
 
     @property
     def nb(self) -> int:
@@ -148,8 +153,9 @@ class Store:
         return int(sum(int(self.k_i[i]) * (self.block_rows(i) + 1 + self.c) for i in range(self.nb)))
 
 
-def store(A, b: int, k: int, rank_tol: float = RANK_TOL, lib=None) -> Store:
-    """Storage phase, batch form (Alg. 1 / Def. 1 / Def. 2)."""
+def store(A, b: int, k: int, rank_tol: float = RANK_TOL, lib=None, xi: float = 0.0) -> Store:
+    """Storage phase, batch form (Alg. 1 / Def. 1 / Def. 2); with 0 < xi < 1
+    block i keeps k_i = min(k, numerical rank, xi rank of Eq. (1))."""
     lib = lib or load()
     A = _f64(A)
     t, c = A.shape
@@ -158,13 +164,14 @@ def store(A, b: int, k: int, rank_tol: float = RANK_TOL, lib=None) -> Store:
     S = np.zeros((nb, k))
     V = np.zeros((nb, c, k))
     k_i = np.zeros(nb, np.int32)
-    bad = lib.zo_store(_p(A), t, c, c, b, k, rank_tol, _p(U), _p(S), _p(V), _p(k_i))
+    bad = lib.zo_store(_p(A), t, c, c, b, k, rank_tol, xi, _p(U), _p(S), _p(V), _p(k_i))
     if bad:
         raise OracleError("Jacobi did not converge on %d blocks" % bad)
-    return Store(t, c, b, k, U, S, V, k_i, rank_tol)
+    return Store(t, c, b, k, U, S, V, k_i, rank_tol, xi)
 
 
-def store_from_arrays(t, c, b, k, U, S, V, k_i=None, rank_tol: float = RANK_TOL) -> Store:
+def store_from_arrays(t, c, b, k, U, S, V, k_i=None, rank_tol: float = RANK_TOL,
+                      xi: float = 0.0) -> Store:
     """Wrap block factors produced elsewhere (e.g. downloaded from the GPU)
     so that the oracle's query phase can run on them."""
     U = _f64(U).reshape(t, k)
@@ -172,7 +179,7 @@ def store_from_arrays(t, c, b, k, U, S, V, k_i=None, rank_tol: float = RANK_TOL)
     V = _f64(V).reshape(-1, c, k)
     if k_i is None:
         k_i = (S > 0).sum(axis=1).astype(np.int32)
-    return Store(t, c, b, k, U, S, V, np.ascontiguousarray(k_i, np.int32), rank_tol)
+    return Store(t, c, b, k, U, S, V, np.ascontiguousarray(k_i, np.int32), rank_tol, xi)
 
 
 def partial_svd(st: Store, i: int, r0: int, r1: int, lib=None):
@@ -186,10 +193,18 @@ def partial_svd(st: Store, i: int, r0: int, r1: int, lib=None):
     Vp = np.zeros((st.c, rp))
     rank = np.zeros(1, np.int32)
     sw = lib.zo_partial_svd(_p(st.U), _p(st.S), _p(st.V), st.c, st.b, st.k, i, r0, r1,
-                            st.rank_tol, _p(Up), _p(sp), _p(Vp), _p(rank))
+                            st.rank_tol, st.xi, _p(Up), _p(sp), _p(Vp), _p(rank))
     if sw < 0:
         raise OracleError("Jacobi did not converge")
     return Up, sp, Vp, int(rank[0])
+
+
+def xi_rank(s, xi: float, lib=None) -> int:
+    """Eq. (1): the smallest k with sum_{j<k} s_j^2 >= xi sum_j s_j^2 over all
+    the singular values s (descending); len(s) when 0 < xi < 1 does not hold."""
+    lib = lib or load()
+    s = _f64(np.asarray(s, np.float64).ravel())
+    return int(lib.zo_xi_rank(_p(s), len(s), float(xi)))
 
 
 def query_blocks(t_s: int, t_e: int, b: int, lib=None):
@@ -211,7 +226,7 @@ def query(st: Store, t_s: int, t_e: int, kq: int, lib=None):
     V = np.zeros((st.c, kq))
     kout = np.zeros(1, np.int32)
     bad = lib.zo_query(_p(st.U), _p(st.S), _p(st.V), st.t, st.c, st.b, st.k, t_s, t_e, kq,
-                       st.rank_tol, _p(U), _p(s), _p(V), _p(kout))
+                       st.rank_tol, st.xi, _p(U), _p(s), _p(V), _p(kout))
     if bad:
         raise OracleError("Jacobi did not converge")
     return U, s, V, int(kout[0])
@@ -238,7 +253,7 @@ def query_batch(st: Store, ts, te, kq, lib=None):
     s = np.zeros(int(kq.sum()))
     kout = np.zeros(nq, np.int32)
     bad = lib.zo_query_batch(_p(st.U), _p(st.S), _p(st.V), st.t, st.c, st.b, st.k, nq, _p(ts),
-                             _p(te), _p(kq), st.rank_tol, _p(U), _p(uoff), _p(s), _p(soff),
+                             _p(te), _p(kq), st.rank_tol, st.xi, _p(U), _p(uoff), _p(s), _p(soff),
                              _p(V), _p(voff), _p(kout))
     if bad:
         raise OracleError("Jacobi did not converge in %d queries" % bad)

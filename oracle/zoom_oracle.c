@@ -33,6 +33,12 @@
  *   - Partial-SVD keeps all numerically non-zero triplets (no truncation
  *     beyond numerical rank), so the stitched result is exact when every
  *     block has rank <= k.
+ *   - Energy threshold xi (Eq. (1)), optional: with 0 < xi < 1 every
+ *     low-rank approximation of the method (the block SVDs of the storage
+ *     phase, the Partial-SVD of a boundary block, the SVD of the stacked
+ *     matrix) keeps the smallest rank whose leading squared singular values
+ *     reach xi times the sum of all of them, within the other caps (k, k_q,
+ *     numerical rank).  xi = 0 (or >= 1) turns the rule off.
  */
 #include <math.h>
 #include <stdint.h>
@@ -243,6 +249,26 @@ int zo_svd(int64_t m, int64_t n, const double *A, int64_t lda, double rank_tol, 
 }
 
 /* --------------------------------------------------------------------------
+ * Energy-threshold rank (Eq. (1)).  s holds all r singular values in
+ * descending order.  Returns the smallest k' >= 1 with
+ *     sum_{j < k'} s_j^2 >= xi * sum_{j < r} s_j^2,
+ * or r when xi <= 0 or xi >= 1 (no threshold) or when s is all zero.
+ * ------------------------------------------------------------------------ */
+int64_t zo_xi_rank(const double *s, int64_t r, double xi)
+{
+    if (!(xi > 0.0 && xi < 1.0)) return r;
+    double total = 0.0;
+    for (int64_t j = 0; j < r; ++j) total += s[j] * s[j];
+    if (total <= 0.0) return r;
+    double run = 0.0;
+    for (int64_t j = 0; j < r; ++j) {
+        run += s[j] * s[j];
+        if (run >= xi * total) return j + 1;
+    }
+    return r;
+}
+
+/* --------------------------------------------------------------------------
  * Block index math (Def. 1 and Alg. 3, read for 0-based half-open ranges).
  * ------------------------------------------------------------------------ */
 int64_t zo_num_blocks(int64_t t, int64_t b) { return (t + b - 1) / b; }
@@ -271,11 +297,11 @@ void zo_query_blocks(int64_t t_s, int64_t t_e, int64_t b, int64_t *S, int64_t *E
  *   Uall: t x k row-major; rows of block i hold U_(i) (rows_i x k)
  *   S:    nb x k;  block i holds Sigma_(i) (zero-padded past k_i)
  *   V:    nb x c x k; block i holds V_(i) (c x k, column j = v_j)
- *   kk:   nb;  k_i = min(k, numerical rank of A_(i))
+ *   kk:   nb;  k_i = min(k, numerical rank of A_(i), xi rank of Eq. (1))
  * Returns the number of blocks whose Jacobi did not converge.
  * ------------------------------------------------------------------------ */
 int zo_store(const double *A, int64_t t, int64_t c, int64_t lda, int64_t b, int32_t k,
-             double rank_tol, double *Uall, double *S, double *V, int32_t *kk)
+             double rank_tol, double xi, double *Uall, double *S, double *V, int32_t *kk)
 {
     const int64_t nb = zo_num_blocks(t, b);
     int failures = 0;
@@ -290,6 +316,8 @@ int zo_store(const double *A, int64_t t, int64_t c, int64_t lda, int64_t b, int3
         int sw = zo_svd(rows, c, A + i * b * lda, lda, rank_tol, k, Ub, r, sb, Vb, r, &rank);
         if (sw < 0) ++failures;
         int32_t ki = rank < k ? rank : k;
+        const int64_t kx = zo_xi_rank(sb, r, xi);      /* Eq. (1) over all r values */
+        if (kx < ki) ki = (int32_t)kx;
         kk[i] = ki;
         for (int64_t j = 0; j < k; ++j) S[i * k + j] = j < ki ? sb[j] : 0.0;
         for (int64_t row = 0; row < rows; ++row)
@@ -307,12 +335,13 @@ int zo_store(const double *A, int64_t t, int64_t c, int64_t lda, int64_t b, int3
  * Partial-SVD of block i restricted to its rows [r0, r1) (Alg. 3, Eqs. 5-6):
  *   P = X U_(i) Sigma_(i)  (the kept rows of U_(i), columns scaled by sigma)
  *   P = U~ Sigma~ V~^T,   U' = U~,  Sigma' = Sigma~,  V' = V_(i) V~
- * m = r1 - r0 rows, rp = min(m, k) triplets.  Outputs:
+ * m = r1 - r0 rows, rp = min(m, k) triplets, those past the numerical rank
+ * and past the xi rank (Eq. (1)) zeroed.  Outputs:
  *   Up: m x rp,  sp: rp,  Vp: c x rp  (row-major).
  * ------------------------------------------------------------------------ */
 int zo_partial_svd(const double *Uall, const double *S, const double *V, int64_t c,
                    int64_t b, int32_t k, int64_t i, int64_t r0, int64_t r1, double rank_tol,
-                   double *Up, double *sp, double *Vp, int32_t *rank)
+                   double xi, double *Up, double *sp, double *Vp, int32_t *rank)
 {
     const int64_t m = r1 - r0;
     const int64_t rp = m < k ? m : k;
@@ -322,6 +351,15 @@ int zo_partial_svd(const double *Uall, const double *S, const double *V, int64_t
             P[row * k + j] = Uall[(i * b + r0 + row) * k + j] * S[i * k + j];
     double *Vt = (double *)malloc(sizeof(double) * (size_t)(k * rp));   /* V~ : k x rp */
     int sw = zo_svd(m, k, P, k, rank_tol, rp, Up, rp, sp, Vt, rp, rank);
+    /* low-rank approximation with threshold xi (Alg. 3, Eq. (1)): the
+     * triplets past the xi rank of P's rp singular values are dropped */
+    const int64_t kx = zo_xi_rank(sp, rp, xi);
+    if (kx < *rank) *rank = (int32_t)kx;
+    for (int64_t j = *rank; j < rp; ++j) {
+        sp[j] = 0.0;
+        for (int64_t row = 0; row < m; ++row) Up[row * rp + j] = 0.0;
+        for (int64_t l = 0; l < k; ++l) Vt[l * rp + j] = 0.0;
+    }
     /* V' = V_(i) V~  (c x k times k x rp) */
     const double *Vi = V + i * c * k;
     for (int64_t row = 0; row < c; ++row)
@@ -335,9 +373,10 @@ int zo_partial_svd(const double *Uall, const double *S, const double *V, int64_t
 }
 
 /* --------------------------------------------------------------------------
- * Query phase (Alg. 2) for the range [t_s, t_e), truncated to rank kq.
- *   Uo: n x kq,  so: kq,  Vo: c x kq  (row-major); *kout = numerical rank
- *   kept (<= kq).  Columns past *kout are zero.
+ * Query phase (Alg. 2) for the range [t_s, t_e), truncated to rank kq (and
+ * to the xi rank of the stacked matrix, Eq. (1)).
+ *   Uo: n x kq,  so: kq,  Vo: c x kq  (row-major); *kout = rank kept
+ *   (<= kq).  Columns past *kout are zero.
  * ------------------------------------------------------------------------ */
 typedef struct {
     int64_t block, r0, r1;   /* block index and the kept rows inside it     */
@@ -348,7 +387,7 @@ typedef struct {
 
 int zo_query(const double *Uall, const double *S, const double *V, int64_t t, int64_t c,
              int64_t b, int32_t k, int64_t t_s, int64_t t_e, int32_t kq, double rank_tol,
-             double *Uo, double *so, double *Vo, int32_t *kout)
+             double xi, double *Uo, double *so, double *Vo, int32_t *kout)
 {
     int64_t Sb, Eb, lo, hi;
     zo_query_blocks(t_s, t_e, b, &Sb, &Eb, &lo, &hi);
@@ -374,7 +413,8 @@ int zo_query(const double *Uall, const double *S, const double *V, int64_t t, in
             double *sp = (double *)malloc(sizeof(double) * (size_t)rp);
             double *Vp = (double *)malloc(sizeof(double) * (size_t)(c * rp));
             int32_t rk;
-            if (zo_partial_svd(Uall, S, V, c, b, k, i, r0, r1, rank_tol, Up, sp, Vp, &rk) < 0) bad = 1;
+            if (zo_partial_svd(Uall, S, V, c, b, k, i, r0, r1, rank_tol, xi, Up, sp, Vp, &rk) < 0)
+                bad = 1;
             /* Stack rows Sigma' V'^T (rp x c). */
             for (int64_t j = 0; j < rp; ++j)
                 for (int64_t col = 0; col < c; ++col)
@@ -401,7 +441,9 @@ int zo_query(const double *Uall, const double *S, const double *V, int64_t t, in
     double *Vr = (double *)malloc(sizeof(double) * (size_t)(c * r));
     int32_t rk = 0;
     if (zo_svd(K, c, M, c, rank_tol, kq, Ur, r, sr, Vr, r, &rk) < 0) bad = 1;
-    const int32_t ko = rk < kq ? rk : kq;
+    int32_t ko = rk < kq ? rk : kq;
+    const int64_t kx = zo_xi_rank(sr, r, xi);   /* Eq. (1) over all r values of M */
+    if (kx < ko) ko = (int32_t)kx;
     *kout = ko;
     for (int64_t j = 0; j < kq; ++j) so[j] = j < ko ? sr[j] : 0.0;
     for (int64_t row = 0; row < c; ++row)
@@ -434,14 +476,14 @@ int zo_query(const double *Uall, const double *S, const double *V, int64_t t, in
  * V at Vo + voff[q] (c x kq[q]). */
 int zo_query_batch(const double *Uall, const double *S, const double *V, int64_t t, int64_t c,
                    int64_t b, int32_t k, int32_t nq, const int64_t *ts, const int64_t *te,
-                   const int32_t *kq, double rank_tol, double *Uo, const int64_t *uoff,
+                   const int32_t *kq, double rank_tol, double xi, double *Uo, const int64_t *uoff,
                    double *so, const int64_t *soff, double *Vo, const int64_t *voff,
                    int32_t *kout)
 {
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
     for (int32_t q = 0; q < nq; ++q) {
-        if (zo_query(Uall, S, V, t, c, b, k, ts[q], te[q], kq[q], rank_tol, Uo + uoff[q],
+        if (zo_query(Uall, S, V, t, c, b, k, ts[q], te[q], kq[q], rank_tol, xi, Uo + uoff[q],
                      so + soff[q], Vo + voff[q], kout + q) < 0)
             ++bad;
     }
