@@ -229,6 +229,47 @@ def main():
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": None, "traffic": None}
 
+    # Every timed kernel against its own binding roof, per step (store + batch).
+    # Units of work: the store's t rows, nb blocks (one c x c eigen-problem
+    # each, with k kept), and the batch's queries (one c x c eigen-problem each),
+    # pieces and boundary blocks.  Flops count what the method must do; bytes
+    # count each operand once.
+    nb = (t + b - 1) // b
+    nq = args.queries
+    part_rows = 0                     # rows of the boundary blocks cut by the ranges
+    for s_, e_ in zip(ts, te):
+        s_, e_ = int(s_), int(e_)
+        S_, E_ = s_ // b, (e_ - 1) // b
+        if S_ == E_:
+            part_rows += (e_ - s_) if (s_ % b or e_ - S_ * b != min(b, t - S_ * b)) else 0
+            continue
+        part_rows += (min(b, t - S_ * b) - (s_ - S_ * b)) if s_ % b else 0
+        part_rows += (e_ - E_ * b) if e_ - E_ * b != min(b, t - E_ * b) else 0
+    eig_flops = (nb + nq) * (4.0 / 3.0 * c ** 3 + 2.0 * c * c * k)
+    per_kernel = {
+        "gram": ("mfma_fp64", float(t) * c * (c + 1), FP64_PEAK_TFLOPS),
+        "project": ("hbm", esize * t * c + 8.0 * t * k, HBM_PEAK_GBPS),
+        "utransform": ("hbm", 16.0 * t * k, HBM_PEAK_GBPS),
+        "eig": ("fp64", eig_flops, FP64_PEAK_TFLOPS),
+        "partial": ("hbm", usize * part_rows * k, HBM_PEAK_GBPS),
+        "stack_project": ("mfma_fp64", 2.0 * pieces * k * c * k, FP64_PEAK_TFLOPS),
+        "coef": ("hbm", 8.0 * pieces * (k * k + kp * k), HBM_PEAK_GBPS),
+        "blockprod": ("hbm", usize * 2.0 * n_rows * k + 8.0 * pieces * kp * k, HBM_PEAK_GBPS),
+    }
+    kernel_roofs = {}
+    for name, (bound, amount, peak) in per_kernel.items():
+        if name not in kernels:
+            continue
+        sec = kernels[name]["total_ms"] / args.steps / 1e3
+        if bound == "hbm":
+            ach = amount / sec / 1e9
+            kernel_roofs[name] = {"bound": "hbm", "achieved": ach, "peak": peak, "unit": "GB/s",
+                                  "frac": ach / peak, "ms_per_step": sec * 1e3}
+        else:
+            ach = amount / sec / 1e12
+            kernel_roofs[name] = {"bound": bound, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                                  "frac": ach / peak, "ms_per_step": sec * 1e3}
+
     cpu = None
     if not args.no_cpu_baseline and wl == WORKLOAD:
         cpu = cpu_baseline(A_host, b, k, ts, te, args.cpu_queries)
@@ -261,6 +302,7 @@ def main():
         "single_query_svds_per_s": 1e3 / float(np.mean(lat)) if lat else None,
         "kernels_ms_per_step": {n: v["total_ms"] / args.steps for n, v in kernels.items()},
         "roofline": roof,
+        "kernel_rooflines": kernel_roofs,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -85,6 +85,26 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
                           int64_t b, int32_t k, zs_mode mode, hipStream_t stream, zs_store **out);
 
 /*
+ * zs_store_blocks_xi -- zs_store_blocks with the paper's energy threshold
+ * (Eq. (1), Sec. 2.1; xi = 0.98 in its experiments).  With 0 < xi < 1 every
+ * low-rank approximation of the method keeps the smallest rank whose leading
+ * squared singular values reach xi times the sum of all of them:
+ *   - block i keeps k_i = min(k, rows_i, numerical rank, xi rank of A_(i));
+ *     k is then the cap, and columns past k_i are stored as zeros;
+ *   - the store remembers xi, and every query on it (zs_query,
+ *     zs_query_batch, zs_query_batch_graph) applies the same rule to the
+ *     Partial-SVD of its boundary blocks (Alg. 3) and to the SVD of its
+ *     stacked matrix (Alg. 2): k_out = min(k_q, numerical rank, xi rank).
+ *   The denominator of Eq. (1) is the matrix's squared Frobenius norm (the
+ *   trace of its Gram).  xi = 0 or xi = 1 turns the rule off: the results are
+ *   then those of zs_store_blocks.  Other arguments and errors as in
+ *   zs_store_blocks, plus ZS_EINVAL for xi outside [0, 1] (or NaN).
+ */
+zs_status zs_store_blocks_xi(const void *A, int64_t t, int64_t c, int64_t lda, zs_dtype a_type,
+                             int64_t b, int32_t k, zs_mode mode, double xi, hipStream_t stream,
+                             zs_store **out);
+
+/*
  * zs_query -- query phase for one range (Alg. 2 with Alg. 3).
  *   [t_s, t_e)  0 <= t_s < t_e <= t.   k_q: requested rank, 1 <= k_q <= k.
  *   U       device, n x k_q row-major, leading dimension ldu >= k_q (n = t_e - t_s).

@@ -131,12 +131,41 @@ __device__ int sym_jacobi(double *G, double *W, int n, int ld, double *cs_sh, do
 
 constexpr int kFinRows = 64;   // rows of V_k staged at a time by finalize
 
-__global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *__restrict__ probs,
+// Energy threshold of Eq. (1): triplet j (of rank pos[j] in descending order)
+// is kept when the squared singular values ranked above it, summed in that
+// order, stay below xi times the total energy.  Off unless 0 < xi < 1.
+__device__ __forceinline__ bool xi_keep(const double *sig, const int *inv, int p, double xi,
+                                        double total)
+{
+    if (!(xi > 0.0 && xi < 1.0) || !(total > 0.0)) return true;
+    double run = 0.0;
+    for (int i = 0; i < p; ++i) run += sig[inv[i]] * sig[inv[i]];
+    return run < xi * total;
+}
+
+// Deterministic sum of one value per thread of the work-group (fixed tree).
+__device__ double block_sum(double v, double *red)
+{
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int s = kThreads / 2; s >= 1; s /= 2) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kThreads) void finalize_kernel(int c, int k, const Prob *__restrict__ probs,
                                                             const double *__restrict__ GYpart,
                                                             double *__restrict__ Vk,
                                                             double *__restrict__ F,
                                                             double rank_tol, int kk_max,
-                                                            int *__restrict__ conv_flag)
+                                                            const double *const *__restrict__ gsrc,
+                                                            const double *const *__restrict__ msrc,
+                                                            double xi, int *__restrict__ conv_flag)
 {
     extern __shared__ __align__(16) double smem[];
     const int ld = kk_max + 1;                // leading dimension of the kk x kk matrices
@@ -148,10 +177,26 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *_
     __shared__ int pos[kMaxK], inv[kMaxK], keep[kMaxK];
     __shared__ int flag_sh;
     __shared__ double tr_sh;
+    __shared__ double red[kThreads];
 
     const Prob P = probs[blockIdx.x];
     const int kk = P.kk;
     const int tid = threadIdx.x;
+    // total energy of the matrix whose SVD this is (the denominator of
+    // Eq. (1)): the trace of its c x c Gram, term by term
+    double total = 0.0;
+    if (xi > 0.0 && xi < 1.0) {
+        double part = 0.0;
+        for (int g = 0; g < P.ng; ++g) {
+            const double *Gs = gsrc[P.g0 + g];
+            for (int a = tid; a < c; a += kThreads) part += Gs[(int64_t)a * c + a];
+        }
+        for (int m = 0; m < P.nm; ++m) {
+            const double *R = msrc[P.m0 + m];
+            for (int e = tid; e < k * c; e += kThreads) part += R[e] * R[e];
+        }
+        total = block_sum(part, red);
+    }
     for (int e = tid; e < kk * kk; e += kThreads) {
         const int a = e / kk, b = e % kk;
         double s = 0.0;
@@ -172,8 +217,10 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, const Prob *_
         for (int i = 0; i < kk; ++i) p += (sig[i] > sig[j]) || (sig[i] == sig[j] && i < j);
         pos[j] = p;
         inv[p] = j;
-        keep[j] = (sig[j] > rank_tol * smax) && (sig[j] > 0.0);
     }
+    __syncthreads();
+    for (int j = tid; j < kk; j += kThreads)
+        keep[j] = (sig[j] > rank_tol * smax) && (sig[j] > 0.0) && xi_keep(sig, inv, pos[j], xi, total);
     // Vn = V_k W, in place over V_k (no longer needed), kFinRows rows at a time
     double *Vn = Vk + (int64_t)blockIdx.x * c * kMaxK;
     for (int a0 = 0; a0 < c; a0 += kFinRows) {
@@ -241,7 +288,7 @@ void partial_kernel(StoreView st,
                                                            const int32_t *__restrict__ pidx,
                                                            double *__restrict__ Mp,
                                                            double *__restrict__ T, double rank_tol,
-                                                           int *__restrict__ conv_flag)
+                                                           double xi, int *__restrict__ conv_flag)
 {
     constexpr int RB = kPartialRows;
     extern __shared__ __align__(16) double smem[];
@@ -254,6 +301,7 @@ void partial_kernel(StoreView st,
     double *Ys = Us + RB * k;                 // RB x k rows of Y = P W1
     __shared__ double cs_sh[kMaxK / 2], sn_sh[kMaxK / 2], dp_sh[kMaxK / 2], dq_sh[kMaxK / 2];
     __shared__ double sig[kMaxK], sblk[kMaxK];
+    __shared__ int pinv[kMaxK], pkeep[kMaxK];
     __shared__ int flag_sh;
     __shared__ double tr_sh;
 
@@ -330,6 +378,29 @@ void partial_kernel(StoreView st,
     __syncthreads();
     double smax = 0.0;
     for (int j = 0; j < k; ++j) smax = fmax(smax, sig[j]);
+    // kept triplets: numerically non-zero and within the xi rank of Eq. (1)
+    // over all k singular values of P (its whole spectrum), summed in
+    // descending order
+    for (int j = tid; j < k; j += kThreads) {
+        int p = 0;
+        for (int i = 0; i < k; ++i) p += (sig[i] > sig[j]) || (sig[i] == sig[j] && i < j);
+        pinv[p] = j;
+    }
+    __syncthreads();
+    double total = 0.0;
+    for (int i = 0; i < k; ++i) total += sig[pinv[i]] * sig[pinv[i]];
+    for (int j = tid; j < k; j += kThreads) {
+        int prank = 0;
+        for (int i = 0; i < k; ++i) prank += (sig[i] > sig[j]) || (sig[i] == sig[j] && i < j);
+        bool kp = sig[j] > rank_tol * smax && sig[j] > 0.0;
+        if (kp && xi > 0.0 && xi < 1.0 && total > 0.0) {
+            double run = 0.0;
+            for (int i = 0; i < prank; ++i) run += sig[pinv[i]] * sig[pinv[i]];
+            kp = run < xi * total;
+        }
+        pkeep[j] = kp ? 1 : 0;
+    }
+    __syncthreads();
 
     // stack rows: Mp[j] = sigma~_j (V_(i) v~_j)^T = sigma~_j sum_l v~_lj V_(i)^T[l]
     const TU *Vt = static_cast<const TU *>(st.Vt) + pc.blk * k * st.c;
@@ -338,22 +409,22 @@ void partial_kernel(StoreView st,
         const int j = e / c, col = e % c;
         double s = 0.0;
         for (int l = 0; l < k; ++l) s = fma(G[l * ld + j], (double)Vt[(int64_t)l * c + col], s);
-        Mrows[e] = sig[j] * s;
+        Mrows[e] = pkeep[j] ? sig[j] * s : 0.0;
     }
     // T = Sigma_(i) V~ Sigma~^+  (k x k, row-major)
     double *Tp = T + (int64_t)pc.t_idx * k * k;
     for (int e = tid; e < k * k; e += kThreads) {
         const int a = e / k, j = e % k;
-        const bool kp = sig[j] > rank_tol * smax && sig[j] > 0.0;
-        Tp[e] = kp ? sblk[a] * G[a * ld + j] / sig[j] : 0.0;
+        Tp[e] = pkeep[j] ? sblk[a] * G[a * ld + j] / sig[j] : 0.0;
     }
 }
 
 }  // namespace
 
-hipError_t launch_finalize(int c, const Prob *probs, int nprob, int kk_max, const double *GYpart,
-                           double *Vk, double *F, double rank_tol, int *conv_flag,
-                           hipStream_t stream)
+hipError_t launch_finalize(int c, int k, const Prob *probs, int nprob, int kk_max,
+                           const double *GYpart, double *Vk, double *F, double rank_tol,
+                           const double *const *gsrc, const double *const *msrc, double xi,
+                           int *conv_flag, hipStream_t stream)
 {
     if (nprob <= 0) return hipSuccess;
     if (kk_max < 1 || kk_max > kMaxK) return hipErrorInvalidValue;
@@ -364,8 +435,8 @@ hipError_t launch_finalize(int c, const Prob *probs, int nprob, int kk_max, cons
         hipError_t e = ensure_lds((const void *)finalize_kernel, lds, cur);
         if (e != hipSuccess) return e;
     }
-    finalize_kernel<<<nprob, kThreads, lds, stream>>>(c, probs, GYpart, Vk, F, rank_tol, kk_max,
-                                                      conv_flag);
+    finalize_kernel<<<nprob, kThreads, lds, stream>>>(c, k, probs, GYpart, Vk, F, rank_tol, kk_max,
+                                                      gsrc, msrc, xi, conv_flag);
     hipError_t e = hipGetLastError();
     timing_end("finalize", stream);
     return e;
@@ -375,8 +446,8 @@ namespace {
 
 template <int EPT>
 hipError_t run_partial(StoreView st, const Piece *pieces, const int32_t *pidx, int npartial,
-                       double *Mp, double *T, double rank_tol, int *conv_flag, size_t lds,
-                       hipStream_t stream)
+                       double *Mp, double *T, double rank_tol, double xi, int *conv_flag,
+                       size_t lds, hipStream_t stream)
 {
     static size_t cur_f = 0, cur_d = 0;   // one limit per instantiation
     hipError_t e = st.f32 ? ensure_lds((const void *)partial_kernel<float, EPT>, lds, cur_f)
@@ -384,17 +455,17 @@ hipError_t run_partial(StoreView st, const Piece *pieces, const int32_t *pidx, i
     if (e != hipSuccess) return e;
     if (st.f32)
         partial_kernel<float, EPT><<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T,
-                                                                        rank_tol, conv_flag);
+                                                                        rank_tol, xi, conv_flag);
     else
         partial_kernel<double, EPT><<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T,
-                                                                         rank_tol, conv_flag);
+                                                                         rank_tol, xi, conv_flag);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx, int npartial,
-                          double *Mp, double *T, double rank_tol, int *conv_flag,
+                          double *Mp, double *T, double rank_tol, double xi, int *conv_flag,
                           hipStream_t stream)
 {
     if (npartial <= 0) return hipSuccess;
@@ -403,11 +474,11 @@ hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx
     const size_t lds = (size_t)(3 * st.k * (st.k + 1) + 2 * kPartialRows * st.k) * sizeof(double);
     const int need = (st.k * st.k + kThreads - 1) / kThreads;
     hipError_t e;
-    if (need <= 1) e = run_partial<1>(st, pieces, pidx, npartial, Mp, T, rank_tol, conv_flag, lds, stream);
-    else if (need <= 2) e = run_partial<2>(st, pieces, pidx, npartial, Mp, T, rank_tol, conv_flag, lds, stream);
-    else if (need <= 4) e = run_partial<4>(st, pieces, pidx, npartial, Mp, T, rank_tol, conv_flag, lds, stream);
-    else if (need <= 8) e = run_partial<8>(st, pieces, pidx, npartial, Mp, T, rank_tol, conv_flag, lds, stream);
-    else e = run_partial<16>(st, pieces, pidx, npartial, Mp, T, rank_tol, conv_flag, lds, stream);
+    if (need <= 1) e = run_partial<1>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
+    else if (need <= 2) e = run_partial<2>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
+    else if (need <= 4) e = run_partial<4>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
+    else if (need <= 8) e = run_partial<8>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
+    else e = run_partial<16>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
     timing_end("partial", stream);
     return e;
 }

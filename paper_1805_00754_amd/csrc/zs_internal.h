@@ -126,9 +126,10 @@ hipError_t launch_stack_project(StoreView st, const Piece *pieces, const double 
                                 const StackChunk *chunks, int nchunks, int kq_max,
                                 const double *Vk, double *Y, double *GYpart, hipStream_t stream);
 // Overwrites V_k (no longer needed) with V_k W.
-hipError_t launch_finalize(int c, const Prob *probs, int nprob, int kk_max, const double *GYpart,
-                           double *Vk, double *F, double rank_tol, int *conv_flag,
-                           hipStream_t stream);
+hipError_t launch_finalize(int c, int k, const Prob *probs, int nprob, int kk_max,
+                           const double *GYpart, double *Vk, double *F, double rank_tol,
+                           const double *const *gsrc, const double *const *msrc, double xi,
+                           int *conv_flag, hipStream_t stream);
 // U <- Y F per chunk; Y is FP64, U has the store's element type (may alias Y
 // in FP64 mode).
 hipError_t launch_utransform(const double *Y, void *U, int u_f32, int k, const Chunk *chunks,
@@ -145,7 +146,7 @@ hipError_t launch_eig_big(int c, int k, const Prob *probs, int nprob, const doub
 hipError_t launch_tree_level(int c, double *tree, int64_t node0, int64_t nnodes,
                              hipStream_t stream);
 hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx, int npartial,
-                          double *Mp, double *T, double rank_tol, int *conv_flag,
+                          double *Mp, double *T, double rank_tol, double xi, int *conv_flag,
                           hipStream_t stream);
 hipError_t launch_expand_pieces(StoreView st, const QueryDesc *qd, int nq, int max_np, Piece *pieces,
                                 hipStream_t stream);

@@ -130,6 +130,7 @@ struct zs_store {
     int32_t k = 0;
     zs_mode mode = ZS_MODE_FP64;
     int device = 0;
+    void *base = nullptr;               // one allocation holding the arrays below
     void *U = nullptr, *Vt = nullptr;   // double in FP64 mode, float otherwise
     double *S = nullptr;
     int f32 = 0;                        // U and Vt hold float
@@ -137,6 +138,7 @@ struct zs_store {
     // numerical-rank threshold relative to sigma_1: FP32 storage rounds the
     // factors at about 1e-7, so a tighter cut would count rounding as rank
     double rank_tol() const { return f32 ? kRankTolF32 : kRankTolFP64; }
+    double xi = 0.0;                    // energy threshold of Eq. (1), 0: none
     int32_t *kvec = nullptr;
     double *tree = nullptr;       // Gram tree: 2 * n2 nodes of c x c (node 0 unused)
     int64_t n2 = 1;               // leaves of the Gram tree (power of two >= nb)
@@ -433,13 +435,14 @@ zs_status query_launch(zs_store *st, const QueryPlan &pl, Workspace *w, hipStrea
     const StoreView sv = st->view();
     HIP_TRY(launch_expand_pieces(sv, d_qds, pl.nq, pl.max_np, w->P.as<Piece>(), stream));
     HIP_TRY(launch_partial(sv, d_pieces, d_pidx, pl.npartial, Mp, w->T.as<double>(), st->rank_tol(),
-                           st->conv, stream));
+                           st->xi, st->conv, stream));
     HIP_TRY(first_stage_eig((int)c, k, d_probs, pl.nq, d_gsrc, d_msrc, w->Vk.as<double>(), w->big,
                             st->conv, stream));
     HIP_TRY(launch_stack_project(sv, d_pieces, Mp, d_chunks, pl.nchunks, pl.kq_max,
                                  w->Vk.as<double>(), w->Y.as<double>(), w->GY.as<double>(), stream));
-    HIP_TRY(launch_finalize((int)c, d_probs, pl.nq, pl.kq_max, w->GY.as<double>(), w->Vk.as<double>(),
-                            w->F.as<double>(), st->rank_tol(), st->conv, stream));
+    HIP_TRY(launch_finalize((int)c, k, d_probs, pl.nq, pl.kq_max, w->GY.as<double>(),
+                            w->Vk.as<double>(), w->F.as<double>(), st->rank_tol(), d_gsrc, d_msrc,
+                            st->xi, st->conv, stream));
     HIP_TRY(launch_coef(k, pl.kq_max, d_pieces, d_chunks, pl.nchunks, w->Y.as<double>(),
                         w->F.as<double>(), w->T.as<double>(), w->C.as<double>(), stream));
     HIP_TRY(launch_order_pieces(d_pieces, pl.npieces, st->nb, d_boff, w->bcount.as<int32_t>(),
@@ -491,7 +494,15 @@ const char *zs_version(void) { return "zoomsvd-gfx950 0.1"; }
 zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_dtype a_type,
                           int64_t b, int32_t k, zs_mode mode, hipStream_t stream, zs_store **out)
 {
+    return zs_store_blocks_xi(A, t, c, lda, a_type, b, k, mode, 0.0, stream, out);
+}
+
+zs_status zs_store_blocks_xi(const void *A, int64_t t, int64_t c, int64_t lda, zs_dtype a_type,
+                             int64_t b, int32_t k, zs_mode mode, double xi, hipStream_t stream,
+                             zs_store **out)
+{
     if (!out) return fail(ZS_EINVAL, "out is null");
+    if (!(xi >= 0.0 && xi <= 1.0)) return fail(ZS_EINVAL, "xi = %g outside [0, 1]", xi);
     *out = nullptr;
     if (!A) return fail(ZS_EINVAL, "A is null");
     if (t < 1) return fail(ZS_EINVAL, "t = %lld < 1", (long long)t);
@@ -509,6 +520,7 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
 
     zs_store *st = new zs_store();
     st->t = t; st->c = c; st->b = b; st->k = k; st->mode = mode;
+    st->xi = xi > 0.0 && xi < 1.0 ? xi : 0.0;
     st->f32 = mode == ZS_MODE_FP64 ? 0 : 1;
     st->nb = (t + b - 1) / b;
     const int64_t nb = st->nb;
@@ -524,13 +536,25 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
             return cleanup(fail(e_ == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "%s: %s", \
                                 #expr, hipGetErrorString(e_)));                             \
     } while (0)
-    ST_TRY(hipMalloc(&st->U, st->esize() * t * k));
-    ST_TRY(hipMalloc(&st->Vt, st->esize() * nb * k * c));
-    ST_TRY(hipMalloc(&st->S, sizeof(double) * nb * k));
-    ST_TRY(hipMalloc(&st->kvec, sizeof(int32_t) * nb));
+    // the store's arrays share one allocation (one driver call per store)
     while (st->n2 < nb) st->n2 *= 2;
-    ST_TRY(hipMalloc(&st->tree, sizeof(double) * 2 * st->n2 * c * c));
-    ST_TRY(hipMalloc(&st->conv, sizeof(int)));
+    {
+        const size_t sz[6] = {st->esize() * t * k, st->esize() * nb * k * c, sizeof(double) * nb * k,
+                              sizeof(int32_t) * nb, sizeof(double) * 2 * st->n2 * c * c, sizeof(int)};
+        size_t off[6], total = 0;
+        for (int i = 0; i < 6; ++i) {
+            off[i] = total;
+            total = align_up(total + sz[i], 256);
+        }
+        ST_TRY(hipMalloc(&st->base, total));
+        char *p = static_cast<char *>(st->base);
+        st->U = p + off[0];
+        st->Vt = p + off[1];
+        st->S = reinterpret_cast<double *>(p + off[2]);
+        st->kvec = reinterpret_cast<int32_t *>(p + off[3]);
+        st->tree = reinterpret_cast<double *>(p + off[4]);
+        st->conv = reinterpret_cast<int *>(p + off[5]);
+    }
     ST_TRY(hipMemsetAsync(st->conv, 0, sizeof(int), stream));
 
     // Work lists: one problem per block.  The Gram works on chunks of at most
@@ -636,8 +660,9 @@ zs_status zs_store_blocks(const void *A, int64_t t, int64_t c, int64_t lda, zs_d
                             st->conv, stream));
     ST_TRY2(launch_project(A, x_type, lda, (int)c, d_pchunks, npchunks, k, Vk.as<double>(), Y,
                            GY.as<double>(), stream));
-    ST_TRY2(launch_finalize((int)c, d_probs, (int)nb, k, GY.as<double>(), Vk.as<double>(),
-                            F.as<double>(), st->rank_tol(), st->conv, stream));
+    ST_TRY2(launch_finalize((int)c, k, d_probs, (int)nb, k, GY.as<double>(), Vk.as<double>(),
+                            F.as<double>(), st->rank_tol(), d_gsrc, nullptr, st->xi, st->conv,
+                            stream));
     ST_TRY2(launch_utransform(Y, st->U, st->f32, k, d_pchunks, npchunks, F.as<double>(), stream));
     // Gram tree over the stored blocks: leaves, then one launch per level.  For
     // c > 128 a leaf is the Gram of the block's rows sigma_ij v_ij^T, formed by
@@ -815,12 +840,7 @@ void zs_store_free(zs_store *st)
         kv.second->release();
         delete kv.second;
     }
-    if (st->U) (void)hipFree(st->U);
-    if (st->Vt) (void)hipFree(st->Vt);
-    if (st->S) (void)hipFree(st->S);
-    if (st->kvec) (void)hipFree(st->kvec);
-    if (st->tree) (void)hipFree(st->tree);
-    if (st->conv) (void)hipFree(st->conv);
+    if (st->base) (void)hipFree(st->base);
     delete st;
 }
 

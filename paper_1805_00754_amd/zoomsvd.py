@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "ZS_OK", -1: "ZS_EINVAL", -2: "ZS_ERANGE", -3: "ZS_ENOMEM", -
                 -5: "ZS_EDEVICE", -6: "ZS_EUNSUPPORTED"}
 
 # Symbols the header declares (the CPU test checks the library exports all).
-EXPORTED = ["zs_store_blocks", "zs_query", "zs_query_batch", "zs_query_batch_graph",
+EXPORTED = ["zs_store_blocks", "zs_store_blocks_xi", "zs_query", "zs_query_batch", "zs_query_batch_graph",
             "zs_batch_graph_launch", "zs_batch_graph_free", "zs_store_free", "zs_store_bytes",
             "zs_store_info", "zs_store_get_block", "zs_sync_status", "zs_last_error", "zs_version",
             "zs_timing_enable", "zs_timing_reset", "zs_timing_get"]
@@ -61,6 +61,8 @@ def load(path: str | None = None):
         lib = ctypes.CDLL(p)
         lib.zs_store_blocks.argtypes = [_vp, _i64, _i64, _i64, ctypes.c_int, _i64, _i32,
                                         ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+        lib.zs_store_blocks_xi.argtypes = [_vp, _i64, _i64, _i64, ctypes.c_int, _i64, _i32,
+                                           ctypes.c_int, ctypes.c_double, _vp, ctypes.POINTER(_vp)]
         lib.zs_query.argtypes = [_vp, _i64, _i64, _i32, _vp, _i64, _vp, _vp, _i64, _vp, _vp]
         lib.zs_query_batch.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                        _vp, _vp]
@@ -82,7 +84,7 @@ def load(path: str | None = None):
         lib.zs_timing_enable.restype = None
         lib.zs_timing_reset.restype = None
         lib.zs_timing_get.argtypes = [ctypes.c_char_p, _vp, _vp]
-        for name in ("zs_store_blocks", "zs_query", "zs_query_batch", "zs_store_info",
+        for name in ("zs_store_blocks", "zs_store_blocks_xi", "zs_query", "zs_query_batch", "zs_store_info",
                      "zs_store_get_block", "zs_sync_status", "zs_timing_get",
                      "zs_query_batch_graph", "zs_batch_graph_launch"):
             getattr(lib, name).restype = ctypes.c_int
@@ -117,9 +119,10 @@ def _ptr(t: torch.Tensor) -> int:
 class Store:
     """A device-resident store (Def. 2 sets U, S, V) owned by the library."""
 
-    def __init__(self, handle: int, t: int, c: int, b: int, k: int, mode: int):
+    def __init__(self, handle: int, t: int, c: int, b: int, k: int, mode: int, xi: float = 0.0):
         self.handle = handle
         self.t, self.c, self.b, self.k, self.mode = t, c, b, k, mode
+        self.xi = xi
         self.nb = (t + b - 1) // b
 
     def block_rows(self, i: int) -> int:
@@ -141,21 +144,28 @@ class Store:
         return torch.float64 if self.mode == ZS_MODE_FP64 else torch.float32
 
 
-def zs_store_blocks(A: torch.Tensor, b: int, k: int, mode: int = ZS_MODE_FP64, stream=None) -> Store:
+def zs_store_blocks(A: torch.Tensor, b: int, k: int, mode: int = ZS_MODE_FP64, stream=None,
+                    xi: float = 0.0) -> Store:
     """Storage phase: compress every b-row block of A (t x c, on the GPU) to
-    its rank-k SVD.  Raises ZSError on failure (ZS_ENOCONV still leaves the
-    error raised; the store is freed)."""
+    its rank-k SVD (zs_store_blocks), or with 0 < xi < 1 to the rank of the
+    energy threshold of Eq. (1) capped at k (zs_store_blocks_xi; queries on the
+    store then apply the same rule).  Raises ZSError on failure (ZS_ENOCONV
+    still leaves the error raised; the store is freed)."""
     if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
         raise ValueError("A must be a 2-D CUDA/HIP tensor with unit column stride")
     a_type = {torch.float64: ZS_F64, torch.float32: ZS_F32, torch.bfloat16: ZS_BF16}[A.dtype]
     t, c = A.shape
     h = _vp()
-    st = load().zs_store_blocks(_vp(_ptr(A)), t, c, A.stride(0), a_type, b, k, mode,
-                                _vp(_stream(stream)), ctypes.byref(h))
+    if xi:
+        st = load().zs_store_blocks_xi(_vp(_ptr(A)), t, c, A.stride(0), a_type, b, k, mode,
+                                       float(xi), _vp(_stream(stream)), ctypes.byref(h))
+    else:
+        st = load().zs_store_blocks(_vp(_ptr(A)), t, c, A.stride(0), a_type, b, k, mode,
+                                    _vp(_stream(stream)), ctypes.byref(h))
     if st == ZS_ENOCONV and h.value:
         load().zs_store_free(h)
     _check(st)
-    return Store(h.value, t, c, b, k, mode)
+    return Store(h.value, t, c, b, k, mode, float(xi))
 
 
 def zs_query(st: Store, t_s: int, t_e: int, k_q: int, U=None, S=None, V=None, k_out=None,

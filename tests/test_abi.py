@@ -62,6 +62,18 @@ def test_store_rejects_bad_arguments(zs):
     assert lib.zs_store_blocks(A, 10, 4, 4, 0, 2, 2, 0, vp(0), None) == zs.ZS_EINVAL
 
 
+def test_store_xi_rejects_bad_threshold(zs):
+    lib = zs.load()
+    vp = ctypes.c_void_p
+    out = vp()
+    A = vp(0x1000)   # never dereferenced: validation happens first
+    for xi in (-0.1, 1.5, float("nan")):
+        assert lib.zs_store_blocks_xi(A, 10, 4, 4, 0, 2, 2, 0, xi, vp(0), ctypes.byref(out)) \
+            == zs.ZS_EINVAL, xi
+        assert out.value is None
+    assert "xi" in zs.zs_last_error()
+
+
 def test_query_rejects_null_store(zs):
     lib = zs.load()
     vp = ctypes.c_void_p
