@@ -147,6 +147,30 @@ def main():
     g.free()
     log("graph replay %.2f ms" % float(np.mean(graph_ms)))
 
+    # The case study of Sec. 5: u_1 of every earlier 20,000-row window (stride
+    # 500) against u_1 of the last 20,000 rows, all windows as one batch.
+    windows = None
+    if wl == WORKLOAD and t >= 40_000:
+        W, stride = 20_000, 500
+        base = t - W
+        nw = base // stride
+        sim = zs.zs_window_similarity(st, base, t, stride, nw)      # warm-up
+        torch.cuda.synchronize()
+        wms = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            zs.zs_window_similarity(st, base, t, stride, nw, sim=sim)
+            e1.record(stream)
+            e1.synchronize()
+            wms.append(e0.elapsed_time(e1))
+        top = torch.topk(sim, 2).indices.cpu().numpy() + 1
+        windows = {"window_rows": W, "stride": stride, "windows": nw,
+                   "ms": float(np.mean(wms)), "windows_per_s": nw / (float(np.mean(wms)) / 1e3),
+                   "most_similar_offsets_rows": [int(x) * stride for x in top]}
+        log("window similarity: %d windows in %.2f ms" % (nw, windows["ms"]))
+
     # Write ceiling of this very output allocation: a plain fill of the batch's
     # U buffer.  Sustained write bandwidth into a large allocation depends on
     # where it landed in physical memory (5.5 to 6.9 TB/s seen for the same
@@ -304,6 +328,7 @@ def main():
         "roofline": roof,
         "kernel_rooflines": kernel_roofs,
         "serving": serving,
+        "windows": windows,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

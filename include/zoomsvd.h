@@ -134,7 +134,25 @@ zs_status zs_query_batch(const zs_store *st, int32_t nq, const int64_t *t_s, con
                          const int64_t *s_off, void *V, const int64_t *v_off, int32_t *k_out,
                          hipStream_t stream);
 
-/* Releases the store's device memory (synchronises the device first). */
+/*
+ * zs_window_similarity -- the measure of the paper's case study of finding
+ * similar time ranges (Sec. 5): u_1, the first left singular vector of the
+ * range (Problem 1 at rank 1, computed by the query phase), of the base
+ * range [t_s, t_e) and of each earlier window of the same length,
+ * [t_s - w*stride, t_e - w*stride) for w = 1..n_windows, all answered as one
+ * batch; then the cosine of each window's u_1 with the base's, row by row
+ * within the window.
+ *   stride      >= 1 rows; the last window must start at >= 0, else ZS_ERANGE.
+ *   sim         device, n_windows doubles: sim[w - 1] = <u_base, u_w> /
+ *               (|u_base| |u_w|), 0 when either range has rank 0.  Signs
+ *               follow the sign rule of the query outputs.
+ *   The windows' factors go to scratch of the store for this stream (n
+ *   rows per window), not to the caller.  Asynchronous on `stream`.  Errors as
+ *   in zs_query_batch, plus ZS_EINVAL for stride < 1 or n_windows < 1.
+ */
+zs_status zs_window_similarity(const zs_store *st, int64_t t_s, int64_t t_e, int64_t stride,
+                               int32_t n_windows, double *sim, hipStream_t stream);
+
 /*
  * zs_query_batch_graph -- the batched query form captured into a HIP graph
  * for repeated replay of one fixed batch (the same ranges, ranks and output
@@ -165,6 +183,8 @@ zs_status zs_batch_graph_launch(zs_batch_graph *g, hipStream_t stream);
  * Every replay must have completed. */
 void zs_batch_graph_free(zs_batch_graph *g);
 
+/* Releases the store's device memory (synchronises the device first); NULL is
+ * a no-op. */
 void zs_store_free(zs_store *st);
 
 /* Device bytes held by the store: the block factors (8 or 4 bytes per element

@@ -266,6 +266,20 @@ def query_batch(st: Store, ts, te, kq, lib=None):
     return res
 
 
+def window_similarity(st: Store, t_s: int, t_e: int, stride: int, n_windows: int, lib=None):
+    """The case study of Sec. 5 (finding similar time ranges): u_1 of the base
+    range [t_s, t_e) and of every earlier window [t_s - w stride, t_e - w
+    stride), w = 1..n_windows, each from the query phase at rank 1; returns
+    the cosines <u_base, u_w> / (|u_base| |u_w|) (0 for a zero vector)."""
+    u0 = query(st, t_s, t_e, 1, lib=lib)[0][:, 0]
+    out = np.zeros(n_windows)
+    for w in range(1, n_windows + 1):
+        uw = query(st, t_s - w * stride, t_e - w * stride, 1, lib=lib)[0][:, 0]
+        den = np.linalg.norm(u0) * np.linalg.norm(uw)
+        out[w - 1] = float(u0 @ uw) / den if den > 0 else 0.0
+    return out
+
+
 def direct(A, t_s: int, t_e: int, kq: int, rank_tol: float = RANK_TOL, lib=None):
     """SVD of the raw rows A[t_s:t_e) truncated to kq (Problem 1)."""
     lib = lib or load()

@@ -157,6 +157,10 @@ hipError_t launch_coef(int k, int kq_max, const Piece *pieces, const StackChunk 
 // block 1, ... (boff[i] = first position of block i; bcount is nb counters).
 hipError_t launch_order_pieces(const Piece *pieces, int npieces, int64_t nb, const int32_t *boff,
                                int32_t *bcount, int32_t *perm, hipStream_t stream);
+// sim[w - 1] = cosine of u_1 of window w with u_1 of the base (window 0); U
+// holds nw + 1 vectors of n elements (float when u_f32).
+hipError_t launch_cosine(const void *U, int u_f32, int64_t n, int nw, double *sim,
+                         hipStream_t stream);
 // contiguous: every query's U has leading dimension k_q (rows back to back)
 hipError_t launch_blockprod(StoreView st, const Piece *pieces, const int32_t *perm, int npieces,
                             const double *C, void *U, bool contiguous, hipStream_t stream);

@@ -88,6 +88,7 @@ struct DevBuf {
 // Scratch of the query pipeline for one stream (grow-only).
 struct Workspace {
     DevBuf Mp, Vk, Y, GY, F, T, C, P, perm, bcount, big, desc;
+    DevBuf wU, wS, wV, wK;       // outputs of the windows of zs_window_similarity
     void *host = nullptr;        // pinned staging of the descriptors
     size_t host_bytes = 0;
     hipEvent_t copied = nullptr; // the last upload from `host` has completed
@@ -96,6 +97,7 @@ struct Workspace {
         Mp.release(); Vk.release(); Y.release(); GY.release();
         F.release(); T.release(); C.release(); P.release(); perm.release(); bcount.release();
         big.release(); desc.release();
+        wU.release(); wS.release(); wV.release(); wK.release();
         if (host) (void)hipHostFree(host);
         if (copied) (void)hipEventDestroy(copied);
         host = nullptr;
@@ -748,6 +750,50 @@ zs_status zs_query_batch(const zs_store *cst, int32_t nq, const int64_t *t_s, co
     zs_store *st = const_cast<zs_store *>(cst);
     return query_impl(st, nq, t_s, t_e, k_q, U, u_off, ld.data(), S, s_off, V, v_off, ld.data(),
                       k_out, stream);
+}
+
+zs_status zs_window_similarity(const zs_store *cst, int64_t t_s, int64_t t_e, int64_t stride,
+                               int32_t n_windows, double *sim, hipStream_t stream)
+{
+    if (!cst) return fail(ZS_EINVAL, "store is null");
+    if (!sim) return fail(ZS_EINVAL, "sim is null");
+    zs_status s = check_query(cst, t_s, t_e, 1);
+    if (s != ZS_OK) return s;
+    if (stride < 1) return fail(ZS_EINVAL, "stride = %lld < 1", (long long)stride);
+    if (n_windows < 1) return fail(ZS_EINVAL, "n_windows = %d < 1", n_windows);
+    if (t_s - (int64_t)n_windows * stride < 0)
+        return fail(ZS_ERANGE, "window %d would start at %lld < 0", n_windows,
+                    (long long)(t_s - (int64_t)n_windows * stride));
+    zs_store *st = const_cast<zs_store *>(cst);
+    // the base and its earlier windows as one batch of rank-1 queries
+    const int32_t nq = n_windows + 1;
+    const int64_t n = t_e - t_s;
+    std::vector<int64_t> ts(nq), te(nq), u_off(nq), s_off(nq), v_off(nq), ld(nq, 1);
+    std::vector<int32_t> kq(nq, 1);
+    for (int32_t w = 0; w < nq; ++w) {
+        ts[w] = t_s - (int64_t)w * stride;
+        te[w] = t_e - (int64_t)w * stride;
+        u_off[w] = (int64_t)w * n;
+        s_off[w] = w;
+        v_off[w] = (int64_t)w * st->c;
+    }
+    Workspace *w;
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        auto it = st->ws.find(stream);
+        if (it == st->ws.end()) it = st->ws.emplace(stream, new Workspace()).first;
+        w = it->second;
+    }
+    HIP_TRY(w->wU.ensure(st->esize() * (size_t)nq * n));
+    HIP_TRY(w->wS.ensure(sizeof(double) * (size_t)nq));
+    HIP_TRY(w->wV.ensure(st->esize() * (size_t)nq * st->c));
+    HIP_TRY(w->wK.ensure(sizeof(int32_t) * (size_t)nq));
+    s = query_impl(st, nq, ts.data(), te.data(), kq.data(), w->wU.p, u_off.data(), ld.data(),
+                   w->wS.as<double>(), s_off.data(), w->wV.p, v_off.data(), ld.data(),
+                   w->wK.as<int32_t>(), stream);
+    if (s != ZS_OK) return s;
+    HIP_TRY(launch_cosine(w->wU.p, st->f32, n, n_windows, sim, stream));
+    return ZS_OK;
 }
 
 struct zs_batch_graph {

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "ZS_OK", -1: "ZS_EINVAL", -2: "ZS_ERANGE", -3: "ZS_ENOMEM", -
                 -5: "ZS_EDEVICE", -6: "ZS_EUNSUPPORTED"}
 
 # Symbols the header declares (the CPU test checks the library exports all).
-EXPORTED = ["zs_store_blocks", "zs_store_blocks_xi", "zs_query", "zs_query_batch", "zs_query_batch_graph",
+EXPORTED = ["zs_store_blocks", "zs_store_blocks_xi", "zs_window_similarity", "zs_query", "zs_query_batch", "zs_query_batch_graph",
             "zs_batch_graph_launch", "zs_batch_graph_free", "zs_store_free", "zs_store_bytes",
             "zs_store_info", "zs_store_get_block", "zs_sync_status", "zs_last_error", "zs_version",
             "zs_timing_enable", "zs_timing_reset", "zs_timing_get"]
@@ -64,6 +64,7 @@ def load(path: str | None = None):
         lib.zs_store_blocks_xi.argtypes = [_vp, _i64, _i64, _i64, ctypes.c_int, _i64, _i32,
                                            ctypes.c_int, ctypes.c_double, _vp, ctypes.POINTER(_vp)]
         lib.zs_query.argtypes = [_vp, _i64, _i64, _i32, _vp, _i64, _vp, _vp, _i64, _vp, _vp]
+        lib.zs_window_similarity.argtypes = [_vp, _i64, _i64, _i64, _i32, _vp, _vp]
         lib.zs_query_batch.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                        _vp, _vp]
         lib.zs_query_batch_graph.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -84,7 +85,7 @@ def load(path: str | None = None):
         lib.zs_timing_enable.restype = None
         lib.zs_timing_reset.restype = None
         lib.zs_timing_get.argtypes = [ctypes.c_char_p, _vp, _vp]
-        for name in ("zs_store_blocks", "zs_store_blocks_xi", "zs_query", "zs_query_batch", "zs_store_info",
+        for name in ("zs_store_blocks", "zs_store_blocks_xi", "zs_window_similarity", "zs_query", "zs_query_batch", "zs_store_info",
                      "zs_store_get_block", "zs_sync_status", "zs_timing_get",
                      "zs_query_batch_graph", "zs_batch_graph_launch"):
             getattr(lib, name).restype = ctypes.c_int
@@ -235,6 +236,19 @@ def zs_query_batch(st: Store, t_s, t_e, k_q, out: Batch | None = None, stream=No
                                  _vp(_ptr(out.V)), a(out.v_off), _vp(_ptr(out.k_out)),
                                  _vp(_stream(stream))))
     return out
+
+
+def zs_window_similarity(st: Store, t_s: int, t_e: int, stride: int, n_windows: int,
+                         sim=None, stream=None) -> torch.Tensor:
+    """Cosine of u_1 of each earlier window [t_s - w stride, t_e - w stride),
+    w = 1..n_windows, with u_1 of the base range [t_s, t_e) (the case study of
+    Sec. 5).  Returns a device tensor of n_windows doubles."""
+    if sim is None:
+        sim = torch.empty(n_windows, dtype=torch.float64,
+                          device=torch.device("cuda", torch.cuda.current_device()))
+    _check(load().zs_window_similarity(_vp(st.handle), t_s, t_e, stride, n_windows, _vp(_ptr(sim)),
+                                       _vp(_stream(stream))))
+    return sim
 
 
 class BatchGraph:

@@ -74,6 +74,13 @@ def test_store_xi_rejects_bad_threshold(zs):
     assert "xi" in zs.zs_last_error()
 
 
+def test_window_similarity_rejects_bad_arguments(zs):
+    lib = zs.load()
+    vp = ctypes.c_void_p
+    assert lib.zs_window_similarity(vp(0), 10, 20, 5, 2, vp(8), vp(0)) == zs.ZS_EINVAL
+    assert lib.zs_window_similarity(vp(8), 10, 20, 5, 2, vp(0), vp(0)) == zs.ZS_EINVAL
+
+
 def test_query_rejects_null_store(zs):
     lib = zs.load()
     vp = ctypes.c_void_p
