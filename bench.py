@@ -52,6 +52,10 @@ def main():
                     help="named synthetic workload (synth.WORKLOADS); the default is the one "
                          "the headline metric is quoted on")
     ap.add_argument("--query-len", type=int, default=QUERY_LEN)
+    ap.add_argument("--sweep-b", default=None,
+                    help="comma-separated block sizes: instead of the benchmark, store the "
+                         "workload at each b and time query batches at range lengths 1e3, 1e4 "
+                         "and 1e5 (the paper's block-size study), one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -68,6 +72,9 @@ def main():
     zs.load()
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream()
+
+    if args.sweep_b:
+        return sweep_b(args)
 
     wl = args.workload
     log("generating %s" % wl)
@@ -332,6 +339,73 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
+
+
+def sweep_b(args):
+    """The paper's block-size study on the synthetic workload: for each b, the
+    store time, the stored elements against the raw matrix (Thm. 3:
+    sum_i k_i (b_i + 1 + c) with k_i = min(k, b_i) on full-rank noisy blocks)
+    and the time of a batch of queries at each range length."""
+    import numpy as np
+    import torch
+
+    from paper_1805_00754_amd import synth
+    from paper_1805_00754_amd import zoomsvd as zs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    zs.load()
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    ser, cfg = synth.workload(args.workload)
+    t, c = ser.A.shape
+    k = cfg["k"]
+    A = torch.from_numpy(ser.A).to(dev)
+    lengths = [1_000, 10_000, 100_000]
+    nq = args.queries
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    rows = []
+    for b in [int(x) for x in args.sweep_b.split(",") if x]:
+        log("b = %d" % b)
+        holder = {}
+
+        def store():
+            if "st" in holder:
+                holder.pop("st").free()
+            holder["st"] = zs.zs_store_blocks(A, b, k)
+        store_ms = timed(store)
+        st = holder["st"]
+        nb = (t + b - 1) // b
+        brows = np.minimum(b, t - np.arange(nb) * b)
+        elems = int((np.minimum(k, brows) * (brows + 1 + c)).sum())
+        q = {}
+        for L in lengths:
+            ts, te = synth.queries_fixed(synth.rng_for(synth.SEED_BASE + 9), t, nq, L)
+            out = zs.Batch(st, ts, te, np.full(nq, k, np.int32), dev)
+            qms = timed(lambda: zs.zs_query_batch(st, ts, te, k, out=out))
+            q[str(L)] = {"batch_ms": qms, "svds_per_s": nq / (qms / 1e3)}
+            del out
+        rows.append({"b": b, "blocks": nb, "store_ms": store_ms,
+                     "store_gbps": t * c * 8 / (store_ms / 1e3) / 1e9,
+                     "stored_elements": elems, "compression": t * c / elems, "queries": q})
+        st.free()
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "block-size sweep (store time, compression, query batches)",
+                      "workload": args.workload, "t": t, "c": c, "k": k, "queries_per_batch": nq,
+                      "range_lengths": lengths, "sweep": rows}), flush=True)
 
 
 def serve_runs(st, args):
