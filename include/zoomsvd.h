@@ -105,6 +105,28 @@ zs_status zs_store_blocks_xi(const void *A, int64_t t, int64_t c, int64_t lda, z
                              zs_store **out);
 
 /*
+ * zs_store_append -- streaming ingest: appends m rows (time ticks t .. t+m-1)
+ * to the store.  Rows first fill the store's last block by the incremental
+ * update of Alg. 1 (Eqs. (2)-(3)) taken for those rows at once: the last
+ * block's [Sigma V^T; new rows] is decomposed by the storage phase, U' Sigma'
+ * V'^T, truncated as any block (k, numerical rank, and xi when the store has
+ * one), and the block's U becomes diag(U, I) U'.  The remaining rows form new
+ * blocks of b rows, compressed as by zs_store_blocks.  With every block of
+ * rank <= k the result equals compressing all rows at once; otherwise the
+ * last block carries the truncation of both updates.
+ *   R      device pointer, m x c row-major, leading dimension ldr >= c,
+ *          element type r_type.  Read during the call only.
+ *   The store's arrays are reallocated (its device pointers change): no other
+ *   call on the store may overlap this one, and a zs_batch_graph captured on
+ *   the store before the append must not be replayed after it.  Queries made
+ *   after the call see all t + m rows.  Synchronises `stream`.  On an error
+ *   the store is unchanged; ZS_ENOCONV as in zs_store_blocks (the rows are
+ *   appended).
+ */
+zs_status zs_store_append(zs_store *st, const void *R, int64_t m, int64_t ldr, zs_dtype r_type,
+                          hipStream_t stream);
+
+/*
  * zs_query -- query phase for one range (Alg. 2 with Alg. 3).
  *   [t_s, t_e)  0 <= t_s < t_e <= t.   k_q: requested rank, 1 <= k_q <= k.
  *   U       device, n x k_q row-major, leading dimension ldu >= k_q (n = t_e - t_s).

@@ -170,6 +170,39 @@ def store(A, b: int, k: int, rank_tol: float = RANK_TOL, lib=None, xi: float = 0
     return Store(t, c, b, k, U, S, V, k_i, rank_tol, xi)
 
 
+def append(st: Store, R, lib=None) -> Store:
+    """Streaming ingest (Alg. 1's incremental update, Eqs. (2)-(3), for the
+    appended rows at once): the rows first fill the last block,
+        [U S V^T; R1] = diag(U, I) [S V^T; R1],  [S V^T; R1] = U' S' V'^T,
+    the last block becoming diag(U, I) U', S', V' (truncated as any block);
+    the remaining rows form new blocks as in the storage phase.  Returns a new
+    Store of t + m rows."""
+    lib = lib or load()
+    R = _f64(R)
+    m = R.shape[0]
+    t0, b, k, c = st.t, st.b, st.k, st.c
+    nb0 = st.nb
+    r_tail = t0 - (nb0 - 1) * b
+    m1 = min(m, b - r_tail) if r_tail < b else 0
+    U = [st.U]
+    S, V, k_i = st.S.copy(), st.V.copy(), st.k_i.copy()
+    if m1:
+        i = nb0 - 1
+        P = np.vstack([st.S[i][:, None] * st.V[i].T, R[:m1]])       # (k + m1) x c
+        tp = store(P, k + m1, k, rank_tol=st.rank_tol, lib=lib, xi=st.xi)
+        Ut = np.vstack([st.U[i * b:i * b + r_tail] @ tp.U[:k], tp.U[k:]])
+        U = [st.U[:i * b], Ut]
+        S[i], V[i], k_i[i] = tp.S[0], tp.V[0], tp.k_i[0]
+    if m > m1:
+        nst = store(R[m1:], b, k, rank_tol=st.rank_tol, lib=lib, xi=st.xi)
+        U.append(nst.U)
+        S = np.concatenate([S, nst.S])
+        V = np.concatenate([V, nst.V])
+        k_i = np.concatenate([k_i, nst.k_i])
+    return Store(t0 + m, c, b, k, np.ascontiguousarray(np.vstack(U)), np.ascontiguousarray(S),
+                 np.ascontiguousarray(V), np.ascontiguousarray(k_i, np.int32), st.rank_tol, st.xi)
+
+
 def store_from_arrays(t, c, b, k, U, S, V, k_i=None, rank_tol: float = RANK_TOL,
                       xi: float = 0.0) -> Store:
     """Wrap block factors produced elsewhere (e.g. downloaded from the GPU)

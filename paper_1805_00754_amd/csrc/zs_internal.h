@@ -157,6 +157,13 @@ hipError_t launch_coef(int k, int kq_max, const Piece *pieces, const StackChunk 
 // block 1, ... (boff[i] = first position of block i; bcount is nb counters).
 hipError_t launch_order_pieces(const Piece *pieces, int npieces, int64_t nb, const int32_t *boff,
                                int32_t *bcount, int32_t *perm, hipStream_t stream);
+// Streaming ingest (append.hip).  P = [sigma_j v_j^T rows of block blk (k);
+// m1 rows of R (element type r_type, leading dimension ldr)] in FP64.
+hipError_t launch_tail_rows(StoreView st, int64_t blk, const void *R, int r_type, int64_t ldr,
+                            int64_t m1, double *P, hipStream_t stream);
+// Unew (r_tail + m1 rows x k) = [Uold Up[0:k]; Up[k:k+m1]], all k columns wide.
+hipError_t launch_tail_u(const void *Uold, int64_t r_tail, const void *Up, int64_t m1, int k, int f32,
+                         void *Unew, hipStream_t stream);
 // sim[w - 1] = cosine of u_1 of window w with u_1 of the base (window 0); U
 // holds nw + 1 vectors of n elements (float when u_f32).
 hipError_t launch_cosine(const void *U, int u_f32, int64_t n, int nw, double *sim,

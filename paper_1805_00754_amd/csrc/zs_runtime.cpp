@@ -752,6 +752,166 @@ zs_status zs_query_batch(const zs_store *cst, int32_t nq, const int64_t *t_s, co
                       k_out, stream);
 }
 
+// The Gram tree of a store from its factors: leaves, then one launch per
+// level (leaves past nb are zero).  Synchronises the stream.
+static zs_status build_tree(zs_store *st, hipStream_t stream)
+{
+    const int64_t c = st->c, k = st->k, nb = st->nb;
+    if (c <= kMaxC) {
+        HIP_TRY(launch_leaf_gram(st->view(), st->n2, st->tree, st->n2, stream));
+    } else {
+        DevBuf rows, desc;
+        std::vector<Chunk> leaf(nb);
+        for (int64_t i = 0; i < nb; ++i) {
+            std::memset(&leaf[i], 0, sizeof(Chunk));
+            leaf[i].x_off = i * k * c;
+            leaf[i].rows = (int32_t)k;
+            leaf[i].prob = (int32_t)i;
+            leaf[i].slot = (int32_t)i;
+            leaf[i].kk = (int32_t)k;
+        }
+        zs_status s = ZS_OK;
+        hipError_t e = rows.ensure(sizeof(double) * (size_t)nb * k * c);
+        if (e == hipSuccess) e = desc.ensure(sizeof(Chunk) * (size_t)nb);
+        if (e == hipSuccess)
+            e = hipMemcpy(desc.p, leaf.data(), sizeof(Chunk) * (size_t)nb, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_scale_rows(st->view(), nb, rows.as<double>(), stream);
+        double *leaves = st->tree + st->n2 * c * c;
+        if (e == hipSuccess)
+            e = launch_gram(rows.as<double>(), kElemF64, c, (int)c, desc.as<Chunk>(), (int)nb, leaves,
+                            stream);
+        if (e == hipSuccess) e = launch_zero(leaves + nb * c * c, (st->n2 - nb) * c * c, stream);
+        const hipError_t e2 = hipStreamSynchronize(stream);
+        if (e == hipSuccess) e = e2;
+        rows.release();
+        desc.release();
+        if (e != hipSuccess)
+            s = fail(e == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "Gram tree: %s",
+                     hipGetErrorString(e));
+        if (s != ZS_OK) return s;
+    }
+    for (int64_t lev = st->n2 / 2; lev >= 1; lev /= 2)
+        HIP_TRY(launch_tree_level((int)c, st->tree, lev, lev, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return ZS_OK;
+}
+
+zs_status zs_store_append(zs_store *st, const void *R, int64_t m, int64_t ldr, zs_dtype r_type,
+                          hipStream_t stream)
+{
+    if (!st) return fail(ZS_EINVAL, "store is null");
+    if (!R) return fail(ZS_EINVAL, "R is null");
+    if (m < 1) return fail(ZS_EINVAL, "m = %lld < 1", (long long)m);
+    if (ldr < st->c) return fail(ZS_EINVAL, "ldr = %lld < c = %lld", (long long)ldr, (long long)st->c);
+    if (r_type != ZS_F64 && r_type != ZS_F32 && r_type != ZS_BF16)
+        return fail(ZS_EINVAL, "r_type %d is not a zs_dtype", (int)r_type);
+    const int64_t t0 = st->t, b = st->b, c = st->c, k = st->k, nb0 = st->nb;
+    const int64_t r_tail = t0 - (nb0 - 1) * b;              // rows of the last block
+    const int64_t m1 = r_tail < b ? std::min(m, b - r_tail) : 0;   // rows that fill it
+    const int64_t m2 = m - m1;                              // rows of new blocks
+    const int64_t t1 = t0 + m, nb1 = (t1 + b - 1) / b;
+    int64_t n2 = 1;
+    while (n2 < nb1) n2 *= 2;
+    const int rt = r_type == ZS_F32 ? kElemF32 : r_type == ZS_BF16 ? kElemBF16 : kElemF64;
+    const size_t es = st->esize(), rs = r_type == ZS_F64 ? 8 : r_type == ZS_F32 ? 4 : 2;
+    zs_store *tp = nullptr, *np = nullptr;
+    DevBuf P;
+    void *base = nullptr;
+    auto cleanup = [&](zs_status s) {
+        (void)hipStreamSynchronize(stream);
+        if (base) (void)hipFree(base);
+        zs_store_free(tp);
+        zs_store_free(np);
+        P.release();
+        return s;
+    };
+    bool noconv = false;
+    // the last block: [Sigma V^T; R[0:m1]] = U' Sigma' V'^T by the storage phase
+    if (m1 > 0) {
+        hipError_t e = P.ensure(sizeof(double) * (size_t)(k + m1) * c);
+        if (e == hipSuccess) e = launch_tail_rows(st->view(), nb0 - 1, R, rt, ldr, m1, P.as<double>(), stream);
+        if (e != hipSuccess)
+            return cleanup(fail(e == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "append: %s",
+                                hipGetErrorString(e)));
+        zs_status s = zs_store_blocks_xi(P.p, k + m1, c, c, ZS_F64, k + m1, (int32_t)k, st->mode,
+                                         st->xi, stream, &tp);
+        if (s == ZS_ENOCONV && tp) noconv = true;
+        else if (s != ZS_OK) return cleanup(s);
+    }
+    // whole new blocks from the remaining rows
+    if (m2 > 0) {
+        zs_status s = zs_store_blocks_xi(static_cast<const char *>(R) + m1 * ldr * (int64_t)rs, m2, c,
+                                         ldr, r_type, b, (int32_t)k, st->mode, st->xi, stream, &np);
+        if (s == ZS_ENOCONV && np) noconv = true;
+        else if (s != ZS_OK) return cleanup(s);
+    }
+    // the grown arrays, in the layout of zs_store_blocks
+    const size_t sz[6] = {es * t1 * k, es * nb1 * k * c, sizeof(double) * nb1 * k,
+                          sizeof(int32_t) * nb1, sizeof(double) * 2 * n2 * c * c, sizeof(int)};
+    size_t off[6], total = 0;
+    for (int i = 0; i < 6; ++i) {
+        off[i] = total;
+        total = align_up(total + sz[i], 256);
+    }
+#define AP_TRY(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return cleanup(fail(e_ == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "%s: %s", \
+                                #expr, hipGetErrorString(e_)));                             \
+    } while (0)
+    AP_TRY(hipMalloc(&base, total));
+    char *p = static_cast<char *>(base);
+    char *U1 = p + off[0], *Vt1 = p + off[1];
+    double *S1 = reinterpret_cast<double *>(p + off[2]);
+    int32_t *K1 = reinterpret_cast<int32_t *>(p + off[3]);
+    double *tree1 = reinterpret_cast<double *>(p + off[4]);
+    int *conv1 = reinterpret_cast<int *>(p + off[5]);
+    const char *U0 = static_cast<const char *>(st->U), *Vt0 = static_cast<const char *>(st->Vt);
+    const int64_t bkeep = m1 > 0 ? nb0 - 1 : nb0;          // blocks copied unchanged
+    const int64_t rkeep = m1 > 0 ? bkeep * b : t0;          // rows copied unchanged
+    const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;
+    AP_TRY(hipMemcpyAsync(U1, U0, es * rkeep * k, d2d, stream));
+    AP_TRY(hipMemcpyAsync(Vt1, Vt0, es * bkeep * k * c, d2d, stream));
+    AP_TRY(hipMemcpyAsync(S1, st->S, sizeof(double) * bkeep * k, d2d, stream));
+    AP_TRY(hipMemcpyAsync(K1, st->kvec, sizeof(int32_t) * bkeep, d2d, stream));
+    if (m1 > 0) {
+        AP_TRY(launch_tail_u(U0 + es * rkeep * k, r_tail, tp->U, m1, (int)k, st->f32, U1 + es * rkeep * k,
+                             stream));
+        AP_TRY(hipMemcpyAsync(Vt1 + es * bkeep * k * c, tp->Vt, es * k * c, d2d, stream));
+        AP_TRY(hipMemcpyAsync(S1 + bkeep * k, tp->S, sizeof(double) * k, d2d, stream));
+        AP_TRY(hipMemcpyAsync(K1 + bkeep, tp->kvec, sizeof(int32_t), d2d, stream));
+    }
+    if (m2 > 0) {
+        const int64_t b0 = (t0 + m1) / b;                   // first new block
+        AP_TRY(hipMemcpyAsync(U1 + es * (t0 + m1) * k, np->U, es * m2 * k, d2d, stream));
+        AP_TRY(hipMemcpyAsync(Vt1 + es * b0 * k * c, np->Vt, es * np->nb * k * c, d2d, stream));
+        AP_TRY(hipMemcpyAsync(S1 + b0 * k, np->S, sizeof(double) * np->nb * k, d2d, stream));
+        AP_TRY(hipMemcpyAsync(K1 + b0, np->kvec, sizeof(int32_t) * np->nb, d2d, stream));
+    }
+    AP_TRY(hipMemsetAsync(conv1, 0, sizeof(int), stream));
+    AP_TRY(hipStreamSynchronize(stream));
+#undef AP_TRY
+    // swap in the grown arrays
+    void *old = st->base;
+    st->base = base;
+    base = nullptr;
+    st->U = U1;
+    st->Vt = Vt1;
+    st->S = S1;
+    st->kvec = K1;
+    st->tree = tree1;
+    st->conv = conv1;
+    st->t = t1;
+    st->nb = nb1;
+    st->n2 = n2;
+    (void)hipFree(old);
+    zs_status s = build_tree(st, stream);
+    cleanup(ZS_OK);
+    if (s != ZS_OK) return s;
+    return noconv ? fail(ZS_ENOCONV, "an appended block's eigen-solve hit the sweep cap") : ZS_OK;
+}
+
 zs_status zs_window_similarity(const zs_store *cst, int64_t t_s, int64_t t_e, int64_t stride,
                                int32_t n_windows, double *sim, hipStream_t stream)
 {

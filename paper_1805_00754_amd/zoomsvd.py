@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "ZS_OK", -1: "ZS_EINVAL", -2: "ZS_ERANGE", -3: "ZS_ENOMEM", -
                 -5: "ZS_EDEVICE", -6: "ZS_EUNSUPPORTED"}
 
 # Symbols the header declares (the CPU test checks the library exports all).
-EXPORTED = ["zs_store_blocks", "zs_store_blocks_xi", "zs_window_similarity", "zs_query", "zs_query_batch", "zs_query_batch_graph",
+EXPORTED = ["zs_store_blocks", "zs_store_blocks_xi", "zs_store_append", "zs_window_similarity",
+            "zs_query", "zs_query_batch", "zs_query_batch_graph",
             "zs_batch_graph_launch", "zs_batch_graph_free", "zs_store_free", "zs_store_bytes",
             "zs_store_info", "zs_store_get_block", "zs_sync_status", "zs_last_error", "zs_version",
             "zs_timing_enable", "zs_timing_reset", "zs_timing_get"]
@@ -65,6 +66,7 @@ def load(path: str | None = None):
                                            ctypes.c_int, ctypes.c_double, _vp, ctypes.POINTER(_vp)]
         lib.zs_query.argtypes = [_vp, _i64, _i64, _i32, _vp, _i64, _vp, _vp, _i64, _vp, _vp]
         lib.zs_window_similarity.argtypes = [_vp, _i64, _i64, _i64, _i32, _vp, _vp]
+        lib.zs_store_append.argtypes = [_vp, _vp, _i64, _i64, ctypes.c_int, _vp]
         lib.zs_query_batch.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                        _vp, _vp]
         lib.zs_query_batch_graph.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -85,7 +87,8 @@ def load(path: str | None = None):
         lib.zs_timing_enable.restype = None
         lib.zs_timing_reset.restype = None
         lib.zs_timing_get.argtypes = [ctypes.c_char_p, _vp, _vp]
-        for name in ("zs_store_blocks", "zs_store_blocks_xi", "zs_window_similarity", "zs_query", "zs_query_batch", "zs_store_info",
+        for name in ("zs_store_blocks", "zs_store_blocks_xi", "zs_store_append",
+                     "zs_window_similarity", "zs_query", "zs_query_batch", "zs_store_info",
                      "zs_store_get_block", "zs_sync_status", "zs_timing_get",
                      "zs_query_batch_graph", "zs_batch_graph_launch"):
             getattr(lib, name).restype = ctypes.c_int
@@ -167,6 +170,22 @@ def zs_store_blocks(A: torch.Tensor, b: int, k: int, mode: int = ZS_MODE_FP64, s
         load().zs_store_free(h)
     _check(st)
     return Store(h.value, t, c, b, k, mode, float(xi))
+
+
+def zs_store_append(st: Store, R: torch.Tensor, stream=None) -> Store:
+    """Streaming ingest: append the rows of R (m x c, on the GPU) to the store
+    (its last block by the incremental update, then new blocks).  Updates
+    st.t and st.nb; returns st."""
+    if R.dim() != 2 or R.stride(1) != 1 or not R.is_cuda or R.shape[1] != st.c:
+        raise ValueError("R must be a 2-D CUDA/HIP tensor of c columns with unit column stride")
+    r_type = {torch.float64: ZS_F64, torch.float32: ZS_F32, torch.bfloat16: ZS_BF16}[R.dtype]
+    s = load().zs_store_append(_vp(st.handle), _vp(_ptr(R)), R.shape[0], R.stride(0), r_type,
+                               _vp(_stream(stream)))
+    if s in (ZS_OK, ZS_ENOCONV):
+        st.t += R.shape[0]
+        st.nb = (st.t + st.b - 1) // st.b
+    _check(s)
+    return st
 
 
 def zs_query(st: Store, t_s: int, t_e: int, k_q: int, U=None, S=None, V=None, k_out=None,
