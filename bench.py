@@ -178,6 +178,26 @@ def main():
                    "most_similar_offsets_rows": [int(x) * stride for x in top]}
         log("window similarity: %d windows in %.2f ms" % (nw, windows["ms"]))
 
+    # Streaming ingest: ten appends of 1,000 rows each (one block's worth, cut
+    # across block boundaries) to a copy of the benchmark store.
+    ingest = None
+    if wl == WORKLOAD:
+        extra = synth.sinusoid_mixture(11_000, c, sources=16, seed=synth.SEED_BASE + 11,
+                                       noise="ar1", noise_sigma=0.05).A
+        R = torch.from_numpy(extra).to(dev)
+        sa = zs.zs_store_blocks(A[:t - 500], b, k, mode=mode)     # last block half full
+        zs.zs_store_append(sa, R[:1_000])                          # warm-up
+        torch.cuda.synchronize()
+        ams = []
+        for j in range(1, 11):
+            a0 = time.perf_counter()
+            zs.zs_store_append(sa, R[j * 1_000:(j + 1) * 1_000])
+            ams.append((time.perf_counter() - a0) * 1e3)
+        sa.free()
+        ingest = {"rows_per_append": 1_000, "appends": 10, "ms_per_append": float(np.median(ams)),
+                  "rows_per_s": 1_000 / (float(np.median(ams)) / 1e3), "store_rows": t - 500}
+        log("ingest: %.2f ms per 1,000-row append" % ingest["ms_per_append"])
+
     # Write ceiling of this very output allocation: a plain fill of the batch's
     # U buffer.  Sustained write bandwidth into a large allocation depends on
     # where it landed in physical memory (5.5 to 6.9 TB/s seen for the same
@@ -336,6 +356,7 @@ def main():
         "kernel_rooflines": kernel_roofs,
         "serving": serving,
         "windows": windows,
+        "ingest": ingest,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
