@@ -11,7 +11,7 @@
 //    rule folded in), giving the block's left singular vectors.
 //
 // project and stack_project share one tile body (one wave per chunk, tiles of
-// 64 rows), described at tile_project.
+// 32 or 64 rows), described at tile_project.
 #include "zs_internal.h"
 
 namespace zs {
@@ -25,11 +25,12 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// tile_project: one wave per chunk, tiles of 64 rows.  Row r of a tile is
-// s_r x_r for a row x_r in HBM and a scale s_r (the caller's row function
-// gives both, and the row's element type).  The tile product X V_k runs on
-// the matrix cores (FP64 MFMA 16x16x4) over 16-column panels, four row blocks
-// times ceil(kq / 16) column blocks; each lane loads its A fragments (four
+// tile_project: one wave per chunk, tiles of 16 RBN rows (RBN = 2 row blocks
+// for 16 < kq <= 32, which keeps two waves per SIMD without spills; 4 else).
+// Row r of a tile is s_r x_r for a row x_r in HBM and a scale s_r (the
+// caller's row function gives both, and the row's element type).  The tile
+// product X V_k runs on the matrix cores (FP64 MFMA 16x16x4) over 16-column
+// panels, RBN row blocks times ceil(kq / 16) column blocks; each lane loads its A fragments (four
 // consecutive columns of one row each) straight from HBM one panel ahead of
 // the matrix-core work, and the B fragments of V_k from cache.  Operand layout: A(i, s)
 // in lane i + 16 s, B(s, j) in lane j + 16 s, D(i, j) in register i / 4 of
@@ -89,6 +90,8 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
                                              double *__restrict__ G, RowRef fallback, double *sm)
 {
     constexpr int NCB = (KQM + 15) / 16;           // 16-column blocks of Y
+    constexpr int RBN = (KQM > 16 && KQM <= 32) ? 2 : 4;   // 16-row blocks per tile
+    constexpr int TR = 16 * RBN;                   // rows per tile
     const int lane = threadIdx.x;
     const int ldy = kq + 1;
     v4d gacc[NCB][NCB];
@@ -97,25 +100,25 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
 #pragma unroll
         for (int cj = 0; cj < NCB; ++cj) gacc[ci][cj] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-    for (int r0 = 0; r0 < rows; r0 += 64) {
-        const int nr = min(64, rows - r0);
+    for (int r0 = 0; r0 < rows; r0 += TR) {
+        const int nr = min(TR, rows - r0);
         // lanes past the tile read the fallback row with scale 0
         const RowRef rr = lane < nr ? row(r0 + lane) : fallback;
         const double scale = lane < nr ? rr.scale : 0.0;
-        v4d acc[4][NCB];
+        v4d acc[RBN][NCB];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = (v4d){0.0, 0.0, 0.0, 0.0};
         // A fragment (rb, t) of a panel is X(16 rb + i, a0 + 4 t + s) in lane
         // i + 16 s: the lane reads row 16 rb + lane % 16 itself, whose start
         // and type it takes from the row's owner lane once per tile.
-        const char *rp[4];
-        int rt[4];
+        const char *rp[RBN];
+        int rt[RBN];
         {
             const uint64_t pa = reinterpret_cast<uint64_t>(rr.p);
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
+            for (int rb = 0; rb < RBN; ++rb) {
                 const int owner = 16 * rb + lane % 16;
                 const uint32_t lo = __shfl((uint32_t)pa, owner, 64);
                 const uint32_t hi = __shfl((uint32_t)(pa >> 32), owner, 64);
@@ -139,10 +142,10 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
         // (one order for every element type: FP32 or BF16 input widened to
         // FP64 gives the same sums, bit for bit, as the widened input itself)
         auto kcol = [&](int t) { return 4 * sc4 + t; };
-        auto load_a = [&](auto clamp, int a0, double (&af)[4][4]) {
+        auto load_a = [&](auto clamp, int a0, double (&af)[RBN][4]) {
             if constexpr (!decltype(clamp)::value && TYPE != kMixed) {
 #pragma unroll
-                for (int rb = 0; rb < 4; ++rb) {
+                for (int rb = 0; rb < RBN; ++rb) {
                     const uintptr_t ra = reinterpret_cast<uintptr_t>(rp[rb]);
                     if constexpr (TYPE == kElemF64) {
                         const gdouble2 *q = reinterpret_cast<const gdouble2 *>(ra + 8 * (a0 + 4 * sc4));
@@ -171,7 +174,7 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
                     const int col = a0 + kcol(t);
                     const int colc = decltype(clamp)::value ? min(col, c - 1) : col;
 #pragma unroll
-                    for (int rb = 0; rb < 4; ++rb) af[rb][t] = typed_elem<TYPE>(rp[rb], rt[rb], colc);
+                    for (int rb = 0; rb < RBN; ++rb) af[rb][t] = typed_elem<TYPE>(rp[rb], rt[rb], colc);
                 }
             }
         };
@@ -185,7 +188,7 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
         // the products of one panel: its B fragments are loaded here (from
         // cache), after the loads already in flight, and their rows past c and
         // columns past kq are zeroed by an exact multiply
-        auto panel = [&](int a0, const double (&af)[4][4]) {
+        auto panel = [&](int a0, const double (&af)[RBN][4]) {
             double bf[NCB][4];
             load_b(a0, bf);
             if constexpr (KQM <= 32) __builtin_amdgcn_sched_barrier(0);
@@ -195,7 +198,7 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
                 for (int t = 0; t < 4; ++t)
                     bf[cb][t] *= (a0 + kcol(t) < c && 16 * cb + lane % 16 < kq) ? 1.0 : 0.0;
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
+            for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -207,7 +210,7 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
                 // two sets of A registers in turn: the next panel's A loads are
                 // in flight during this panel's products, and no register copy
                 // between the sets waits for them
-                double a1[4][4], a2[4][4];
+                double a1[RBN][4], a2[RBN][4];
                 load_a(clamp, 0, a1);
                 for (int a0 = 0; a0 < c; a0 += 2 * kPanel) {
                     // past c: a clamped panel that is not used, or none
@@ -222,7 +225,7 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
             } else {
                 // wider tiles have no registers to spare for a second set
                 for (int a0 = 0; a0 < c; a0 += kPanel) {
-                    double af[4][4];
+                    double af[RBN][4];
                     load_a(clamp, a0, af);
                     panel(a0, af);
                 }
@@ -235,7 +238,7 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
         // scale the rows: D(i, j) of a 16 x 16 block sits in register i / 4 of
         // lane j + 16 (i mod 4)
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const double sc = __shfl(scale, 16 * rb + 4 * v + lane / 16, 64);
@@ -244,7 +247,7 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
             }
         // Gram of the tile on the matrix cores
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -255,7 +258,7 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
                                                                             gacc[ci][cj], 0, 0, 0);
         wave_sync();
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int rw = 16 * rb + 4 * v + lane / 16;
@@ -322,7 +325,7 @@ __device__ __forceinline__ void stack_project_body(StoreView st, const Piece *__
 
 // project (storage phase): rows of A of the chunk, scale 1.
 template <int KQM, typename TA>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KQM <= 16 ? 2 : 1)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KQM <= 32 ? 2 : 1)))
 void project_kernel(const TA *__restrict__ X, int64_t ld, int c, const Chunk *__restrict__ chunks,
                     const double *__restrict__ Vk, double *__restrict__ Y, double *__restrict__ GYpart)
 {
@@ -341,7 +344,7 @@ void project_kernel(const TA *__restrict__ X, int64_t ld, int c, const Chunk *__
 // Up to 32 columns the kernel fits two waves per SIMD in registers; wider
 // tiles keep the compiler's choice (more registers, no spills).
 template <int KQM>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KQM <= 16 ? 2 : 1))) void stack_project_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KQM <= 32 ? 2 : 1))) void stack_project_kernel(
     StoreView st, const Piece *__restrict__ pieces, const double *__restrict__ Mp,
     const StackChunk *__restrict__ chunks, const double *__restrict__ Vk, double *__restrict__ Y,
     double *__restrict__ GYpart)
