@@ -56,16 +56,4 @@ __device__ __forceinline__ double wave_sum64(double v)
     return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
-// a / b from the hardware reciprocal refined by two Newton steps (about one
-// ulp): for loop-carried recurrences whose latency the full division sequence
-// would dominate.  Divisors below the normal range take the IEEE division.
-__device__ __forceinline__ double div_nr(double a, double b)
-{
-    if (!(fabs(b) >= __DBL_MIN__)) return a / b;
-    double r = __builtin_amdgcn_rcp(b);
-    r = fma(r, fma(-b, r, 1.0), r);
-    r = fma(r, fma(-b, r, 1.0), r);
-    return a * r;
-}
-
 }  // namespace zs

@@ -471,7 +471,6 @@ zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
                              stream, w, false, pl);
     if (s != ZS_OK) return s;
     return query_launch(st, pl, w, stream);
-    return ZS_OK;
 }
 
 zs_status check_query(const zs_store *st, int64_t ts, int64_t te, int32_t kq)
@@ -734,17 +733,8 @@ zs_status zs_query_batch(const zs_store *cst, int32_t nq, const int64_t *t_s, co
                          const int64_t *s_off, void *V, const int64_t *v_off, int32_t *k_out,
                          hipStream_t stream)
 {
-    if (!cst) return fail(ZS_EINVAL, "store is null");
-    if (nq < 1) return fail(ZS_EINVAL, "nq = %d < 1", nq);
-    if (!t_s || !t_e || !k_q || !u_off || !s_off || !v_off)
-        return fail(ZS_EINVAL, "null host array");
-    if (!U || !S || !V || !k_out) return fail(ZS_EINVAL, "null output pointer");
-    for (int32_t q = 0; q < nq; ++q) {
-        zs_status s = check_query(cst, t_s[q], t_e[q], k_q[q]);
-        if (s != ZS_OK) return s;
-        if (u_off[q] < 0 || s_off[q] < 0 || v_off[q] < 0)
-            return fail(ZS_EINVAL, "negative output offset for query %d", q);
-    }
+    zs_status s = check_batch(cst, nq, t_s, t_e, k_q, U, u_off, S, s_off, V, v_off, k_out);
+    if (s != ZS_OK) return s;
     std::vector<int64_t> ld(nq);
     for (int32_t q = 0; q < nq; ++q) ld[q] = k_q[q];
     zs_store *st = const_cast<zs_store *>(cst);
