@@ -1,5 +1,7 @@
 // Leading eigenvectors of a symmetric positive semi-definite c x c Gram matrix
-// by tridiagonalisation, one work-group per matrix, in LDS (c <= 128).
+// by tridiagonalisation, one work-group per matrix (c <= 128).  A work-group
+// keeps under half of a CU's LDS and registers, so two matrices share a CU and
+// each one's barrier and latency stalls are filled by the other's work.
 //
 // First stage of every rank-k SVD of the method (the block SVDs of the
 // storage phase and the SVD of each query's stacked matrix).  Only the span of
@@ -8,14 +10,16 @@
 //
 //   1. G <- the problem's Gram terms (fixed order), as in the Jacobi variant.
 //   2. Householder tridiagonalisation Q^T G Q = T (Golub & Van Loan 8.3.1),
-//      each reflector vector packed into matrix rows the reduction is done with.
+//      the reflector vectors packed one after another.
 //   3. The kk largest eigenvalues of T by multisection on Sturm counts
 //      (groups of up to 64 threads per eigenvalue).
 //   4. Eigenvectors of T by inverse iteration (tridiagonal LU with partial
 //      pivoting, two solves, one thread per cluster of eigenvalues closer
 //      than 1e-9 ||T||, Gram-Schmidt inside a cluster: the approach of
 //      LAPACK's stein).
-//   5. Back-transformation x = Q z, then two passes of classical Gram-Schmidt
+//   5. Back-transformation x = Q z (the reflectors are parked in the
+//      problem's own output slot, which is large enough for them while
+//      c <= 2 kMaxK + 1), then two passes of classical Gram-Schmidt
 //      over the kk vectors (a vector that collapses is replaced by the next
 //      unit vector, which can only happen inside a degenerate eigenspace).
 // The total work is O(c^3) with a small constant, against O(50 c^3) for
@@ -26,8 +30,11 @@
 namespace zs {
 namespace {
 
-constexpr int NTH = 1024;                 // threads of the eigen-solver work-group
+constexpr int NTH = 512;                  // threads of the eigen-solver work-group
 constexpr int kWaves = NTH / 64;
+// Dynamic LDS of one work-group, at most: two fit a CU's 160 KiB together
+// with their static LDS.
+constexpr int kLdsBudget = 10112;          // doubles
 
 // Deterministic start vector in (-1, 1) for inverse iteration.
 __device__ __forceinline__ double start_value(int i, int g, int attempt)
@@ -42,33 +49,39 @@ __device__ __forceinline__ double start_value(int i, int g, int attempt)
 }
 
 // LDS layout of the solver (doubles): d, e, e2, tau (NMAX each), lam (kMaxK),
-// then one region of REGION doubles.  The matrix itself never enters LDS: each
-// thread keeps its elements in registers during the tridiagonal reduction.
-// The region holds, in order: the packed Householder vectors (HPMAX), then a
-// scratch area that the reduction and the multisection use and that later
-// holds the eigenvector block Z (c x kk) and the inverse-iteration arrays.
+// then one region of `region` doubles.  The matrix itself never enters LDS:
+// each thread keeps its elements in registers during the tridiagonal
+// reduction, and the Householder vectors go to global memory.  The region is
+// first the reduction's scratch (wave partials of A v, two v buffers, p, wave
+// dot partials) and the staging of Partial-SVD rows, then the eigenvector block
+// Z (c x kk) followed by the inverse-iteration arrays (two length-c arrays per
+// solver lane).
 template <int NMAX>
 struct TriLayout {
-    static constexpr int HPMAX = (NMAX - 1) * NMAX / 2;             // packed vectors
-    static constexpr int KZ = NMAX < kMaxK ? NMAX : kMaxK;           // largest kk
-    static constexpr int NEED = HPMAX + NMAX * KZ + 3 * NMAX * 8;     // >= 8 solver lanes
-    // reduction: wave partials (16 NMAX), two v buffers, p, wave dot partials;
-    // multisection: NTH points and NTH counts
-    static constexpr int SCR_TRI = 16 * NMAX + 3 * NMAX + 16;
-    static constexpr int SCR_MS = NTH + NTH / 2;
-    static constexpr int SCR = SCR_TRI > SCR_MS ? SCR_TRI : SCR_MS;
-    static constexpr int R0 = HPMAX + SCR;
-    static constexpr int REGION = R0 > NEED ? R0 : NEED;
-    static constexpr size_t bytes() { return (size_t)(4 * NMAX + kMaxK + REGION) * sizeof(double); }
+    static constexpr int FIXED = 4 * NMAX + kMaxK;
+    static constexpr int SCR = kWaves * NMAX + 3 * NMAX + kWaves;
+    static_assert(SCR >= 8 * NMAX, "row staging of step 1 must fit the scratch");
+    static_assert(NMAX <= 128, "two 64-bit words of pivot swaps per solver lane");
+    static_assert((NMAX - 1) * NMAX / 2 <= NMAX * kMaxK, "reflectors fit the output slot");
+    // region for c and a largest kk of k: all of Z, and as many solver lanes
+    // (up to one per eigenvalue) as the budget leaves room for, at least one
+    static int region(int c, int k)
+    {
+        const int room = kLdsBudget - FIXED - c * k;
+        int nt = room / (2 * c);
+        nt = nt < 1 ? 1 : (nt > k ? k : nt);
+        const int need = c * k + 2 * c * nt;
+        return need > SCR ? need : SCR;
+    }
+    static size_t bytes(int region) { return (size_t)(FIXED + region) * sizeof(double); }
 };
 
 template <int NMAX>
-__global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *__restrict__ probs,
-                                                      const double *const *__restrict__ gsrc,
-                                                      const double *const *__restrict__ msrc,
-                                                      double *__restrict__ Vk)
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4)))
+void eig_tri_kernel(int c, int k, int region, const Prob *__restrict__ probs,
+                    const double *const *__restrict__ gsrc, const double *const *__restrict__ msrc,
+                    double *__restrict__ Vk)
 {
-    using L = TriLayout<NMAX>;
     constexpr int RPW = NMAX / kWaves;             // matrix rows per wave
     constexpr int CPL = (NMAX + 63) / 64;          // matrix columns per lane
     constexpr int MR = 8;                          // rows of a Partial-SVD term staged at once
@@ -78,8 +91,7 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
     double *e2 = e + NMAX;
     double *tau = e2 + NMAX;
     double *lam = tau + NMAX;                      // kMaxK
-    double *A = lam + kMaxK;                       // region: packed vectors first
-    double *scr = A + L::HPMAX;                    // scratch (phases 1-3), later Z
+    double *scr = lam + kMaxK;                     // region: scratch (phases 1-3), later Z
     __shared__ double sh_a, sh_b, sh_tnorm, sh_pivmin;
     __shared__ int cl_start[kMaxK + 1];
     __shared__ int sh_ncl;
@@ -88,11 +100,14 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
     const int kk = P.kk;
-    double *out = Vk + (int64_t)blockIdx.x * c * kMaxK;   // c x kk, row-major
+    // c x kk, row-major; before that the packed Householder vectors, of
+    // (c - 1) c / 2 <= c kMaxK doubles
+    double *out = Vk + (int64_t)blockIdx.x * c * kMaxK;
+    double *hv = out;
     // packed Householder vector j starts at hoff(j); its entry 0 is 1
     auto hoff = [c](int j) { return j * (c - 1) - j * (j - 1) / 2; };
 
-    // Matrix element (R, C), R = wave + 16 m, C = lane + 64 s, lives in a[m][s]
+    // Matrix element (R, C), R = wave + kWaves m, C = lane + 64 s, lives in a[m][s]
     // of this thread; elements outside c x c are zero.
     double a[RPW][CPL];
 
@@ -139,10 +154,10 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
     // next reflector from its registers while the other waves go on, so each
     // step has three barriers.  Reflectors are kept in absolute indexing (zero
     // outside (j, c)) in two alternating buffers.
-    double *part = scr;                            // 16 x NMAX wave partials of A v
+    double *part = scr;                            // kWaves x NMAX wave partials of A v
     double *vbuf = part + kWaves * NMAX;           // 2 x NMAX
     double *psh = vbuf + 2 * NMAX;                 // NMAX
-    double *kpart = psh + NMAX;                    // 16
+    double *kpart = psh + NMAX;                    // kWaves
     // Called by the wave that holds row jj once that row is final: x[s] is its
     // element (jj, lane + 64 s).  Sets d_jj and, below the last two rows, the
     // reflector of row jj (tau, e and the vector, also packed for later).
@@ -179,7 +194,7 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
                 if (C >= NMAX) continue;
                 const double v = C == jj + 1 ? 1.0 : (C > jj + 1 && C < c ? x[s] * scal : 0.0);
                 vn[C] = v;
-                if (C > jj && C < c) A[hoff(jj) + C - jj - 1] = v;
+                if (C > jj && C < c) hv[hoff(jj) + C - jj - 1] = v;
             }
             if (lane == 0) {
                 tau[jj] = t;
@@ -217,9 +232,9 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
         const double t = tau[j];
         // v is zero outside (j, c), so rows and columns outside the live block
         // contribute nothing and need no tests.
-        double vr[RPW], vcl[CPL];
-#pragma unroll
-        for (int m = 0; m < RPW; ++m) vr[m] = vc[wave + kWaves * m];
+        // (the row entries of v and w are read from LDS where they are used,
+        // which keeps the registers for the matrix)
+        double vcl[CPL];
 #pragma unroll
         for (int s = 0; s < CPL; ++s) vcl[s] = vc[min(lane + 64 * s, NMAX - 1)];
         // partial A v over this wave's rows (A symmetric: column sums = row sums)
@@ -228,9 +243,11 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
 #pragma unroll
         for (int s = 0; s < CPL; ++s) pp[s] = 0.0;
 #pragma unroll
-        for (int m = 0; m < RPW; ++m)
+        for (int m = 0; m < RPW; ++m) {
+            const double vr = vc[wave + kWaves * m];
 #pragma unroll
-            for (int s = 0; s < CPL; ++s) pp[s] = fma(a[m][s], vr[m], pp[s]);
+            for (int s = 0; s < CPL; ++s) pp[s] = fma(a[m][s], vr, pp[s]);
+        }
         double vav = 0.0;
 #pragma unroll
         for (int s = 0; s < CPL; ++s) {
@@ -240,7 +257,7 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
         vav = wave_sum64(vav);
         if (lane == 0) kpart[wave] = vav;
         __syncthreads();
-        // p = tau A v (pairwise sum of the 16 wave partials)
+        // p = tau A v (pairwise sum of the wave partials)
         if (tid < c) {
             double h[kWaves];
 #pragma unroll
@@ -261,13 +278,7 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
         const double K = 0.5 * t * t * kv[0];      // (tau/2) p.v with p.v = tau v^T A v
         __syncthreads();
         // A <- A - v w^T - w v^T, w = p - K v (zero outside the live block)
-        double wr[RPW], wcol[CPL];
-#pragma unroll
-        for (int m = 0; m < RPW; ++m) {
-            const int R = wave + kWaves * m;
-            const double pr = psh[R];
-            wr[m] = (R > j && R < c) ? pr - K * vr[m] : 0.0;
-        }
+        double wcol[CPL];
 #pragma unroll
         for (int s = 0; s < CPL; ++s) {
             const int C = lane + 64 * s;
@@ -275,12 +286,16 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
             wcol[s] = (C > j && C < c) ? pc - K * vcl[s] : 0.0;
         }
 #pragma unroll
-        for (int m = 0; m < RPW; ++m)
+        for (int m = 0; m < RPW; ++m) {
+            const int R = wave + kWaves * m;
+            const double vr = vc[R], pr = psh[R];   // unconditional reads: a select, no branch
+            const double wr = (R > j && R < c) ? pr - K * vr : 0.0;
 #pragma unroll
             for (int s = 0; s < CPL; ++s) {
-                a[m][s] = fma(-vr[m], wcol[s], a[m][s]);
-                a[m][s] = fma(-wr[m], vcl[s], a[m][s]);
+                a[m][s] = fma(-vr, wcol[s], a[m][s]);
+                a[m][s] = fma(-wr, vcl[s], a[m][s]);
             }
+        }
         // row j+1 is final: its holder prepares step j+1
         if (wave == (j + 1) % kWaves) {
             double x[CPL];
@@ -386,23 +401,24 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
     __syncthreads();
 
     // ---- 4. inverse iteration: one lane of wave 0 per cluster, members in order ----
-    //      Z (c x kk) follows the packed vectors.  Each solver lane keeps the U
-    //      factor of T - lambda I (reciprocal diagonal and two superdiagonals) in
-    //      three length-c arrays after Z, interleaved by lane (element i at
-    //      i * NT + lane); the eliminated right-hand side overwrites z in place.
-    //      The recurrences load the next row of T and of z one step ahead, so
-    //      that LDS latency stays off the dependence chain.
-    const int hp = c >= 3 ? hoff(c - 2) : 0;        // packed length
-    double *Z = A + hp;
+    //      Z (c x kk) starts the region.  Each solver lane keeps the U factor of
+    //      T - lambda I in two length-c arrays after Z, interleaved by lane
+    //      (element i at i * NT + lane): the reciprocal diagonal and the first
+    //      superdiagonal.  The second superdiagonal is e(i+1) where row i was
+    //      swapped and zero elsewhere, so a bit per row in registers stands for
+    //      it.  The eliminated right-hand side overwrites z in place.  The
+    //      recurrences load the next row of T and of z one step ahead, so that
+    //      LDS latency stays off the dependence chain.
+    double *Z = scr;
     if (wave == 0) {
         double *lu = Z + c * kk;
-        const int NT = min((int)((A + L::REGION - lu) / (3 * c)), 64);
+        const int NT = min((region - c * kk) / (2 * c), 64);
         const int ncl = sh_ncl;
         const double pivfloor = __DBL_EPSILON__ * tnorm;
         for (int cb = 0; cb < ncl; cb += NT) {
             const int cl = cb + lane;
             const bool act = lane < NT && cl < ncl;
-            double *u1 = lu + min(lane, NT - 1), *u2 = u1 + c * NT, *u3 = u2 + c * NT;
+            double *u1 = lu + min(lane, NT - 1), *u2 = u1 + c * NT;
             const int g0 = act ? cl_start[cl] : 0, g1 = act ? cl_start[cl + 1] : 0;
             // members of every lane's cluster in step (lanes with fewer idle)
             int gmax = g1 - g0;
@@ -422,6 +438,7 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
                         double p0 = d[0] - lmb, p1 = c > 1 ? e[0] : 0.0, r = z[0];
                         double svn = e[0], ddn = d[min(1, c - 1)], een = e[min(1, c - 1)];
                         double znn = z[min(1, c - 1) * kk];
+                        uint64_t swl = 0, swh = 0;   // rows 0-63 and 64-127 swapped
                         for (int i = 0; i + 1 < c; ++i) {
                             const double sv = svn, dd = ddn - lmb, ee = (i + 2 < c) ? een : 0.0;
                             const double zn = znn;
@@ -439,7 +456,9 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
                             const double mlt = (swap ? p0 : sv) * inv;
                             u1[i * NT] = inv;
                             u2[i * NT] = swap ? dd : p1;
-                            u3[i * NT] = swap ? ee : 0.0;
+                            const uint64_t bit = (uint64_t)swap << (i & 63);
+                            if (i < 64) swl |= bit;
+                            else swh |= bit;
                             z[i * kk] = swap ? zn : r;
                             const double np0 = swap ? p1 - mlt * dd : dd - mlt * p1;
                             const double np1 = swap ? -mlt * ee : ee;
@@ -452,7 +471,9 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
                         z[(c - 1) * kk] = y1;
 #pragma unroll 4
                         for (int i = c - 2; i >= 0; --i) {
-                            const double y = (z[i * kk] - u2[i * NT] * y1 - u3[i * NT] * y2) * u1[i * NT];
+                            const bool sw = (((i < 64 ? swl : swh) >> (i & 63)) & 1) != 0;
+                            const double u3 = (sw && i + 2 < c) ? e[i + 1] : 0.0;
+                            const double y = (z[i * kk] - u2[i * NT] * y1 - u3 * y2) * u1[i * NT];
                             z[i * kk] = y;
                             y2 = y1;
                             y1 = y;
@@ -487,8 +508,11 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
     __syncthreads();
 
     // ---- 5. back-transformation x = H_0 H_1 ... H_{c-3} z, columns in registers ----
+    //      The reflectors are read from global memory (just written, so from
+    //      cache) kPre steps ahead of their use.
     {
         constexpr int CPW = kMaxK / kWaves;        // columns per wave, at most
+        constexpr int kPre = 4;
         double z0[CPW], z1[CPW];
         const int ncol = (kk - wave + kWaves - 1) / kWaves;
 #pragma unroll
@@ -497,14 +521,27 @@ __global__ __launch_bounds__(NTH) void eig_tri_kernel(int c, int k, const Prob *
             z0[u] = (u < ncol && lane < c) ? Z[lane * kk + g] : 0.0;
             z1[u] = (u < ncol && lane + 64 < c) ? Z[(lane + 64) * kk + g] : 0.0;
         }
+        // entries (lane, lane + 64) of reflector j, zero outside (j, c)
+        auto vload = [&](int j, double &v0, double &v1) {
+            const int i0 = lane - (j + 1), i1 = lane + 64 - (j + 1);
+            const double *vj = hv + hoff(max(j, 0));
+            v0 = (j >= 0 && i0 >= 0 && lane < c) ? vj[i0] : 0.0;
+            v1 = (j >= 0 && i1 >= 0 && lane + 64 < c) ? vj[i1] : 0.0;
+        };
         if (ncol > 0) {
+            double q0[kPre], q1[kPre];             // reflectors j, j-1, ..., j-kPre+1
+#pragma unroll
+            for (int p = 0; p < kPre; ++p) vload(c - 3 - p, q0[p], q1[p]);
             for (int j = c - 3; j >= 0; --j) {
                 const double t = tau[j];
+                const double v0 = q0[0], v1 = q1[0];
+#pragma unroll
+                for (int p = 0; p + 1 < kPre; ++p) {
+                    q0[p] = q0[p + 1];
+                    q1[p] = q1[p + 1];
+                }
+                vload(j - kPre, q0[kPre - 1], q1[kPre - 1]);
                 if (t == 0.0) continue;
-                const int i0 = lane - (j + 1), i1 = lane + 64 - (j + 1);   // index into v_j
-                const double *vj = A + hoff(j);
-                const double v0 = (i0 >= 0 && lane < c) ? vj[i0] : 0.0;
-                const double v1 = (i1 >= 0 && lane + 64 < c) ? vj[i1] : 0.0;
                 double sv[CPW];
 #pragma unroll
                 for (int u = 0; u < CPW; ++u) sv[u] = fma(v0, z0[u], v1 * z1[u]);
@@ -575,11 +612,13 @@ template <int NMAX>
 hipError_t run_eig_tri(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
                        const double *const *msrc, double *Vk, hipStream_t stream)
 {
-    const size_t lds = TriLayout<NMAX>::bytes();
+    // every problem's kk is at most k
+    const int region = TriLayout<NMAX>::region(c, k);
+    const size_t lds = TriLayout<NMAX>::bytes(region);
     static size_t cur = 0;
     hipError_t e = ensure_lds((const void *)eig_tri_kernel<NMAX>, lds, cur);
     if (e != hipSuccess) return e;
-    eig_tri_kernel<NMAX><<<nprob, NTH, lds, stream>>>(c, k, probs, gsrc, msrc, Vk);
+    eig_tri_kernel<NMAX><<<nprob, NTH, lds, stream>>>(c, k, region, probs, gsrc, msrc, Vk);
     return hipGetLastError();
 }
 
