@@ -1,7 +1,10 @@
 // Leading eigenvectors of a symmetric positive semi-definite c x c Gram matrix
-// by tridiagonalisation, one work-group per matrix (c <= 128).  A work-group
-// keeps under half of a CU's LDS and registers, so two matrices share a CU and
-// each one's barrier and latency stalls are filled by the other's work.
+// by tridiagonalisation, one work-group per matrix (c <= 128).  With more
+// matrices than CUs a work-group has 512 threads and keeps under half of a
+// CU's LDS and registers, so two matrices share a CU and each one's barrier
+// and latency stalls are filled by the other's work; with fewer, 1,024 threads
+// give each matrix a whole CU.  Both forms round identically, so a problem's
+// result does not depend on how many are solved together.
 //
 // First stage of every rank-k SVD of the method (the block SVDs of the
 // storage phase and the SVD of each query's stacked matrix).  Only the span of
@@ -24,14 +27,19 @@
 //      unit vector, which can only happen inside a degenerate eigenspace).
 // The total work is O(c^3) with a small constant, against O(50 c^3) for
 // one-sided Jacobi.
+#include <atomic>
+
 #include "zs_internal.h"
 #include "wave.h"
 
 namespace zs {
 namespace {
 
-constexpr int NTH = 512;                  // threads of the eigen-solver work-group
-constexpr int kWaves = NTH / 64;
+// Partial sums of the reduction: the rows of wave w of a 1,024-thread
+// work-group (w + 16 m) are the even-m rows of wave w mod 8 of a 512-thread
+// one (w + 8 m), so that form keeps two FMA chains per wave and the sums agree
+// bit for bit.
+constexpr int kParts = 16;
 // Dynamic LDS of one work-group, at most: two fit a CU's 160 KiB together
 // with their static LDS.
 constexpr int kLdsBudget = 10112;          // doubles
@@ -56,10 +64,11 @@ __device__ __forceinline__ double start_value(int i, int g, int attempt)
 // dot partials) and the staging of Partial-SVD rows, then the eigenvector block
 // Z (c x kk) followed by the inverse-iteration arrays (two length-c arrays per
 // solver lane).
-template <int NMAX>
+template <int NMAX, int NTH>
 struct TriLayout {
+    static constexpr int kWaves = NTH / 64;
     static constexpr int FIXED = 4 * NMAX + kMaxK;
-    static constexpr int SCR = kWaves * NMAX + 3 * NMAX + kWaves;
+    static constexpr int SCR = kWaves * NMAX + 3 * NMAX + kParts;
     static_assert(SCR >= 8 * NMAX, "row staging of step 1 must fit the scratch");
     static_assert(NMAX <= 128, "two 64-bit words of pivot swaps per solver lane");
     static_assert((NMAX - 1) * NMAX / 2 <= NMAX * kMaxK, "reflectors fit the output slot");
@@ -76,13 +85,17 @@ struct TriLayout {
     static size_t bytes(int region) { return (size_t)(FIXED + region) * sizeof(double); }
 };
 
-template <int NMAX>
+template <int NMAX, int NTH>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4)))
 void eig_tri_kernel(int c, int k, int region, const Prob *__restrict__ probs,
                     const double *const *__restrict__ gsrc, const double *const *__restrict__ msrc,
                     double *__restrict__ Vk)
 {
+    constexpr int kWaves = NTH / 64;
+    constexpr int kSplit = kParts / kWaves;        // FMA chains per wave (1 or 2)
+    static_assert(kSplit == 1 || kSplit == 2, "512 or 1,024 threads");
     constexpr int RPW = NMAX / kWaves;             // matrix rows per wave
+    static_assert(RPW % kSplit == 0, "rows split evenly over the chains");
     constexpr int CPL = (NMAX + 63) / 64;          // matrix columns per lane
     constexpr int MR = 8;                          // rows of a Partial-SVD term staged at once
     extern __shared__ __align__(16) double smem[];
@@ -157,7 +170,7 @@ void eig_tri_kernel(int c, int k, int region, const Prob *__restrict__ probs,
     double *part = scr;                            // kWaves x NMAX wave partials of A v
     double *vbuf = part + kWaves * NMAX;           // 2 x NMAX
     double *psh = vbuf + 2 * NMAX;                 // NMAX
-    double *kpart = psh + NMAX;                    // kWaves
+    double *kpart = psh + NMAX;                    // kParts
     // Called by the wave that holds row jj once that row is final: x[s] is its
     // element (jj, lane + 64 s).  Sets d_jj and, below the last two rows, the
     // reflector of row jj (tau, e and the vector, also packed for later).
@@ -238,24 +251,35 @@ void eig_tri_kernel(int c, int k, int region, const Prob *__restrict__ probs,
 #pragma unroll
         for (int s = 0; s < CPL; ++s) vcl[s] = vc[min(lane + 64 * s, NMAX - 1)];
         // partial A v over this wave's rows (A symmetric: column sums = row sums)
-        // and this wave's share of v^T A v
-        double pp[CPL];
+        // and this wave's share of v^T A v, in kSplit chains (rows w + kWaves m
+        // with m of one parity each)
+        double pp[kSplit][CPL];
 #pragma unroll
-        for (int s = 0; s < CPL; ++s) pp[s] = 0.0;
+        for (int x = 0; x < kSplit; ++x)
+#pragma unroll
+            for (int s = 0; s < CPL; ++s) pp[x][s] = 0.0;
 #pragma unroll
         for (int m = 0; m < RPW; ++m) {
             const double vr = vc[wave + kWaves * m];
 #pragma unroll
-            for (int s = 0; s < CPL; ++s) pp[s] = fma(a[m][s], vr, pp[s]);
+            for (int s = 0; s < CPL; ++s) pp[m % kSplit][s] = fma(a[m][s], vr, pp[m % kSplit][s]);
         }
-        double vav = 0.0;
+#pragma unroll
+        for (int x = 0; x < kSplit; ++x) {
+            double vav = 0.0;
+#pragma unroll
+            for (int s = 0; s < CPL; ++s)
+                if (lane + 64 * s < c) vav = fma(pp[x][s], vcl[s], vav);
+            vav = wave_sum64(vav);
+            if (lane == 0) kpart[wave + kWaves * x] = vav;
+        }
+        // the first level of the pairwise tree over kParts partials (parts w and
+        // w + 8) is the sum of this wave's two chains
 #pragma unroll
         for (int s = 0; s < CPL; ++s) {
-            if (lane + 64 * s < NMAX) part[wave * NMAX + lane + 64 * s] = pp[s];
-            if (lane + 64 * s < c) vav = fma(pp[s], vcl[s], vav);
+            const double ps = kSplit == 2 ? pp[0][s] + pp[kSplit - 1][s] : pp[0][s];
+            if (lane + 64 * s < NMAX) part[wave * NMAX + lane + 64 * s] = ps;
         }
-        vav = wave_sum64(vav);
-        if (lane == 0) kpart[wave] = vav;
         __syncthreads();
         // p = tau A v (pairwise sum of the wave partials)
         if (tid < c) {
@@ -268,11 +292,11 @@ void eig_tri_kernel(int c, int k, int region, const Prob *__restrict__ probs,
                 for (int w = 0; w < st; ++w) h[w] += h[w + st];
             psh[tid] = t * h[0];
         }
-        double kv[kWaves];
+        double kv[kParts];
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) kv[w] = kpart[w];
+        for (int w = 0; w < kParts; ++w) kv[w] = kpart[w];
 #pragma unroll
-        for (int st = kWaves / 2; st >= 1; st /= 2)
+        for (int st = kParts / 2; st >= 1; st /= 2)
 #pragma unroll
             for (int w = 0; w < st; ++w) kv[w] += kv[w + st];
         const double K = 0.5 * t * t * kv[0];      // (tau/2) p.v with p.v = tau v^T A v
@@ -608,18 +632,46 @@ void eig_tri_kernel(int c, int k, int region, const Prob *__restrict__ probs,
     }
 }
 
-template <int NMAX>
+template <int NMAX, int NTH>
 hipError_t run_eig_tri(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
                        const double *const *msrc, double *Vk, hipStream_t stream)
 {
     // every problem's kk is at most k
-    const int region = TriLayout<NMAX>::region(c, k);
-    const size_t lds = TriLayout<NMAX>::bytes(region);
+    const int region = TriLayout<NMAX, NTH>::region(c, k);
+    const size_t lds = TriLayout<NMAX, NTH>::bytes(region);
     static size_t cur = 0;
-    hipError_t e = ensure_lds((const void *)eig_tri_kernel<NMAX>, lds, cur);
+    hipError_t e = ensure_lds((const void *)eig_tri_kernel<NMAX, NTH>, lds, cur);
     if (e != hipSuccess) return e;
-    eig_tri_kernel<NMAX><<<nprob, NTH, lds, stream>>>(c, k, region, probs, gsrc, msrc, Vk);
+    eig_tri_kernel<NMAX, NTH><<<nprob, NTH, lds, stream>>>(c, k, region, probs, gsrc, msrc, Vk);
     return hipGetLastError();
+}
+
+// Compute units of the current device (0 if the query fails), cached per device.
+int device_cus()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    cache[dev].store(n, std::memory_order_relaxed);
+    return n;
+}
+
+// Two matrices per CU once there are more matrices than CUs, else one.
+template <int NMAX>
+hipError_t run_eig_tri(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
+                       const double *const *msrc, double *Vk, hipStream_t stream)
+{
+    if (nprob <= device_cus()) return run_eig_tri<NMAX, 1024>(c, k, probs, nprob, gsrc, msrc, Vk, stream);
+    return run_eig_tri<NMAX, 512>(c, k, probs, nprob, gsrc, msrc, Vk, stream);
 }
 
 }  // namespace
