@@ -201,7 +201,7 @@ def main():
     # Write ceiling of this very output allocation: a plain fill of the batch's
     # U buffer.  Sustained write bandwidth into a large allocation depends on
     # where it landed in physical memory (5.5 to 6.9 TB/s seen for the same
-    # 52 GB size), so blockprod is also judged against this figure.
+    # 52 GB size), so blockprod is also measured against this figure.
     # Two plain writers, torch's fill and zeroing (a runtime memset); the faster
     # one's mean over three passes is the ceiling.
     fills = {}
