@@ -65,9 +65,14 @@ __global__ __launch_bounds__(kThreads) void order_pieces_kernel(const Piece *__r
     perm[boff[blk] + atomicAdd(&bcount[blk], 1)] = p;
 }
 
+// Y elements per thread carried one piece ahead in coef_kernel (all of Y_i
+// while k k_q <= 4 kThreads; the rest is loaded when it is needed).
+constexpr int kCoefPre = 4;
+
 // One work-group per chunk of pieces of one query (the projection chunks):
 // F (k_q x k_q) is loaded once; per piece, Y_i (k x k_q) gives U_r(i) = Y_i F,
-// and C_i = U_r(i) or T_i U_r(i) is written transposed and padded.
+// and C_i = U_r(i) or T_i U_r(i) is written transposed and padded.  The next
+// piece's Y_i is loaded into registers while this one is computed.
 __global__ __launch_bounds__(kThreads) void coef_kernel(int k, const Piece *__restrict__ pieces,
                                                         const StackChunk *__restrict__ chunks,
                                                         const double *__restrict__ Y,
@@ -86,16 +91,33 @@ __global__ __launch_bounds__(kThreads) void coef_kernel(int k, const Piece *__re
     double *Ts = Ur + k * kq;             // k x k
     const double *Fp = F + (int64_t)ch.prob * kSlotK;
     for (int e = tid; e < kq * kq; e += kThreads) Fs[e] = Fp[e];
+    const int nky = k * kq;
+    double ypre[kCoefPre];
+    auto fetch = [&](int p) {
+        const double *Yn = Y + pieces[ch.piece0 + p].y_off;
+#pragma unroll
+        for (int x = 0; x < kCoefPre; ++x) {
+            const int e = tid + x * kThreads;
+            ypre[x] = e < nky ? Yn[e] : 0.0;
+        }
+    };
+    if (ch.npieces > 0) fetch(0);
     for (int p = 0; p < ch.npieces; ++p) {
         const Piece &pc = pieces[ch.piece0 + p];
         const double *Yp = Y + pc.y_off;
         const bool partial = pc.t_idx >= 0;
         __syncthreads();                  // the previous piece is done with Ys, Ur, Ts
-        for (int e = tid; e < k * kq; e += kThreads) Ys[e] = Yp[e];
+#pragma unroll
+        for (int x = 0; x < kCoefPre; ++x) {
+            const int e = tid + x * kThreads;
+            if (e < nky) Ys[e] = ypre[x];
+        }
+        for (int e = tid + kCoefPre * kThreads; e < nky; e += kThreads) Ys[e] = Yp[e];
         if (partial) {
             const double *Tp = T + (int64_t)pc.t_idx * k * k;
             for (int e = tid; e < k * k; e += kThreads) Ts[e] = Tp[e];
         }
+        if (p + 1 < ch.npieces) fetch(p + 1);   // consumed after this piece's products
         __syncthreads();
         for (int e = tid; e < k * kq; e += kThreads) {
             const int l = e / kq, j = e % kq;
