@@ -8,7 +8,11 @@
 //   2. Householder tridiagonalisation Q^T W Q = T, one reflector per step:
 //      the reflector of row j (rows are contiguous, the matrix is kept
 //      symmetric) is formed in LDS and saved over the dead part of row j;
-//      p = t W22 v with one wave per row; W22 -= v w^T + w v^T.
+//      p = t W22 v, W22 -= v w^T + w v^T.  The update of step j and the
+//      product of step j+1 share one pass over the trailing rows: row j+1 is
+//      updated first and gives the next reflector, then every other trailing
+//      row is updated and multiplied by it while in registers (each wave
+//      takes several rows at a time, so their loads overlap).
 //   3. The kk largest eigenvalues of T by multisection on Sturm counts.
 //   4. Eigenvectors of T by inverse iteration (tridiagonal LU with partial
 //      pivoting, two solves, one thread per cluster of eigenvalues closer
@@ -19,6 +23,7 @@
 //      eigenspace).
 // Scratch per problem: c^2 + 5 c kk doubles (eig_big_scratch_doubles).
 #include "zs_internal.h"
+#include "wave.h"
 
 namespace zs {
 namespace {
@@ -67,7 +72,7 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
                                                       double *__restrict__ Vk)
 {
     __shared__ double d[kBigMax], e[kBigMax], e2[kBigMax], tau[kBigMax];
-    __shared__ double vsh[kBigMax], wsh[kBigMax];
+    __shared__ double vbuf[2][kBigMax], wbuf[2][kBigMax];   // v and p / w of two steps
     __shared__ double xs[NTH];
     __shared__ int cs[NTH];
     __shared__ double lam[kMaxK], glo[kMaxK], ghi[kMaxK], red[kWaves];
@@ -102,13 +107,15 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
     }
 
     // ---- 2. tridiagonalisation ---------------------------------------------------
-    for (int j = 0; j + 2 < c; ++j) {
-        const int n1 = c - j - 1;
-        double *rowj = W + (int64_t)j * c;
+    // Reflector of row jr (final): tau, e, d of jr and v (length c - jr - 1,
+    // v(0) = 1) into vdst and over the dead part of row jr.
+    auto make_reflector = [&](int jr, double *vdst) {
+        const int n = c - jr - 1;
+        double *rowj = W + (int64_t)jr * c;
         double part = 0.0;
-        for (int i = tid + 1; i < n1; i += NTH) part = fma(rowj[j + 1 + i], rowj[j + 1 + i], part);
+        for (int i = tid + 1; i < n; i += NTH) part = fma(rowj[jr + 1 + i], rowj[jr + 1 + i], part);
         const double s = block_sum(part, red);
-        const double alpha = rowj[j + 1];
+        const double alpha = rowj[jr + 1];
         double t = 0.0, beta = alpha, scal = 0.0;
         if (s > 0.0) {
             const double mu = sqrt(alpha * alpha + s);
@@ -117,43 +124,92 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
             scal = 1.0 / (alpha - beta);
         }
         if (tid == 0) {
-            tau[j] = t;
-            e[j] = beta;
-            d[j] = rowj[j];
+            tau[jr] = t;
+            e[jr] = beta;
+            d[jr] = rowj[jr];
         }
-        for (int i = tid; i < n1; i += NTH) vsh[i] = (i == 0) ? 1.0 : rowj[j + 1 + i] * scal;
+        for (int i = tid; i < n; i += NTH) vdst[i] = (i == 0) ? 1.0 : rowj[jr + 1 + i] * scal;
         __syncthreads();
-        // v_j replaces the dead entries of row j (read back in phase 5)
-        for (int i = tid; i < n1; i += NTH) rowj[j + 1 + i] = vsh[i];
-        if (t == 0.0) {
+        // v_jr replaces the dead entries of row jr (read back in phase 5)
+        for (int i = tid; i < n; i += NTH) rowj[jr + 1 + i] = vdst[i];
+    };
+    // Step j runs with v_j = vbuf[j & 1] and p_j = t_j W22 v_j in wbuf[j & 1];
+    // j = -1 only forms reflector 0 and p_0.
+    constexpr int RU = 4;                          // rows per wave in flight
+    for (int j = -1; j + 2 < c; ++j) {
+        const int n1 = c - j - 1;                  // trailing size of step j
+        const double *vc = vbuf[j & 1];
+        double *wc = wbuf[j & 1];
+        double *vn = vbuf[(j + 1) & 1];
+        double *wn = wbuf[(j + 1) & 1];
+        const double t = j >= 0 ? tau[j] : 0.0;
+        const bool upd = t != 0.0;
+        if (upd) {
+            // w = p - K v, K = (t/2) p.v
+            double pk = 0.0;
+            for (int i = tid; i < n1; i += NTH) pk = fma(wc[i], vc[i], pk);
+            const double K = 0.5 * t * block_sum(pk, red);
+            for (int i = tid; i < n1; i += NTH) wc[i] -= K * vc[i];
             __syncthreads();
-            continue;
+            // row j+1 first: it gives the next reflector
+            double *r1 = W + (int64_t)(j + 1) * c + j + 1;
+            const double v0 = vc[0], w0 = wc[0];
+            for (int i = tid; i < n1; i += NTH) r1[i] -= v0 * wc[i] + w0 * vc[i];
+            __syncthreads();
         }
-        // p = t W22 v: one wave per row
-        for (int r = wave; r < n1; r += kWaves) {
-            const double *wr = W + (int64_t)(j + 1 + r) * c + j + 1;
-            double acc = 0.0;
-            for (int i = lane; i < n1; i += 64) acc = fma(wr[i], vsh[i], acc);
-            acc = wave_sum(acc);
-            if (lane == 0) wsh[r] = t * acc;
+        const bool next = j + 3 < c;
+        if (next) {
+            make_reflector(j + 1, vn);
+            __syncthreads();
         }
-        __syncthreads();
-        double pk = 0.0;
-        for (int i = tid; i < n1; i += NTH) pk = fma(wsh[i], vsh[i], pk);
-        const double K = 0.5 * t * block_sum(pk, red);
-        for (int i = tid; i < n1; i += NTH) wsh[i] -= K * vsh[i];      // w = p - K v
-        __syncthreads();
-        // W22 -= v w^T + w v^T, rows by waves, columns by lanes
-        for (int r = wave; r < n1; r += kWaves) {
-            double *wr = W + (int64_t)(j + 1 + r) * c + j + 1;
-            const double vr = vsh[r], wrr = wsh[r];
-            for (int i = lane; i < n1; i += 64) wr[i] -= vr * wsh[i] + wrr * vsh[i];
+        const double tn = next ? tau[j + 1] : 0.0;
+        const bool dot = tn != 0.0;
+        // rows j+2 .. c-1, columns j+2 .. c-1: update of step j, then p_{j+1}
+        const int nr = n1 - 1;
+        double *Wt = W + (int64_t)(j + 2) * c + j + 2;
+        if (upd || dot) {
+            for (int q0 = wave * RU; q0 < nr; q0 += kWaves * RU) {
+                double vr[RU], wr[RU], acc[RU];
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    const bool live = q0 + u < nr;
+                    vr[u] = (upd && live) ? vc[q0 + u + 1] : 0.0;
+                    wr[u] = (upd && live) ? wc[q0 + u + 1] : 0.0;
+                    acc[u] = 0.0;
+                }
+                for (int i0 = 0; i0 < nr; i0 += 64) {
+                    const int ip = i0 + lane;
+                    const bool in = ip < nr;
+                    const double vi = (upd && in) ? vc[ip + 1] : 0.0;
+                    const double wi = (upd && in) ? wc[ip + 1] : 0.0;
+                    const double vx = (dot && in) ? vn[ip] : 0.0;
+                    double x[RU];
+#pragma unroll
+                    for (int u = 0; u < RU; ++u)
+                        x[u] = (in && q0 + u < nr) ? Wt[(int64_t)(q0 + u) * c + ip] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < RU; ++u) {
+                        if (upd) {
+                            x[u] -= vr[u] * wi + wr[u] * vi;
+                            if (in && q0 + u < nr) Wt[(int64_t)(q0 + u) * c + ip] = x[u];
+                        }
+                        acc[u] = fma(x[u], vx, acc[u]);
+                    }
+                }
+                if (dot) {
+#pragma unroll
+                    for (int u = 0; u < RU; ++u) {
+                        const double sdot = wave_sum64(acc[u]);
+                        if (lane == 0 && q0 + u < nr) wn[q0 + u] = tn * sdot;
+                    }
+                }
+            }
         }
         __syncthreads();
     }
     if (tid == 0) {
         d[c - 2] = W[(int64_t)(c - 2) * c + c - 2];
-        e[c - 2] = W[(int64_t)(c - 1) * c + c - 2];
+        e[c - 2] = W[(int64_t)(c - 2) * c + c - 1];     // row c-2 is updated in full
         d[c - 1] = W[(int64_t)(c - 1) * c + c - 1];
         double gl = d[0], gu = d[0], emax2 = 0.0;
         for (int i = 0; i < c; ++i) {
