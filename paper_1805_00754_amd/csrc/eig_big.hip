@@ -44,7 +44,7 @@ __device__ __forceinline__ double wave_sum(double v)
 __device__ __forceinline__ double block_sum(double v, double *red)
 {
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    v = wave_sum(v);
+    v = wave_sum64(v);
     __syncthreads();                      // red is free
     if (lane == 0) red[wave] = v;
     __syncthreads();
@@ -136,6 +136,7 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
     // Step j runs with v_j = vbuf[j & 1] and p_j = t_j W22 v_j in wbuf[j & 1];
     // j = -1 only forms reflector 0 and p_0.
     constexpr int RU = 4;                          // rows per wave in flight
+    constexpr int CU = 4;                          // 64-column chunks per row in flight
     for (int j = -1; j + 2 < c; ++j) {
         const int n1 = c - j - 1;                  // trailing size of step j
         const double *vc = vbuf[j & 1];
@@ -177,24 +178,34 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
                     wr[u] = (upd && live) ? wc[q0 + u + 1] : 0.0;
                     acc[u] = 0.0;
                 }
-                for (int i0 = 0; i0 < nr; i0 += 64) {
-                    const int ip = i0 + lane;
-                    const bool in = ip < nr;
-                    const double vi = (upd && in) ? vc[ip + 1] : 0.0;
-                    const double wi = (upd && in) ? wc[ip + 1] : 0.0;
-                    const double vx = (dot && in) ? vn[ip] : 0.0;
-                    double x[RU];
+                for (int i0 = 0; i0 < nr; i0 += 64 * CU) {
+                    double vi[CU], wi[CU], vx[CU], x[RU][CU];
+#pragma unroll
+                    for (int h = 0; h < CU; ++h) {
+                        const int ip = i0 + 64 * h + lane;
+                        const bool in = ip < nr;
+                        vi[h] = (upd && in) ? vc[ip + 1] : 0.0;
+                        wi[h] = (upd && in) ? wc[ip + 1] : 0.0;
+                        vx[h] = (dot && in) ? vn[ip] : 0.0;
+                    }
 #pragma unroll
                     for (int u = 0; u < RU; ++u)
-                        x[u] = (in && q0 + u < nr) ? Wt[(int64_t)(q0 + u) * c + ip] : 0.0;
 #pragma unroll
-                    for (int u = 0; u < RU; ++u) {
-                        if (upd) {
-                            x[u] -= vr[u] * wi + wr[u] * vi;
-                            if (in && q0 + u < nr) Wt[(int64_t)(q0 + u) * c + ip] = x[u];
+                        for (int h = 0; h < CU; ++h) {
+                            const int ip = i0 + 64 * h + lane;
+                            x[u][h] = (ip < nr && q0 + u < nr) ? Wt[(int64_t)(q0 + u) * c + ip] : 0.0;
                         }
-                        acc[u] = fma(x[u], vx, acc[u]);
-                    }
+#pragma unroll
+                    for (int u = 0; u < RU; ++u)
+#pragma unroll
+                        for (int h = 0; h < CU; ++h) {
+                            const int ip = i0 + 64 * h + lane;
+                            if (upd) {
+                                x[u][h] -= vr[u] * wi[h] + wr[u] * vi[h];
+                                if (ip < nr && q0 + u < nr) Wt[(int64_t)(q0 + u) * c + ip] = x[u][h];
+                            }
+                            acc[u] = fma(x[u][h], vx[h], acc[u]);
+                        }
                 }
                 if (dot) {
 #pragma unroll
