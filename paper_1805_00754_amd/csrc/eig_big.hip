@@ -31,7 +31,7 @@ namespace {
 constexpr int NTH = 1024;
 constexpr int kWaves = NTH / 64;
 constexpr int kBigMax = 1024;             // largest c
-constexpr int kVPL = kBigMax / 64;        // vector entries per lane in phase 5
+constexpr int kWU = 8;                    // matrix entries per thread in flight in phase 1
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -65,6 +65,8 @@ __device__ __forceinline__ double start_value(int i, int g, int attempt)
     return (double)(x & 0xFFFFFF) / 8388608.0 - 1.0;
 }
 
+// VPL: vector entries per lane in phase 5 (c <= 64 VPL).
+template <int VPL>
 __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *__restrict__ probs,
                                                       const double *const *__restrict__ gsrc,
                                                       const double *const *__restrict__ msrc,
@@ -89,19 +91,51 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
     double *out = Vk + (int64_t)blockIdx.x * c * kMaxK;
 
     // ---- 1. W ------------------------------------------------------------------
-    for (int64_t q = tid; q < (int64_t)c * c; q += NTH) {
-        double s = 0.0;
-        for (int g = 0; g < P.ng; ++g) s += gsrc[P.g0 + g][q];
-        W[q] = s;
+    //      Each thread sums kWU entries at a time (independent loads in flight),
+    //      each entry in the fixed term order.
+    const int64_t cc = (int64_t)c * c;
+    for (int64_t q0 = tid; q0 < cc; q0 += (int64_t)NTH * kWU) {
+        double s[kWU];
+#pragma unroll
+        for (int x = 0; x < kWU; ++x) s[x] = 0.0;
+        for (int g = 0; g < P.ng; ++g) {
+            const double *src = gsrc[P.g0 + g];
+#pragma unroll
+            for (int x = 0; x < kWU; ++x) {
+                const int64_t q = q0 + (int64_t)x * NTH;
+                if (q < cc) s[x] += src[q];
+            }
+        }
+#pragma unroll
+        for (int x = 0; x < kWU; ++x) {
+            const int64_t q = q0 + (int64_t)x * NTH;
+            if (q < cc) W[q] = s[x];
+        }
     }
     __syncthreads();
     for (int m = 0; m < P.nm; ++m) {
         const double *R = msrc[P.m0 + m];                       // k x c rows
-        for (int64_t q = tid; q < (int64_t)c * c; q += NTH) {
-            const int i = (int)(q / c), j = (int)(q % c);
-            double s = W[q];
-            for (int r = 0; r < k; ++r) s = fma(R[(int64_t)r * c + i], R[(int64_t)r * c + j], s);
-            W[q] = s;
+        for (int64_t q0 = tid; q0 < cc; q0 += (int64_t)NTH * kWU) {
+            double s[kWU];
+            int ii[kWU], jj[kWU];
+#pragma unroll
+            for (int x = 0; x < kWU; ++x) {
+                const int64_t q = q0 + (int64_t)x * NTH;
+                const int64_t qq = q < cc ? q : 0;
+                ii[x] = (int)(qq / c);
+                jj[x] = (int)(qq % c);
+                s[x] = q < cc ? W[q] : 0.0;
+            }
+            for (int r = 0; r < k; ++r) {
+                const double *Rr = R + (int64_t)r * c;
+#pragma unroll
+                for (int x = 0; x < kWU; ++x) s[x] = fma(Rr[ii[x]], Rr[jj[x]], s[x]);
+            }
+#pragma unroll
+            for (int x = 0; x < kWU; ++x) {
+                const int64_t q = q0 + (int64_t)x * NTH;
+                if (q < cc) W[q] = s[x];
+            }
         }
         __syncthreads();
     }
@@ -372,40 +406,60 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
         __syncthreads();
     }
 
-    // ---- 5. back-transformation: one column per wave pass --------------------------
-    for (int g = wave; g < kk; g += kWaves) {
-        double z0[kVPL];
+    // ---- 5. back-transformation: CPP columns per wave pass -----------------------
+    //      The columns of a pass share each reflector's load; up to c = 512 the
+    //      next reflector is loaded while this one is applied (above, the
+    //      registers are not there for it).
+    {
+        constexpr int CPP = VPL <= 4 ? 4 : (VPL <= 8 ? 2 : 1);
+        constexpr bool PRE = VPL <= 8;
+        auto vload = [&](int j, double (&v)[VPL]) {
+            const double *vj = W + (int64_t)max(j, 0) * c + max(j, 0) + 1;   // v_j(i') at vj[i']
 #pragma unroll
-        for (int u = 0; u < kVPL; ++u) {
-            const int i = lane + 64 * u;
-            z0[u] = i < c ? Z[(int64_t)i * kk + g] : 0.0;
-        }
-        for (int j = c - 3; j >= 0; --j) {
-            const double t = tau[j];
-            if (t == 0.0) continue;
-            const double *vj = W + (int64_t)j * c + j + 1;   // v_j(i') at vj[i'], row j + 1 + i'
-            double s0 = 0.0;
-#pragma unroll
-            for (int u = 0; u < kVPL; ++u) {
+            for (int u = 0; u < VPL; ++u) {
                 const int i = lane + 64 * u;
-                const double v = (i >= j + 1 && i < c) ? vj[i - j - 1] : 0.0;
-                s0 = fma(v, z0[u], s0);
+                v[u] = (j >= 0 && i >= j + 1 && i < c) ? vj[i - j - 1] : 0.0;
             }
-            s0 = t * wave_sum(s0);
+        };
+        for (int g0 = wave * CPP; g0 < kk; g0 += kWaves * CPP) {
+            double z[CPP][VPL];
 #pragma unroll
-            for (int u = 0; u < kVPL; ++u) {      // v_j again (an L1 hit)
-                const int i = lane + 64 * u;
-                const double v = (i >= j + 1 && i < c) ? vj[i - j - 1] : 0.0;
-                z0[u] -= s0 * v;
+            for (int h = 0; h < CPP; ++h)
+#pragma unroll
+                for (int u = 0; u < VPL; ++u) {
+                    const int i = lane + 64 * u;
+                    z[h][u] = (g0 + h < kk && i < c) ? Z[(int64_t)i * kk + g0 + h] : 0.0;
+                }
+            double vq[VPL], vn[PRE ? VPL : 1];
+            if constexpr (PRE) vload(c - 3, vq);
+            for (int j = c - 3; j >= 0; --j) {
+                if constexpr (PRE) vload(j - 1, vn);
+                else vload(j, vq);
+                const double t = tau[j];
+                if (t != 0.0) {
+#pragma unroll
+                    for (int h = 0; h < CPP; ++h) {
+                        double s0 = 0.0;
+#pragma unroll
+                        for (int u = 0; u < VPL; ++u) s0 = fma(vq[u], z[h][u], s0);
+                        s0 = t * wave_sum64(s0);
+#pragma unroll
+                        for (int u = 0; u < VPL; ++u) z[h][u] -= s0 * vq[u];
+                    }
+                }
+                if constexpr (PRE)
+#pragma unroll
+                    for (int u = 0; u < VPL; ++u) vq[u] = vn[u];
             }
-        }
 #pragma unroll
-        for (int u = 0; u < kVPL; ++u) {
-            const int i = lane + 64 * u;
-            if (i < c) Z[(int64_t)i * kk + g] = z0[u];
+            for (int h = 0; h < CPP; ++h)
+#pragma unroll
+                for (int u = 0; u < VPL; ++u) {
+                    const int i = lane + 64 * u;
+                    if (g0 + h < kk && i < c) Z[(int64_t)i * kk + g0 + h] = z[h][u];
+                }
         }
     }
-    __threadfence_block();
     __syncthreads();
 
     // ---- 6. classical Gram-Schmidt, twice -----------------------------------------
@@ -456,7 +510,9 @@ hipError_t launch_eig_big(int c, int k, const Prob *probs, int nprob, const doub
     if (nprob <= 0) return hipSuccess;
     if (c > kBigMax) return hipErrorInvalidValue;
     timing_begin("eig", stream);
-    eig_big_kernel<<<nprob, NTH, 0, stream>>>(c, k, probs, gsrc, msrc, scratch, Vk);
+    if (c <= 256) eig_big_kernel<4><<<nprob, NTH, 0, stream>>>(c, k, probs, gsrc, msrc, scratch, Vk);
+    else if (c <= 512) eig_big_kernel<8><<<nprob, NTH, 0, stream>>>(c, k, probs, gsrc, msrc, scratch, Vk);
+    else eig_big_kernel<16><<<nprob, NTH, 0, stream>>>(c, k, probs, gsrc, msrc, scratch, Vk);
     hipError_t e = hipGetLastError();
     timing_end("eig", stream);
     return e;
