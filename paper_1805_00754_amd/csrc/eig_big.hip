@@ -113,31 +113,42 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
         }
     }
     __syncthreads();
-    for (int m = 0; m < P.nm; ++m) {
-        const double *R = msrc[P.m0 + m];                       // k x c rows
-        for (int64_t q0 = tid; q0 < cc; q0 += (int64_t)NTH * kWU) {
-            double s[kWU];
-            int ii[kWU], jj[kWU];
+    // Grams of the Partial-SVD rows: W += R^T R, R k x c.  Each thread owns
+    // 4 x 8 tiles of W (12 loads feed 32 FMAs per row of R); every entry is
+    // still W(i, j) followed by the FMAs over the rows of R in order.
+    {
+        constexpr int TI = 4, TJ = 8;
+        const int nti = (c + TI - 1) / TI, ntj = (c + TJ - 1) / TJ;
+        for (int m = 0; m < P.nm; ++m) {
+            const double *R = msrc[P.m0 + m];                   // k x c rows
+            for (int tt = tid; tt < nti * ntj; tt += NTH) {
+                const int i0 = (tt / ntj) * TI, j0 = (tt % ntj) * TJ;
+                double acc[TI][TJ];
 #pragma unroll
-            for (int x = 0; x < kWU; ++x) {
-                const int64_t q = q0 + (int64_t)x * NTH;
-                const int64_t qq = q < cc ? q : 0;
-                ii[x] = (int)(qq / c);
-                jj[x] = (int)(qq % c);
-                s[x] = q < cc ? W[q] : 0.0;
-            }
-            for (int r = 0; r < k; ++r) {
-                const double *Rr = R + (int64_t)r * c;
+                for (int a = 0; a < TI; ++a)
 #pragma unroll
-                for (int x = 0; x < kWU; ++x) s[x] = fma(Rr[ii[x]], Rr[jj[x]], s[x]);
-            }
+                    for (int b = 0; b < TJ; ++b)
+                        acc[a][b] = (i0 + a < c && j0 + b < c) ? W[(int64_t)(i0 + a) * c + j0 + b] : 0.0;
+                for (int r = 0; r < k; ++r) {
+                    const double *Rr = R + (int64_t)r * c;
+                    double ri[TI], rj[TJ];
 #pragma unroll
-            for (int x = 0; x < kWU; ++x) {
-                const int64_t q = q0 + (int64_t)x * NTH;
-                if (q < cc) W[q] = s[x];
+                    for (int a = 0; a < TI; ++a) ri[a] = Rr[min(i0 + a, c - 1)];
+#pragma unroll
+                    for (int b = 0; b < TJ; ++b) rj[b] = Rr[min(j0 + b, c - 1)];
+#pragma unroll
+                    for (int a = 0; a < TI; ++a)
+#pragma unroll
+                        for (int b = 0; b < TJ; ++b) acc[a][b] = fma(ri[a], rj[b], acc[a][b]);
+                }
+#pragma unroll
+                for (int a = 0; a < TI; ++a)
+#pragma unroll
+                    for (int b = 0; b < TJ; ++b)
+                        if (i0 + a < c && j0 + b < c) W[(int64_t)(i0 + a) * c + j0 + b] = acc[a][b];
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     // ---- 2. tridiagonalisation ---------------------------------------------------
