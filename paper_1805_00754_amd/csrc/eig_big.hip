@@ -75,6 +75,7 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
 {
     __shared__ double d[kBigMax], e[kBigMax], e2[kBigMax], tau[kBigMax];
     __shared__ double vbuf[2][kBigMax], wbuf[2][kBigMax];   // v and p / w of two steps
+    __shared__ double rowb[kBigMax];      // the next row to reduce, from its diagonal on
     __shared__ double xs[NTH];
     __shared__ int cs[NTH];
     __shared__ double lam[kMaxK], glo[kMaxK], ghi[kMaxK], red[kWaves];
@@ -152,15 +153,16 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
     }
 
     // ---- 2. tridiagonalisation ---------------------------------------------------
-    // Reflector of row jr (final): tau, e, d of jr and v (length c - jr - 1,
-    // v(0) = 1) into vdst and over the dead part of row jr.
+    // Reflector of row jr (final, entries jr .. c-1 in rowb): tau, e, d of jr
+    // and v (length c - jr - 1, v(0) = 1) into vdst and over the dead part of
+    // row jr in W.
     auto make_reflector = [&](int jr, double *vdst) {
         const int n = c - jr - 1;
         double *rowj = W + (int64_t)jr * c;
         double part = 0.0;
-        for (int i = tid + 1; i < n; i += NTH) part = fma(rowj[jr + 1 + i], rowj[jr + 1 + i], part);
+        for (int i = tid + 1; i < n; i += NTH) part = fma(rowb[1 + i], rowb[1 + i], part);
         const double s = block_sum(part, red);
-        const double alpha = rowj[jr + 1];
+        const double alpha = rowb[1];
         double t = 0.0, beta = alpha, scal = 0.0;
         if (s > 0.0) {
             const double mu = sqrt(alpha * alpha + s);
@@ -171,17 +173,21 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
         if (tid == 0) {
             tau[jr] = t;
             e[jr] = beta;
-            d[jr] = rowj[jr];
+            d[jr] = rowb[0];
         }
-        for (int i = tid; i < n; i += NTH) vdst[i] = (i == 0) ? 1.0 : rowj[jr + 1 + i] * scal;
+        for (int i = tid; i < n; i += NTH) vdst[i] = (i == 0) ? 1.0 : rowb[1 + i] * scal;
         __syncthreads();
         // v_jr replaces the dead entries of row jr (read back in phase 5)
         for (int i = tid; i < n; i += NTH) rowj[jr + 1 + i] = vdst[i];
     };
     // Step j runs with v_j = vbuf[j & 1] and p_j = t_j W22 v_j in wbuf[j & 1];
-    // j = -1 only forms reflector 0 and p_0.
+    // j = -1 only forms reflector 0 and p_0.  Row j+1 lives in rowb from the
+    // pass of step j-1 on (the pass that updates it also keeps it there), so
+    // its last update and its reflector take no global round trip.
     constexpr int RU = 4;                          // rows per wave in flight
     constexpr int CU = 4;                          // 64-column chunks per row in flight
+    for (int i = tid; i < c; i += NTH) rowb[i] = W[i];   // row 0
+    __syncthreads();
     for (int j = -1; j + 2 < c; ++j) {
         const int n1 = c - j - 1;                  // trailing size of step j
         const double *vc = vbuf[j & 1];
@@ -198,12 +204,15 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
             for (int i = tid; i < n1; i += NTH) wc[i] -= K * vc[i];
             __syncthreads();
             // row j+1 first: it gives the next reflector
-            double *r1 = W + (int64_t)(j + 1) * c + j + 1;
             const double v0 = vc[0], w0 = wc[0];
-            for (int i = tid; i < n1; i += NTH) r1[i] -= v0 * wc[i] + w0 * vc[i];
+            for (int i = tid; i < n1; i += NTH) rowb[i] -= v0 * wc[i] + w0 * vc[i];
             __syncthreads();
         }
         const bool next = j + 3 < c;
+        if (!next && tid == 0) {                   // row c-2 is final: d and e of it
+            d[c - 2] = rowb[0];
+            e[c - 2] = rowb[1];
+        }
         if (next) {
             make_reflector(j + 1, vn);
             __syncthreads();
@@ -251,6 +260,12 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
                             }
                             acc[u] = fma(x[u][h], vx[h], acc[u]);
                         }
+                    if (q0 == 0)                   // row j+2, the next row to reduce
+#pragma unroll
+                        for (int h = 0; h < CU; ++h) {
+                            const int ip = i0 + 64 * h + lane;
+                            if (ip < nr) rowb[ip] = x[0][h];
+                        }
                 }
                 if (dot) {
 #pragma unroll
@@ -260,13 +275,13 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
                     }
                 }
             }
+        } else {
+            for (int i = tid; i < nr; i += NTH) rowb[i] = Wt[i];   // row j+2 as it is
         }
         __syncthreads();
     }
     if (tid == 0) {
-        d[c - 2] = W[(int64_t)(c - 2) * c + c - 2];
-        e[c - 2] = W[(int64_t)(c - 2) * c + c - 1];     // row c-2 is updated in full
-        d[c - 1] = W[(int64_t)(c - 1) * c + c - 1];
+        d[c - 1] = rowb[0];                        // row c-1, kept by the last pass
         double gl = d[0], gu = d[0], emax2 = 0.0;
         for (int i = 0; i < c; ++i) {
             const double ei = i + 1 < c ? fabs(e[i]) : 0.0;
