@@ -1,7 +1,8 @@
 // Leading eigenvectors of a symmetric positive semi-definite c x c Gram matrix
 // for 128 < c <= 1024, one work-group of 1024 threads per matrix, with the
 // matrix in a global scratch slot (L2 / Infinity Cache resident) and the
-// vectors of each step in LDS.  Same method as the LDS solver (eig_tri.hip):
+// vectors of each step in LDS.  Same method as the solver for c <= 128
+// (eig_tri.hip), whose matrix fits in registers:
 //
 //   1. W <- the problem's Gram terms (tree nodes / block chunk Grams, then the
 //      Grams of its Partial-SVD rows), in a fixed order.
@@ -9,15 +10,17 @@
 //      the reflector of row j (rows are contiguous, the matrix is kept
 //      symmetric) is formed in LDS and saved over the dead part of row j;
 //      p = t W22 v, W22 -= v w^T + w v^T.  The update of step j and the
-//      product of step j+1 share one pass over the trailing rows: row j+1 is
-//      updated first and gives the next reflector, then every other trailing
-//      row is updated and multiplied by it while in registers (each wave
-//      takes several rows at a time, so their loads overlap).
+//      product of step j+1 share one pass over the trailing rows: row j+1
+//      (kept in LDS by the previous pass) is updated first and gives the next
+//      reflector, then every other trailing row is updated and multiplied by
+//      it while in registers (each wave takes several rows at a time, so
+//      their loads overlap).
 //   3. The kk largest eigenvalues of T by multisection on Sturm counts.
 //   4. Eigenvectors of T by inverse iteration (tridiagonal LU with partial
 //      pivoting, two solves, one thread per cluster of eigenvalues closer
 //      than 1e-9 ||T||, Gram-Schmidt inside a cluster), arrays in scratch.
-//   5. Back-transformation x = H_0 ... H_{c-3} z, one column per wave pass.
+//   5. Back-transformation x = H_0 ... H_{c-3} z, several columns per wave
+//      pass sharing each reflector's load.
 //   6. Two passes of classical Gram-Schmidt (a collapsed vector is replaced
 //      by the next unit vector, which only happens in a degenerate
 //      eigenspace).
