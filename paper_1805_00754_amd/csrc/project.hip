@@ -90,6 +90,14 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
                                              double *__restrict__ G, RowRef fallback, double *sm)
 {
     constexpr int NCB = (KQM + 15) / 16;           // 16-column blocks of Y
+    // With KQM = 16 m + 4 (m >= 1) the last block has 4 columns and runs on
+    // the 4x4x4 matrix-core shape at a quarter of the cost: its A operand is
+    // the 16x16x4 A fragment unchanged (A(b, i, s) in lane 16 s + 4 b + i),
+    // B(s, j) sits in lane 16 s + 4 b + j for every block b, and D(b, i, j)
+    // in lane 16 i + 4 b + j.  The result is moved into the 16 x 16 layout of
+    // the last block afterwards, so the rest of the tile does not change.
+    constexpr bool TAIL = KQM > 16 && KQM % 16 == 4;
+    constexpr int NF = TAIL ? NCB - 1 : NCB;       // blocks on the 16x16x4 shape
     constexpr int RBN = (KQM > 16 && KQM <= 32) ? 2 : 4;   // 16-row blocks per tile
     constexpr int TR = 16 * RBN;                   // rows per tile
     const int lane = threadIdx.x;
@@ -106,10 +114,13 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
         const RowRef rr = lane < nr ? row(r0 + lane) : fallback;
         const double scale = lane < nr ? rr.scale : 0.0;
         v4d acc[RBN][NCB];
+        double acct[RBN];                          // the 4-column block (TAIL)
 #pragma unroll
-        for (int rb = 0; rb < RBN; ++rb)
+        for (int rb = 0; rb < RBN; ++rb) {
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+            acct[rb] = 0.0;
+        }
         // A fragment (rb, t) of a panel is X(16 rb + i, a0 + 4 t + s) in lane
         // i + 16 s: the lane reads row 16 rb + lane % 16 itself, whose start
         // and type it takes from the row's owner lane once per tile.
@@ -178,12 +189,14 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
                 }
             }
         };
+        // column of B this lane holds in block cb (the 4x4x4 tail: lane % 4)
+        auto bcol = [&](int cb) { return (TAIL && cb == NF) ? 16 * NF + lane % 4 : 16 * cb + lane % 16; };
         auto load_b = [&](int a0, double (&bq)[NCB][4]) {
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    bq[cb][t] = V[min(a0 + kcol(t), c - 1) * kq + min(16 * cb + lane % 16, kq - 1)];
+                    bq[cb][t] = V[min(a0 + kcol(t), c - 1) * kq + min(bcol(cb), kq - 1)];
         };
         // the products of one panel: its B fragments are loaded here (from
         // cache), after the loads already in flight, and their rows past c and
@@ -196,14 +209,17 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
             for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    bf[cb][t] *= (a0 + kcol(t) < c && 16 * cb + lane % 16 < kq) ? 1.0 : 0.0;
+                    bf[cb][t] *= (a0 + kcol(t) < c && bcol(cb) < kq) ? 1.0 : 0.0;
 #pragma unroll
             for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
+                for (int t = 0; t < 4; ++t) {
 #pragma unroll
-                    for (int cb = 0; cb < NCB; ++cb)
+                    for (int cb = 0; cb < NF; ++cb)
                         acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[rb][t], bf[cb][t], acc[rb][cb], 0, 0, 0);
+                    if constexpr (TAIL)
+                        acct[rb] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[rb][t], bf[NF][t], acct[rb], 0, 0, 0);
+                }
         };
         auto panels = [&](auto clamp) {
             if constexpr (KQM <= 32) {
@@ -235,6 +251,17 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
             panels(std::false_type{});
         else
             panels(std::true_type{});
+        if constexpr (TAIL) {
+            // Y(16 rb + 4 v + s, 16 NF + i) for i < 4: in lane 16 s + 4 v + i of
+            // the tail, in register v of lane i + 16 s in the 16 x 16 layout
+#pragma unroll
+            for (int rb = 0; rb < RBN; ++rb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double y = __shfl(acct[rb], (lane & 48) + 4 * v + (lane & 3), 64);
+                    acc[rb][NF][v] = (lane & 15) < 4 ? y : 0.0;
+                }
+        }
         // scale the rows: D(i, j) of a 16 x 16 block sits in register i / 4 of
         // lane j + 16 (i mod 4)
 #pragma unroll
