@@ -272,7 +272,7 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) acc[rb][cb][v] *= sc;
             }
-        // Gram of the tile on the matrix cores
+        // Gram of the tile on the matrix cores (blocks ci <= cj; it is symmetric)
 #pragma unroll
         for (int rb = 0; rb < RBN; ++rb)
 #pragma unroll
@@ -280,7 +280,7 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
 #pragma unroll
                 for (int ci = 0; ci < NCB; ++ci)
 #pragma unroll
-                    for (int cj = 0; cj < NCB; ++cj)
+                    for (int cj = ci; cj < NCB; ++cj)
                         gacc[ci][cj] = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[rb][ci][v], acc[rb][cj][v],
                                                                             gacc[ci][cj], 0, 0, 0);
         wave_sync();
@@ -308,11 +308,14 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
 #pragma unroll
     for (int ci = 0; ci < NCB; ++ci)
 #pragma unroll
-        for (int cj = 0; cj < NCB; ++cj)
+        for (int cj = ci; cj < NCB; ++cj)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int a = 16 * ci + 4 * v + lane / 16, b2 = 16 * cj + lane % 16;
-                if (a < kq && b2 < kq) G[a * kq + b2] = gacc[ci][cj][v];
+                if (a < kq && b2 < kq) {
+                    G[a * kq + b2] = gacc[ci][cj][v];
+                    if (cj != ci) G[b2 * kq + a] = gacc[ci][cj][v];   // the mirror block
+                }
             }
 }
 
