@@ -88,6 +88,11 @@ def _bind(lib):
     lib.zo_block_rows.restype = _i64
     lib.zo_xi_rank.argtypes = [_pd, _i64, _dbl]
     lib.zo_xi_rank.restype = _i64
+    lib.zo_direct_batch.argtypes = [_pd, _i64, _i64, _i32, _pi64, _pi64, _pi32, _dbl, _pd, _pi64,
+                                    _pd, _pi64, _pd, _pi64, _pi32]
+    lib.zo_direct_batch.restype = ctypes.c_int
+    lib.zo_set_threads.argtypes = [ctypes.c_int]
+    lib.zo_set_threads.restype = None
     lib.zo_max_threads.argtypes = []
     lib.zo_max_threads.restype = ctypes.c_int
     return lib
@@ -265,9 +270,11 @@ def query(st: Store, t_s: int, t_e: int, kq: int, lib=None):
     return U, s, V, int(kout[0])
 
 
-def query_batch(st: Store, ts, te, kq, lib=None):
+def query_batch(st: Store, ts, te, kq, lib=None, with_u: bool = True):
     """Many queries, parallel over queries (OpenMP).  Returns a list of
-    (U, s, V, k_out) tuples, one per query."""
+    (U, s, V, k_out) tuples, one per query.  with_u=False skips the
+    block-diagonal product of Eq. (9) (U is then None): Sigma and V of very
+    tall ranges without their n x k_q left factors."""
     lib = lib or load()
     ts = np.ascontiguousarray(ts, np.int64)
     te = np.ascontiguousarray(te, np.int64)
@@ -281,18 +288,18 @@ def query_batch(st: Store, ts, te, kq, lib=None):
         uoff[1:] = np.cumsum(n * kq)[:-1]
         voff[1:] = np.cumsum(np.full(nq, st.c) * kq)[:-1]
         soff[1:] = np.cumsum(kq)[:-1]
-    U = np.zeros(int((n * kq).sum()))
+    U = np.zeros(int((n * kq).sum()) if with_u else 1)
     V = np.zeros(int(st.c * kq.sum()))
     s = np.zeros(int(kq.sum()))
     kout = np.zeros(nq, np.int32)
     bad = lib.zo_query_batch(_p(st.U), _p(st.S), _p(st.V), st.t, st.c, st.b, st.k, nq, _p(ts),
-                             _p(te), _p(kq), st.rank_tol, st.xi, _p(U), _p(uoff), _p(s), _p(soff),
-                             _p(V), _p(voff), _p(kout))
+                             _p(te), _p(kq), st.rank_tol, st.xi, _p(U) if with_u else None,
+                             _p(uoff), _p(s), _p(soff), _p(V), _p(voff), _p(kout))
     if bad:
         raise OracleError("Jacobi did not converge in %d queries" % bad)
     res = []
     for q in range(nq):
-        res.append((U[uoff[q]:uoff[q] + n[q] * kq[q]].reshape(n[q], kq[q]),
+        res.append((U[uoff[q]:uoff[q] + n[q] * kq[q]].reshape(n[q], kq[q]) if with_u else None,
                     s[soff[q]:soff[q] + kq[q]],
                     V[voff[q]:voff[q] + st.c * kq[q]].reshape(st.c, kq[q]),
                     int(kout[q])))
@@ -327,6 +334,41 @@ def direct(A, t_s: int, t_e: int, kq: int, rank_tol: float = RANK_TOL, lib=None)
     if bad:
         raise OracleError("Jacobi did not converge")
     return U, s, V, int(kout[0])
+
+
+def direct_batch(A, ts, te, kq, rank_tol: float = RANK_TOL, lib=None):
+    """direct() for many ranges of one matrix, parallel over ranges (OpenMP).
+    Returns a list of (U, s, V, k_out) tuples, one per range."""
+    lib = lib or load()
+    A = _f64(A)
+    c = A.shape[1]
+    ts = np.ascontiguousarray(ts, np.int64)
+    te = np.ascontiguousarray(te, np.int64)
+    kq = np.ascontiguousarray(np.broadcast_to(kq, ts.shape), np.int32)
+    nq = len(ts)
+    n = te - ts
+    uoff = np.zeros(nq, np.int64)
+    voff = np.zeros(nq, np.int64)
+    soff = np.zeros(nq, np.int64)
+    if nq:
+        uoff[1:] = np.cumsum(n * kq)[:-1]
+        voff[1:] = np.cumsum(np.full(nq, c) * kq)[:-1]
+        soff[1:] = np.cumsum(kq)[:-1]
+    U = np.zeros(int((n * kq).sum()))
+    V = np.zeros(int(c * kq.sum()))
+    s = np.zeros(int(kq.sum()))
+    kout = np.zeros(nq, np.int32)
+    bad = lib.zo_direct_batch(_p(A), c, c, nq, _p(ts), _p(te), _p(kq), rank_tol, _p(U), _p(uoff),
+                              _p(s), _p(soff), _p(V), _p(voff), _p(kout))
+    if bad:
+        raise OracleError("Jacobi did not converge in %d ranges" % bad)
+    return [(U[uoff[q]:uoff[q] + n[q] * kq[q]].reshape(n[q], kq[q]), s[soff[q]:soff[q] + kq[q]],
+             V[voff[q]:voff[q] + c * kq[q]].reshape(c, kq[q]), int(kout[q])) for q in range(nq)]
+
+
+def set_threads(n: int, lib=None) -> None:
+    """Number of OpenMP threads of the oracle's parallel loops."""
+    (lib or load()).zo_set_threads(int(n))
 
 
 def max_threads(lib=None) -> int:

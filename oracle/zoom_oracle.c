@@ -448,9 +448,14 @@ int zo_query(const double *Uall, const double *S, const double *V, int64_t t, in
     for (int64_t j = 0; j < kq; ++j) so[j] = j < ko ? sr[j] : 0.0;
     for (int64_t row = 0; row < c; ++row)
         for (int64_t j = 0; j < kq; ++j) Vo[row * kq + j] = j < ko ? Vr[row * r + j] : 0.0;
-    /* Alg. 2, the block-diagonal product, Eq. (9): U = [U'_S U'_r(S); U_(S+1) U_r(S+1); ...]. */
+    /* Alg. 2, the block-diagonal product, Eq. (9): U = [U'_S U'_r(S); U_(S+1) U_r(S+1); ...].
+     * Skipped when the caller asks for Sigma and V only (Uo == NULL). */
     int64_t krow = 0, orow = 0;
     for (int64_t p = 0; p < npieces; ++p) {
+        if (!Uo) {
+            if (pc[p].owns) free(pc[p].Ublk);
+            continue;
+        }
         const int64_t m = pc[p].r1 - pc[p].r0;
         const int64_t w = pc[p].rows_m;
         const int64_t off = pc[p].owns ? 0 : pc[p].r0;   /* whole blocks start at r0 = 0 */
@@ -472,8 +477,8 @@ int zo_query(const double *Uall, const double *S, const double *V, int64_t t, in
 }
 
 /* Many queries at once, parallel over queries.  Outputs are concatenated:
- * query q writes U at Uo + uoff[q] (n_q x kq[q]), sigma at so + q*kqmax,
- * V at Vo + voff[q] (c x kq[q]). */
+ * query q writes U at Uo + uoff[q] (n_q x kq[q]), sigma at so + soff[q],
+ * V at Vo + voff[q] (c x kq[q]).  Uo == NULL: Sigma and V only. */
 int zo_query_batch(const double *Uall, const double *S, const double *V, int64_t t, int64_t c,
                    int64_t b, int32_t k, int32_t nq, const int64_t *ts, const int64_t *te,
                    const int32_t *kq, double rank_tol, double xi, double *Uo, const int64_t *uoff,
@@ -483,7 +488,8 @@ int zo_query_batch(const double *Uall, const double *S, const double *V, int64_t
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
     for (int32_t q = 0; q < nq; ++q) {
-        if (zo_query(Uall, S, V, t, c, b, k, ts[q], te[q], kq[q], rank_tol, xi, Uo + uoff[q],
+        if (zo_query(Uall, S, V, t, c, b, k, ts[q], te[q], kq[q], rank_tol, xi,
+                     Uo ? Uo + uoff[q] : NULL,
                      so + soff[q], Vo + voff[q], kout + q) < 0)
             ++bad;
     }
@@ -512,6 +518,34 @@ int zo_direct(const double *A, int64_t c, int64_t lda, int64_t t_s, int64_t t_e,
         for (int64_t j = 0; j < kq; ++j) Vo[row * kq + j] = j < ko ? Vv[row * r + j] : 0.0;
     free(U); free(s); free(Vv);
     return sw < 0 ? -1 : 0;
+}
+
+/* Many direct SVDs at once (Problem 1 for each range), parallel over ranges;
+ * outputs laid out as in zo_query_batch. */
+int zo_direct_batch(const double *A, int64_t c, int64_t lda, int32_t nq, const int64_t *ts,
+                    const int64_t *te, const int32_t *kq, double rank_tol, double *Uo,
+                    const int64_t *uoff, double *so, const int64_t *soff, double *Vo,
+                    const int64_t *voff, int32_t *kout)
+{
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+    for (int32_t q = 0; q < nq; ++q) {
+        if (zo_direct(A, c, lda, ts[q], te[q], kq[q], rank_tol, Uo + uoff[q], so + soff[q],
+                      Vo + voff[q], kout + q) < 0)
+            ++bad;
+    }
+    return bad;
+}
+
+/* Threads of the parallel loops above (timing of a one-thread baseline). */
+void zo_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 int zo_max_threads(void)

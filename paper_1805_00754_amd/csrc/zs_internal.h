@@ -111,12 +111,31 @@ __host__ __device__ inline int prod_ld(int k)
     return (k + 15) & ~15;
 }
 
+// Whole pieces per projection chunk of a query's stack (stack_project, coef).
+constexpr int kQueryChunkPieces = 32;
+
+// Projection chunk j of a query whose pieces start at piece0 and whose Y rows
+// start at y0 (slot: the chunk's G_Y partial-sum slot).
+__host__ __device__ inline StackChunk make_stack_chunk(int32_t j, int32_t np, int32_t k, int32_t kq,
+                                                      int64_t y0, int64_t piece0, int32_t q,
+                                                      int32_t slot)
+{
+    StackChunk ch;
+    const int64_t p = (int64_t)j * kQueryChunkPieces;
+    ch.y_off = y0 + p * k * kq;
+    ch.piece0 = (int32_t)(piece0 + p);
+    ch.npieces = (int32_t)(np - p < kQueryChunkPieces ? np - p : kQueryChunkPieces);
+    ch.prob = q;
+    ch.slot = slot;
+    ch.kk = kq;
+    ch.pad = 0;
+    return ch;
+}
+
 // ---------------------------------------------------------------- launches
 // All launches are asynchronous on `stream` and return the launch status.
 hipError_t launch_gram(const void *X, int x_type, int64_t ld, int c, const Chunk *chunks,
                        int nchunks, double *Gpart, hipStream_t stream);
-hipError_t launch_eig(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
-                      const double *const *msrc, double *Vk, int *conv_flag, hipStream_t stream);
 hipError_t launch_eig_tri(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
                           const double *const *msrc, double *Vk, hipStream_t stream);
 hipError_t launch_project(const void *X, int x_type, int64_t ld, int c, const Chunk *chunks,

@@ -44,7 +44,7 @@ zs_status fail(zs_status s, const char *fmt, ...)
 // ------------------------------------------------------------------ timing
 std::mutex g_tmu;
 bool g_timing = false;
-thread_local bool t_capturing = false;   // a graph capture is in progress on this thread
+thread_local bool t_untimed = false;   // launches of this thread are not timed (graph capture)
 struct TimedLaunch {
     std::string name;
     hipEvent_t a, b;
@@ -160,7 +160,7 @@ struct zs_store {
 namespace zs {
 void timing_begin(const char *name, hipStream_t stream)
 {
-    if (!g_timing || t_capturing) return;
+    if (!g_timing || t_untimed) return;
     hipEvent_t a;
     if (hipEventCreate(&a) != hipSuccess) return;
     (void)hipEventRecord(a, stream);
@@ -169,7 +169,7 @@ void timing_begin(const char *name, hipStream_t stream)
 
 void timing_end(const char *name, hipStream_t stream)
 {
-    if (!g_timing || t_capturing) return;
+    if (!g_timing || t_untimed) return;
     auto it = t_open.find(name);
     if (it == t_open.end()) return;
     hipEvent_t b;
@@ -183,24 +183,17 @@ void timing_end(const char *name, hipStream_t stream)
 
 namespace {
 
-// First-stage eigen-solver: tridiagonalisation in LDS (default, c <= 128) or
-// one-sided Jacobi (ZS_EIG=jacobi, c <= 128), both on the same Gram terms; for
-// c > 128 the tridiagonal solver with its matrix in global scratch (`big`,
-// eig_big_scratch_doubles(c) doubles per problem).
-hipError_t first_stage_eig(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
-                           const double *const *msrc, double *Vk, DevBuf &big, int *conv,
-                           hipStream_t stream)
+// First-stage eigen-solver: tridiagonalisation with the matrix in registers
+// (c <= 128) or in global scratch (c > 128: `big` holds big_doubles(c, nprob)).
+size_t big_doubles(int64_t c, int64_t nprob)
 {
-    if (c > kMaxC) {
-        hipError_t e = big.ensure(sizeof(double) * eig_big_scratch_doubles(c) * (size_t)nprob);
-        if (e != hipSuccess) return e;
-        return launch_eig_big(c, k, probs, nprob, gsrc, msrc, big.as<double>(), Vk, stream);
-    }
-    static const bool use_jacobi = [] {
-        const char *v = getenv("ZS_EIG");
-        return v && std::strcmp(v, "jacobi") == 0;
-    }();
-    if (use_jacobi) return launch_eig(c, k, probs, nprob, gsrc, msrc, Vk, conv, stream);
+    return c > kMaxC ? eig_big_scratch_doubles((int)c) * (size_t)nprob : 0;
+}
+
+hipError_t first_stage_eig(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
+                           const double *const *msrc, double *Vk, double *big, hipStream_t stream)
+{
+    if (c > kMaxC) return launch_eig_big(c, k, probs, nprob, gsrc, msrc, big, Vk, stream);
     return launch_eig_tri(c, k, probs, nprob, gsrc, msrc, Vk, stream);
 }
 
@@ -208,7 +201,6 @@ hipError_t first_stage_eig(int c, int k, const Prob *probs, int nprob, const dou
 constexpr int kStoreChunkRows = 512;       // Gram chunk rows, c <= 128
 constexpr int kStoreChunkRowsWide = 2048;  // c > 128: at least a whole block
 constexpr int kProjChunkRows = 256;   // rows per projection wave (storage phase)
-constexpr int kQueryChunkPieces = 32;   // whole pieces per projection work-group
 
 // Upload `bytes` of host data through the workspace's pinned staging buffer.
 zs_status upload(Workspace &w, const void *src, size_t bytes, hipStream_t stream)
@@ -251,6 +243,92 @@ struct QueryPlan {
     void *U = nullptr;
 };
 
+// The O(1) part of the plan of one query (Alg. 3 index math, host side).
+// Pieces are the touched blocks S..E; boundary blocks cut by the range go
+// through the Partial-SVD.  Whole blocks form one contiguous run whose Gram
+// comes from the Gram tree.  Fills the query's descriptor `d` and problem
+// `pr`, reports its Partial-SVD pieces, their stack-row slots and its tree
+// nodes to `sink`, and advances `slot` past its projection chunks (chunk j
+// is make_stack_chunk(j, ...)).  Every quantity depends only on this query
+// and on where the batch puts it (piece0, y0, c0, the first slot).
+template <class Sink>
+void plan_one(const zs_store *st, int32_t q, int64_t ts, int64_t te, int32_t kq, int64_t u_off,
+              int64_t ldu, double *s_dst, void *v_dst, int64_t ldv, int32_t *k_dst,
+              int64_t piece0, int64_t y0, int64_t c0, int32_t &slot, Sink &sink, QueryDesc &d,
+              Prob &pr)
+{
+    (void)q;
+    const int64_t b = st->b;
+    const int64_t S_ = ts / b, E_ = (te - 1) / b;
+    const int64_t lo = ts - S_ * b, hi = te - E_ * b;
+    const int64_t np = E_ - S_ + 1;
+    std::memset(&d, 0, sizeof d);
+    d.S = S_;
+    d.ts = ts;
+    d.piece0 = piece0;
+    d.y0 = y0;
+    d.c0 = c0;
+    d.u_off = u_off;
+    d.ldu = ldu;
+    d.np = (int32_t)np;
+    d.lo = (int32_t)lo;
+    d.hi = (int32_t)hi;
+    d.kq = kq;
+    d.t0 = sink.npidx();
+    // first piece: rows [lo, np == 1 ? hi : rows_S); last piece (np > 1): [0, hi)
+    const bool first_partial = lo != 0 || (np == 1 ? hi != st->block_rows(S_) : false);
+    const bool last_partial = np > 1 && hi != st->block_rows(E_);
+    d.first_partial = first_partial ? 1 : 0;
+    std::memset(&pr, 0, sizeof pr);
+    pr.m0 = sink.nmsrc();
+    if (first_partial) {
+        sink.add_msrc(sink.npidx());
+        sink.add_pidx((int32_t)piece0);
+    }
+    if (last_partial) {
+        sink.add_msrc(sink.npidx());
+        sink.add_pidx((int32_t)(piece0 + np - 1));
+    }
+    pr.nm = sink.nmsrc() - pr.m0;
+    // Whole blocks [whole_a, whole_e) are contiguous: cover them with tree nodes.
+    const int64_t whole_a = S_ + (first_partial ? 1 : 0);
+    const int64_t whole_e = E_ + 1 - (last_partial ? 1 : 0);
+    pr.g0 = sink.ngsrc();
+    if (whole_a < whole_e) {
+        int64_t l = whole_a + st->n2, r = whole_e + st->n2;
+        while (l < r) {
+            if (l & 1) sink.add_gsrc(l++);
+            if (r & 1) sink.add_gsrc(--r);
+            l >>= 1;
+            r >>= 1;
+        }
+    }
+    pr.ng = sink.ngsrc() - pr.g0;
+    pr.y0 = slot;
+    slot += (int32_t)((np + kQueryChunkPieces - 1) / kQueryChunkPieces);
+    pr.ny = slot - pr.y0;
+    pr.kk = kq;
+    pr.v_dst = v_dst;
+    pr.v_f32 = st->f32;
+    pr.v_rs = ldv;
+    pr.v_cs = 1;
+    pr.s_dst = s_dst;
+    pr.k_dst = k_dst;
+}
+
+// Sink of plan_one for a batch: growable host arrays.
+struct VecSink {
+    std::vector<int32_t> pidx;          // pieces that need a Partial-SVD
+    std::vector<int32_t> msrc;          // Partial-SVD slots of the problems' stack rows
+    std::vector<int64_t> gsrc;          // tree node indices
+    int32_t npidx() const { return (int32_t)pidx.size(); }
+    int32_t nmsrc() const { return (int32_t)msrc.size(); }
+    int32_t ngsrc() const { return (int32_t)gsrc.size(); }
+    void add_pidx(int32_t v) { pidx.push_back(v); }
+    void add_msrc(int32_t v) { msrc.push_back(v); }
+    void add_gsrc(int64_t v) { gsrc.push_back(v); }
+};
+
 // Plans a batch (Alg. 3 index math, host side), sizes workspace `w` and uploads
 // the descriptors to it: through the pinned staging buffer on `stream`, or
 // synchronously when `sync_upload` (graphs, whose descriptors must stay put).
@@ -260,99 +338,35 @@ zs_status query_plan(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
                      const int64_t *ldv, int32_t *k_out, hipStream_t stream, Workspace *w,
                      bool sync_upload, QueryPlan &pl)
 {
-    const int64_t c = st->c, b = st->b;
+    const int64_t c = st->c;
     const int32_t k = st->k;
     // ---- plan (Alg. 3 index math for every query) ---------------------------------
-    // Pieces are the touched blocks; boundary blocks cut by the range go through
-    // the Partial-SVD.  Whole blocks form one contiguous run [a, e) whose Gram
-    // comes from the Gram tree.  The host computes the O(1) part of each query
-    // (its descriptor, partial slots, projection chunks, tree nodes); the
-    // pieces themselves are expanded on the device.  Every per-query quantity
-    // depends only on that query.
+    // The host computes the O(1) part of each query (plan_one); the pieces
+    // themselves are expanded on the device.
     std::vector<QueryDesc> qds(nq);
-    std::vector<int32_t> pidx;          // pieces that need a Partial-SVD
+    VecSink sink;                       // Partial-SVD pieces and slots, tree nodes
     std::vector<StackChunk> chunks;
     std::vector<Prob> probs(nq);
-    std::vector<int64_t> gsrc_off;      // tree node indices (converted to pointers below)
-    std::vector<int32_t> msrc_idx;      // Partial-SVD slots
     int64_t y_elems = 0, c_elems = 0, npieces64 = 0;
     int32_t slot = 0, kq_max = 1, max_np = 0;
     const int kp = prod_ld(k);
     for (int32_t q = 0; q < nq; ++q) {
         kq_max = std::max(kq_max, kq[q]);
-        const int64_t S_ = ts[q] / b, E_ = (te[q] - 1) / b;
-        const int64_t lo = ts[q] - S_ * b, hi = te[q] - E_ * b;
-        const int64_t np = E_ - S_ + 1;
-        max_np = std::max<int32_t>(max_np, (int32_t)np);
-        QueryDesc &d = qds[q];
-        std::memset(&d, 0, sizeof d);
-        d.S = S_;
-        d.ts = ts[q];
-        d.piece0 = npieces64;
-        d.y0 = y_elems;
-        d.c0 = c_elems;
-        d.u_off = u_off[q];
-        d.ldu = ldu[q];
-        d.np = (int32_t)np;
-        d.lo = (int32_t)lo;
-        d.hi = (int32_t)hi;
-        d.kq = kq[q];
-        d.t0 = (int32_t)pidx.size();
-        // first piece: rows [lo, np == 1 ? hi : rows_S); last piece (np > 1): [0, hi)
-        const bool first_partial = lo != 0 || (np == 1 ? hi != st->block_rows(S_) : false);
-        const bool last_partial = np > 1 && hi != st->block_rows(E_);
-        d.first_partial = first_partial ? 1 : 0;
-        Prob pr;
-        std::memset(&pr, 0, sizeof pr);
-        pr.m0 = (int32_t)msrc_idx.size();
-        if (first_partial) {
-            msrc_idx.push_back((int32_t)pidx.size());
-            pidx.push_back((int32_t)npieces64);
-        }
-        if (last_partial) {
-            msrc_idx.push_back((int32_t)pidx.size());
-            pidx.push_back((int32_t)(npieces64 + np - 1));
-        }
-        pr.nm = (int32_t)msrc_idx.size() - pr.m0;
-        // Whole blocks [whole_a, whole_e) are contiguous: cover them with tree nodes.
-        const int64_t whole_a = S_ + (first_partial ? 1 : 0);
-        const int64_t whole_e = E_ + 1 - (last_partial ? 1 : 0);
-        pr.g0 = (int32_t)gsrc_off.size();
-        if (whole_a < whole_e) {
-            int64_t l = whole_a + st->n2, r = whole_e + st->n2;
-            while (l < r) {
-                if (l & 1) gsrc_off.push_back(l++);
-                if (r & 1) gsrc_off.push_back(--r);
-                l >>= 1;
-                r >>= 1;
-            }
-        }
-        pr.ng = (int32_t)gsrc_off.size() - pr.g0;
-        pr.y0 = slot;
-        for (int64_t p = 0; p < np; p += kQueryChunkPieces) {
-            StackChunk ch;
-            std::memset(&ch, 0, sizeof ch);
-            ch.y_off = y_elems + p * k * kq[q];
-            ch.piece0 = (int32_t)(npieces64 + p);
-            ch.npieces = (int32_t)std::min<int64_t>(kQueryChunkPieces, np - p);
-            ch.prob = q;
-            ch.slot = slot++;
-            ch.kk = kq[q];
-            chunks.push_back(ch);
-        }
-        pr.ny = slot - pr.y0;
-        pr.kk = kq[q];
-        pr.v_dst = static_cast<char *>(V) + v_off[q] * (int64_t)st->esize();
-        pr.v_f32 = st->f32;
-        pr.v_rs = ldv[q];
-        pr.v_cs = 1;
-        pr.s_dst = S + s_off[q];
-        pr.k_dst = k_out + q;
-        probs[q] = pr;
-        y_elems += np * k * kq[q];
-        c_elems += np * kp * kq[q];
+        const int32_t slot0 = slot;
+        plan_one(st, q, ts[q], te[q], kq[q], u_off[q], ldu[q], S + s_off[q],
+                 static_cast<char *>(V) + v_off[q] * (int64_t)st->esize(), ldv[q], k_out + q,
+                 npieces64, y_elems, c_elems, slot, sink, qds[q], probs[q]);
+        const int32_t np = qds[q].np;
+        for (int32_t j = 0; j < slot - slot0; ++j)
+            chunks.push_back(make_stack_chunk(j, np, k, kq[q], y_elems, npieces64, q, slot0 + j));
+        max_np = std::max(max_np, np);
+        y_elems += (int64_t)np * k * kq[q];
+        c_elems += (int64_t)np * kp * kq[q];
         npieces64 += np;
     }
+    std::vector<int32_t> &pidx = sink.pidx;
+    std::vector<int64_t> &gsrc_off = sink.gsrc;
+    std::vector<int32_t> &msrc_idx = sink.msrc;
     // first position of each block in the block-major order of the pieces
     std::vector<int32_t> boff(st->nb + 1, 0);
     for (int32_t q = 0; q < nq; ++q) {
@@ -417,41 +431,67 @@ zs_status query_plan(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
     return ZS_OK;
 }
 
-// Enqueues the kernels of a planned batch on `stream` (no host synchronisation
-// and, once the workspace is sized, no allocation, so the sequence can be
-// captured into a graph).
-zs_status query_launch(zs_store *st, const QueryPlan &pl, Workspace *w, hipStream_t stream)
+// Device buffers of one planned batch: descriptors and scratch.
+struct QueryBufs {
+    const StackChunk *chunks;
+    const Prob *probs;
+    const QueryDesc *qds;
+    const int32_t *pidx, *boff;        // boff null: perm is already in place
+    const double *const *gsrc;
+    const double *const *msrc;
+    Piece *P;
+    int32_t *perm, *bcount;
+    double *Mp, *T, *Vk, *Y, *GY, *F, *C, *big;
+};
+
+// Enqueues the kernels of a planned batch on `stream`: no host
+// synchronisation and no allocation, so the sequence can be captured into a
+// graph.
+zs_status query_kernels(zs_store *st, const QueryPlan &pl, const QueryBufs &qb, hipStream_t stream)
 {
     const int64_t c = st->c;
     const int32_t k = st->k;
-    char *d = w->desc.as<char>();
-    const StackChunk *d_chunks = (const StackChunk *)(d + pl.o_chunks);
-    const Prob *d_probs = (const Prob *)(d + pl.o_probs);
-    const QueryDesc *d_qds = (const QueryDesc *)(d + pl.o_qds);
-    const Piece *d_pieces = w->P.as<Piece>();
-    const int32_t *d_boff = (const int32_t *)(d + pl.o_boff);
-    const int32_t *d_pidx = (const int32_t *)(d + pl.o_pidx);
-    const double *const *d_gsrc = (const double *const *)(d + pl.o_gsrc);
-    const double *const *d_msrc = (const double *const *)(d + pl.o_msrc);
-    double *Mp = w->Mp.as<double>();
     const StoreView sv = st->view();
-    HIP_TRY(launch_expand_pieces(sv, d_qds, pl.nq, pl.max_np, w->P.as<Piece>(), stream));
-    HIP_TRY(launch_partial(sv, d_pieces, d_pidx, pl.npartial, Mp, w->T.as<double>(), st->rank_tol(),
-                           st->xi, st->conv, stream));
-    HIP_TRY(first_stage_eig((int)c, k, d_probs, pl.nq, d_gsrc, d_msrc, w->Vk.as<double>(), w->big,
-                            st->conv, stream));
-    HIP_TRY(launch_stack_project(sv, d_pieces, Mp, d_chunks, pl.nchunks, pl.kq_max,
-                                 w->Vk.as<double>(), w->Y.as<double>(), w->GY.as<double>(), stream));
-    HIP_TRY(launch_finalize((int)c, k, d_probs, pl.nq, pl.kq_max, w->GY.as<double>(),
-                            w->Vk.as<double>(), w->F.as<double>(), st->rank_tol(), d_gsrc, d_msrc,
-                            st->xi, st->conv, stream));
-    HIP_TRY(launch_coef(k, pl.kq_max, d_pieces, d_chunks, pl.nchunks, w->Y.as<double>(),
-                        w->F.as<double>(), w->T.as<double>(), w->C.as<double>(), stream));
-    HIP_TRY(launch_order_pieces(d_pieces, pl.npieces, st->nb, d_boff, w->bcount.as<int32_t>(),
-                                w->perm.as<int32_t>(), stream));
-    HIP_TRY(launch_blockprod(sv, d_pieces, w->perm.as<int32_t>(), pl.npieces, w->C.as<double>(), pl.U,
-                             pl.contiguous, stream));
+    HIP_TRY(launch_expand_pieces(sv, qb.qds, pl.nq, pl.max_np, qb.P, stream));
+    HIP_TRY(launch_partial(sv, qb.P, qb.pidx, pl.npartial, qb.Mp, qb.T, st->rank_tol(), st->xi,
+                           st->conv, stream));
+    HIP_TRY(first_stage_eig((int)c, k, qb.probs, pl.nq, qb.gsrc, qb.msrc, qb.Vk, qb.big, stream));
+    HIP_TRY(launch_stack_project(sv, qb.P, qb.Mp, qb.chunks, pl.nchunks, pl.kq_max, qb.Vk, qb.Y,
+                                 qb.GY, stream));
+    HIP_TRY(launch_finalize((int)c, k, qb.probs, pl.nq, pl.kq_max, qb.GY, qb.Vk, qb.F,
+                            st->rank_tol(), qb.gsrc, qb.msrc, st->xi, st->conv, stream));
+    HIP_TRY(launch_coef(k, pl.kq_max, qb.P, qb.chunks, pl.nchunks, qb.Y, qb.F, qb.T, qb.C, stream));
+    if (qb.boff)
+        HIP_TRY(launch_order_pieces(qb.P, pl.npieces, st->nb, qb.boff, qb.bcount, qb.perm, stream));
+    HIP_TRY(launch_blockprod(sv, qb.P, qb.perm, pl.npieces, qb.C, pl.U, pl.contiguous, stream));
     return ZS_OK;
+}
+
+// The kernels of a batch planned into workspace `w`.
+zs_status query_launch(zs_store *st, const QueryPlan &pl, Workspace *w, hipStream_t stream)
+{
+    HIP_TRY(w->big.ensure(sizeof(double) * std::max<size_t>(1, big_doubles(st->c, pl.nq))));
+    char *d = w->desc.as<char>();
+    QueryBufs qb;
+    qb.chunks = (const StackChunk *)(d + pl.o_chunks);
+    qb.probs = (const Prob *)(d + pl.o_probs);
+    qb.qds = (const QueryDesc *)(d + pl.o_qds);
+    qb.pidx = (const int32_t *)(d + pl.o_pidx);
+    qb.boff = (const int32_t *)(d + pl.o_boff);
+    qb.gsrc = (const double *const *)(d + pl.o_gsrc);
+    qb.msrc = (const double *const *)(d + pl.o_msrc);
+    qb.P = w->P.as<Piece>();
+    qb.perm = w->perm.as<int32_t>();
+    qb.bcount = w->bcount.as<int32_t>();
+    qb.Mp = w->Mp.as<double>();
+    qb.T = w->T.as<double>();
+    qb.Vk = w->Vk.as<double>();
+    qb.Y = w->Y.as<double>();
+    qb.GY = w->GY.as<double>();
+    qb.F = w->F.as<double>();
+    qb.C = w->C.as<double>();
+    qb.big = w->big.as<double>();
+    return query_kernels(st, pl, qb, stream);
 }
 
 zs_status query_impl(zs_store *st, int32_t nq, const int64_t *ts, const int64_t *te,
@@ -656,9 +696,10 @@ zs_status zs_store_blocks_xi(const void *A, int64_t t, int64_t c, int64_t lda, z
     const Chunk *d_leaf_chunks = (const Chunk *)(desc.as<char>() + o_leaf);
     const Chunk *d_pchunks = (const Chunk *)(desc.as<char>() + o_pchunks);
     const int x_type = a_type == ZS_F32 ? kElemF32 : a_type == ZS_BF16 ? kElemBF16 : kElemF64;
+    ST_TRY2(Big.ensure(sizeof(double) * std::max<size_t>(1, big_doubles(c, nb))));
     ST_TRY2(launch_gram(A, x_type, lda, (int)c, d_chunks, nchunks, Gpart.as<double>(), stream));
-    ST_TRY2(first_stage_eig((int)c, k, d_probs, (int)nb, d_gsrc, nullptr, Vk.as<double>(), Big,
-                            st->conv, stream));
+    ST_TRY2(first_stage_eig((int)c, k, d_probs, (int)nb, d_gsrc, nullptr, Vk.as<double>(),
+                            Big.as<double>(), stream));
     ST_TRY2(launch_project(A, x_type, lda, (int)c, d_pchunks, npchunks, k, Vk.as<double>(), Y,
                            GY.as<double>(), stream));
     ST_TRY2(launch_finalize((int)c, k, d_probs, (int)nb, k, GY.as<double>(), Vk.as<double>(),
@@ -1002,7 +1043,7 @@ zs_status zs_query_batch_graph(const zs_store *cst, int32_t nq, const int64_t *t
     GR_TRY(hipStreamSynchronize(stream));
     hipStream_t cs = nullptr;
     GR_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    t_capturing = true;
+    t_untimed = true;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         s = query_launch(g->st, g->pl, g->w, cs);
@@ -1011,7 +1052,7 @@ zs_status zs_query_batch_graph(const zs_store *cst, int32_t nq, const int64_t *t
         g->graph = graph;
         if (e == hipSuccess) e = e2;
     }
-    t_capturing = false;
+    t_untimed = false;
     (void)hipStreamDestroy(cs);
     if (s != ZS_OK) return bail(s);
     GR_TRY(e);

@@ -61,3 +61,30 @@ def subspace_errs(U_hat, U_ref, s_ref, tol):
         st = sin_theta(U_hat[:, : j + 1], U_ref[:, : j + 1])
         worst = max(worst, st / (tol / g))
     return worst
+
+
+def joint_sign_errs(U_hat, V_hat, U_ref, V_ref, s_ref, tol, min_angle=0.1):
+    """The SVD fixes each pair (u_j, v_j) only up to a JOINT sign: flipping
+    u_j alone changes U Sigma V^T (Sec. 2.1).  For every isolated j (relative
+    gaps to both neighbours >= 1e-8, and tol / gap <= min_angle so that the
+    subspace tests pin each vector to within that angle), the overlaps
+    u_hat_j . u_j and v_hat_j . v_j must have the same sign.  Returns the
+    number of pairs that violate it."""
+    s_ref = np.asarray(s_ref, float)
+    r = int((s_ref > 0).sum())
+    if r == 0:
+        return 0
+    s1 = s_ref[0]
+    bad = 0
+    for j in range(r):
+        nxt = s_ref[j + 1] if j + 1 < len(s_ref) else 0.0
+        g = (s_ref[j] - nxt) / s1
+        if j > 0:
+            g = min(g, (s_ref[j - 1] - s_ref[j]) / s1)
+        if g < 1e-8 or tol / g > min_angle:
+            continue
+        pu = float(U_hat[:, j] @ U_ref[:, j])
+        pv = float(V_hat[:, j] @ V_ref[:, j])
+        if not (pu * pv > 0.0):
+            bad += 1
+    return bad

@@ -58,14 +58,37 @@ def test_fullsize_store_sample(full):
                     "block %d" % i)
 
 
-def test_fullsize_batch_sample(full):
+def test_fullsize_batch_all_sigma_v(full):
+    """Sigma, V and k_out of every query of the batch against the oracle's
+    query phase on the downloaded store (Alg. 2; U is checked on a sample)."""
     A, cfg, st, out, ts, te, _, ost = full
-    for q in (0, QUERIES // 2, QUERIES - 1):
+    say("full size: oracle sigma and V of all %d queries" % QUERIES)
+    refs = oracle.query_batch(ost, ts, te, cfg["k"], with_u=False)
+    S_all = out.S.cpu().numpy()
+    V_all = out.V.cpu().numpy()
+    k_all = out.k_out.cpu().numpy()
+    for q in range(QUERIES):
+        so, vo = int(out.s_off[q]), int(out.v_off[q])
+        kq = int(out.k_q[q])
+        got = (None, S_all[so:so + kq], V_all[vo:vo + st.c * kq].reshape(st.c, kq), int(k_all[q]))
+        compare_svd(got, refs[q], TOL_FP64, st.c, "query %d [%d,%d)" % (q, ts[q], te[q]))
+
+
+def test_fullsize_batch_sample(full):
+    """U of a seeded sample of 32 queries (Eq. (9)), with the joint signs of
+    (u_j, v_j); three of them also alone, bitwise equal to the batch."""
+    A, cfg, st, out, ts, te, _, ost = full
+    rng = synth.rng_for(1806)
+    sample = sorted(set(rng.choice(QUERIES, size=29, replace=False).tolist())
+                    | {0, QUERIES // 2, QUERIES - 1})
+    refs = oracle.query_batch(ost, ts[sample], te[sample], cfg["k"])
+    for ref, q in zip(refs, sample):
         Ub, Sb, Vb, kb = out.result(q)
         got = (Ub.cpu().numpy(), Sb.cpu().numpy(), Vb.cpu().numpy(), int(kb.item()))
-        ref = oracle.query(ost, int(ts[q]), int(te[q]), cfg["k"])
         say("full size: query", q, int(ts[q]), int(te[q]))
         compare_svd(got, ref, TOL_FP64, st.c, "query %d [%d,%d)" % (q, ts[q], te[q]))
+        if q not in (0, QUERIES // 2, QUERIES - 1):
+            continue
         # the same query alone gives the batch's bits
         U1, S1, V1, k1 = zs.zs_query(st, int(ts[q]), int(te[q]), cfg["k"])
         torch.cuda.synchronize()

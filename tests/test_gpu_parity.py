@@ -118,7 +118,9 @@ def test_query_parity_other_widths(t, c, b, k):
 # c above 128: the eigen-solver keeps its matrix in global scratch and the
 # leaf Grams go through the Gram kernel.
 LARGE_C = [(3_000, 200, 600, 24), (4_000, 256, 1000, 32), (2_600, 512, 1300, 48),
-           (2_100, 1024, 1050, 64)]
+           (2_100, 1024, 1050, 64),
+           # short last blocks (300 rows) at c = 256 and c = 1024
+           (3_300, 256, 1000, 32), (2_300, 1024, 1000, 64)]
 
 
 @pytest.mark.parametrize("t,c,b,k", LARGE_C)
@@ -134,6 +136,25 @@ def test_large_c_store_and_query_parity(t, c, b, k):
         got = gpu_query(st, int(ts[q]), int(te[q]), kq)
         ref = oracle.query(gst, int(ts[q]), int(te[q]), kq)
         compare_svd(got, ref, TOL_FP64, c, "c %d [%d,%d) kq %d" % (c, ts[q], te[q], kq))
+
+
+# Block sizes of the paper's sensitivity study (Sec. 4.5, Fig. 6) beyond the
+# default 10^3: 10^4 and 10^5 rows per block, each with a short last block.
+@pytest.mark.parametrize("t,c,b,k", [(25_000, 128, 10_000, 20), (230_000, 128, 100_000, 20)])
+def test_large_block_sizes(t, c, b, k):
+    ser = synth.sinusoid_mixture(t, c, sources=16, seed=61 + b // 1000, noise="ar1",
+                                 noise_sigma=0.05)
+    st, (U, S, V, kk) = check_store(ser.A, b, k, "b %d" % b)
+    gst = oracle.store_from_arrays(st.t, st.c, st.b, st.k, U, S, V, kk)
+    rng = synth.rng_for(b)
+    ts, te = synth.queries_loguniform(rng, t, 4, 1e3, t)
+    for q in range(4):
+        kq = [k, 7][q % 2]
+        say("b %d query" % b, int(ts[q]), int(te[q]), kq)
+        got = gpu_query(st, int(ts[q]), int(te[q]), kq)
+        ref = oracle.query(gst, int(ts[q]), int(te[q]), kq)
+        compare_svd(got, ref, TOL_FP64, c, "b %d [%d,%d) kq %d" % (b, ts[q], te[q], kq))
+    st.free()
 
 
 def test_query_exact_on_block_low_rank():

@@ -88,3 +88,47 @@ def test_fp64_mode_accepts_float32_input():
     a, b = download_store(st32), download_store(st64)
     for x, y in zip(a, b):
         np.testing.assert_array_equal(x, y)
+
+
+# The wide workload's geometry (c = 1024, k = 64, b = 4096, bf16-valued input
+# with singular values decaying as 0.9^j, a 1,152-row last block) at a reduced
+# t of two full blocks plus the tail.  The same values go in as bfloat16 (BF16
+# mode) and as float32 (FP32 mode), so one oracle store serves both.
+WIDE_T = 2 * 4096 + 1152
+
+
+@pytest.fixture(scope="module")
+def wide():
+    ser, cfg = synth.workload("decay_2m_x1024_bf16", t=WIDE_T)
+    say("wide: oracle store", ser.A.shape)
+    ost = oracle.store(ser.A, cfg["b"], cfg["k"], rank_tol=RANK_TOL_F32)
+    return ser, cfg, ost
+
+
+@pytest.mark.parametrize("name,tdtype,mode", [("bf16", torch.bfloat16, zs.ZS_MODE_BF16),
+                                              ("f32", torch.float32, zs.ZS_MODE_FP32)])
+def test_wide_geometry_parity(wide, name, tdtype, mode):
+    ser, cfg, ost = wide
+    A = ser.A
+    b, k = cfg["b"], cfg["k"]
+    c = A.shape[1]
+    say("wide", name, A.shape, b, k)
+    st = zs.zs_store_blocks(to_dev(A, tdtype), b, k, mode=mode)
+    torch.cuda.synchronize()
+    assert st.nb == 3 and st.block_rows(2) == 1152
+    U, S, V, kk = download_store(st)
+    for i in range(st.nb):
+        r = st.block_rows(i)
+        compare_svd((U[i * b:i * b + r], S[i], V[i], int(kk[i])),
+                    (ost.U[i * b:i * b + r], ost.S[i], ost.V[i], int(ost.k_i[i])),
+                    TOL_FP32, c, "wide %s block %d" % (name, i), **F32_KW)
+    gst = oracle.store_from_arrays(st.t, st.c, st.b, st.k, U, S, V, kk, rank_tol=RANK_TOL_F32)
+    # ranges over the tail, across both block edges, inside one block, and all rows
+    for ts, te, kq in [(0, WIDE_T, k), (1_000, 9_000, k), (4_000, 4_200, 16), (8_200, WIDE_T, 32),
+                       (3_000, 8_500, 8)]:
+        Ug, Sg, Vg, kg = zs.zs_query(st, ts, te, kq)
+        zs.zs_sync_status(st)
+        got = (Ug.double().cpu().numpy(), Sg.cpu().numpy(), Vg.double().cpu().numpy(), int(kg.item()))
+        ref = oracle.query(gst, ts, te, kq)
+        compare_svd(got, ref, TOL_FP32, c, "wide %s [%d,%d) kq %d" % (name, ts, te, kq), **F32_KW)
+    st.free()

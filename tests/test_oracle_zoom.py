@@ -203,6 +203,13 @@ def test_query_batch_matches_single(orc):
         np.testing.assert_array_equal(res[q][1], s)
         np.testing.assert_array_equal(res[q][2], V)
         assert res[q][3] == ko
+    # Sigma and V only: the same values, no left factor
+    res2 = orc.query_batch(st, ts, te, [3, 1, 2, 3, 3], with_u=False)
+    for q in range(len(ts)):
+        assert res2[q][0] is None
+        np.testing.assert_array_equal(res2[q][1], res[q][1])
+        np.testing.assert_array_equal(res2[q][2], res[q][2])
+        assert res2[q][3] == res[q][3]
 
 
 # ------------------------------------------------ planted mistakes are caught
@@ -277,3 +284,25 @@ def test_unmutated_oracle_passes_pin_script(orc, tmp_path):
     script.write_text(PIN_SCRIPT.format(root=ROOT, lib=os.path.join(ROOT, "oracle", "liboracle.so")))
     r = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, timeout=120)
     assert "ALL PINS PASSED" in r.stdout, r.stdout + r.stderr
+
+
+def test_direct_batch_matches_single(orc):
+    rng = np.random.default_rng(19)
+    A = rng.standard_normal((600, 9))
+    ts = np.array([0, 5, 100, 590])
+    te = np.array([600, 9, 420, 600])
+    res = orc.direct_batch(A, ts, te, [4, 2, 9, 3])
+    for q in range(len(ts)):
+        ref = orc.direct(A, int(ts[q]), int(te[q]), [4, 2, 9, 3][q])
+        for x, y in zip(res[q][:3], ref[:3]):
+            np.testing.assert_array_equal(x, y)
+        assert res[q][3] == ref[3]
+    # one thread gives the same bits
+    n0 = orc.max_threads()
+    orc.set_threads(1)
+    try:
+        res1 = orc.direct_batch(A, ts, te, [4, 2, 9, 3])
+    finally:
+        orc.set_threads(n0)
+    for a, b in zip(res, res1):
+        np.testing.assert_array_equal(a[1], b[1])
