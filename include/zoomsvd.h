@@ -141,6 +141,25 @@ zs_status zs_query(const zs_store *st, int64_t t_s, int64_t t_e, int32_t k_q, vo
                    double *S, void *V, int64_t ldv, int32_t *k_out, hipStream_t stream);
 
 /*
+ * zs_query_noalloc -- zs_query for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, outputs (bit for bit) and errors as
+ * zs_query; the call makes no hipMalloc, hipFree, pinned-host allocation or
+ * host-to-device copy.  Its intermediate factors and descriptors live in a
+ * fixed device scratch of 64 MiB per GPU (allocated with the library's code
+ * object, held until the process ends):
+ *   - a query needs about 16 * n_blocks * k * k_q + 8 * (c * 64 + c^2 [c > 128]
+ *     + 2 * k * c) bytes of it (n_blocks: blocks the range touches); a query
+ *     that needs more returns ZS_ENOMEM before any work is enqueued;
+ *   - every call on a GPU uses that GPU's one scratch, so calls that overlap
+ *     on one GPU (different streams, host threads, or a graph replay beside
+ *     an eager call) race: the caller orders them, e.g. on one stream.
+ */
+zs_status zs_query_noalloc(const zs_store *st, int64_t t_s, int64_t t_e, int32_t k_q, void *U,
+                           int64_t ldu, double *S, void *V, int64_t ldv, int32_t *k_out,
+                           hipStream_t stream);
+
+/*
  * zs_query_batch -- nq independent queries in one set of launches.
  *   t_s, t_e, k_q   host arrays of nq ranges and ranks (same rules as zs_query).
  *   U, S, V         device base pointers (element types as in zs_query); query q writes

@@ -132,6 +132,37 @@ __host__ __device__ inline StackChunk make_stack_chunk(int32_t j, int32_t np, in
     return ch;
 }
 
+// ------------------------------------------------ no-allocation query scratch
+// Size of the fixed device scratch of zs_query_noalloc (one copy per device).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+// Gram-tree nodes of one query: at most two per level of the tree.
+constexpr int kMaxPlanNodes = 96;
+
+// The plan of one query, passed by value to the kernel that writes it into
+// the scratch (d_* are the destinations there).
+struct SinglePlan {
+    QueryDesc qd;
+    Prob prob;
+    int32_t npidx, ngsrc, nchunks, k;
+    int32_t pidx[2];              // pieces that go through the Partial-SVD
+    int32_t msrc[2];              // their stack-row slots in Mp
+    int64_t gsrc[kMaxPlanNodes];  // Gram-tree nodes of the whole blocks
+    int64_t c;
+    const double *tree;
+    const double *Mp;
+    QueryDesc *d_qd;
+    Prob *d_prob;
+    StackChunk *d_chunks;
+    int32_t *d_pidx;
+    const double **d_msrc;
+    const double **d_gsrc;
+    int32_t *d_perm;              // identity order of the pieces
+};
+
+// Device address of this device's scratch (looked up once per device).
+hipError_t noalloc_scratch(void **ptr);
+hipError_t launch_plan_single(const SinglePlan &p, hipStream_t stream);
+
 // ---------------------------------------------------------------- launches
 // All launches are asynchronous on `stream` and return the launch status.
 hipError_t launch_gram(const void *X, int x_type, int64_t ld, int c, const Chunk *chunks,

@@ -329,6 +329,31 @@ struct VecSink {
     void add_gsrc(int64_t v) { gsrc.push_back(v); }
 };
 
+// Sink of plan_one for one query planned into a SinglePlan (fixed arrays).
+struct PlanSink {
+    SinglePlan &p;
+    bool overflow = false;
+    int32_t nm = 0;
+    int32_t npidx() const { return p.npidx; }
+    int32_t nmsrc() const { return nm; }
+    int32_t ngsrc() const { return p.ngsrc; }
+    void add_pidx(int32_t v)
+    {
+        if (p.npidx < 2) p.pidx[p.npidx++] = v;
+        else overflow = true;
+    }
+    void add_msrc(int32_t v)
+    {
+        if (nm < 2) p.msrc[nm++] = v;
+        else overflow = true;
+    }
+    void add_gsrc(int64_t v)
+    {
+        if (p.ngsrc < kMaxPlanNodes) p.gsrc[p.ngsrc++] = v;
+        else overflow = true;
+    }
+};
+
 // Plans a batch (Alg. 3 index math, host side), sizes workspace `w` and uploads
 // the descriptors to it: through the pinned staging buffer on `stream`, or
 // synchronously when `sync_upload` (graphs, whose descriptors must stay put).
@@ -749,6 +774,101 @@ zs_status zs_query(const zs_store *cst, int64_t t_s, int64_t t_e, int32_t k_q, v
     const int64_t zero = 0;
     return query_impl(st, 1, &t_s, &t_e, &k_q, U, &zero, &ldu, S, &zero, V, &zero, &ldv, k_out,
                       stream);
+}
+
+zs_status zs_query_noalloc(const zs_store *cst, int64_t t_s, int64_t t_e, int32_t k_q, void *U,
+                           int64_t ldu, double *S, void *V, int64_t ldv, int32_t *k_out,
+                           hipStream_t stream)
+{
+    if (!cst) return fail(ZS_EINVAL, "store is null");
+    zs_status s = check_query(cst, t_s, t_e, k_q);
+    if (s != ZS_OK) return s;
+    if (!U || !S || !V || !k_out) return fail(ZS_EINVAL, "null output pointer");
+    if (ldu < k_q || ldv < k_q) return fail(ZS_EINVAL, "ldu/ldv < k_q");
+    zs_store *st = const_cast<zs_store *>(cst);
+    const int64_t c = st->c;
+    const int32_t k = st->k;
+    // the plan, on the host (O(log nb) work), into a by-value descriptor
+    SinglePlan p;
+    std::memset(&p, 0, sizeof p);
+    PlanSink sink{p};
+    int32_t nchunks = 0;
+    plan_one(st, 0, t_s, t_e, k_q, 0, ldu, S, V, ldv, k_out, 0, 0, 0, nchunks, sink, p.qd, p.prob);
+    if (sink.overflow) return fail(ZS_EUNSUPPORTED, "query plan exceeds %d Gram-tree nodes", kMaxPlanNodes);
+    const int64_t np = p.qd.np;
+    const int64_t npartial = p.npidx;
+    // the scratch layout: descriptors, then the intermediate factors
+    size_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const size_t o = off;
+        off = align_up(off + (size_t)std::max<int64_t>(bytes, 1), 256);
+        return o;
+    };
+    const size_t o_qd = take(sizeof(QueryDesc)), o_pr = take(sizeof(Prob));
+    const size_t o_ch = take((int64_t)sizeof(StackChunk) * nchunks);
+    const size_t o_pidx = take(2 * sizeof(int32_t)), o_msrc = take(2 * sizeof(double *));
+    const size_t o_gsrc = take((int64_t)sizeof(double *) * p.ngsrc);
+    const size_t o_perm = take((int64_t)sizeof(int32_t) * np);
+    const size_t o_P = take((int64_t)sizeof(Piece) * np);
+    const size_t o_Mp = take(8 * npartial * k * c), o_T = take(8 * npartial * k * k);
+    const size_t o_Vk = take(8 * c * kMaxK), o_Y = take(8 * np * k * k_q);
+    const size_t o_GY = take(8 * (int64_t)nchunks * kSlotK), o_F = take(8 * (int64_t)kSlotK);
+    const size_t o_C = take(8 * np * prod_ld(k) * k_q);
+    const size_t o_big = take(8 * (int64_t)big_doubles(c, 1));
+    if (off > kNoAllocScratchBytes)
+        return fail(ZS_ENOMEM, "query of %lld blocks needs %zu bytes of scratch; the fixed "
+                    "no-allocation scratch holds %zu", (long long)np, off, kNoAllocScratchBytes);
+    void *vbase = nullptr;
+    HIP_TRY(noalloc_scratch(&vbase));
+    char *base = static_cast<char *>(vbase);
+    p.nchunks = nchunks;
+    p.k = k;
+    p.c = c;
+    p.tree = st->tree;
+    p.Mp = reinterpret_cast<const double *>(base + o_Mp);
+    p.d_qd = reinterpret_cast<QueryDesc *>(base + o_qd);
+    p.d_prob = reinterpret_cast<Prob *>(base + o_pr);
+    p.d_chunks = reinterpret_cast<StackChunk *>(base + o_ch);
+    p.d_pidx = reinterpret_cast<int32_t *>(base + o_pidx);
+    p.d_msrc = reinterpret_cast<const double **>(base + o_msrc);
+    p.d_gsrc = reinterpret_cast<const double **>(base + o_gsrc);
+    p.d_perm = reinterpret_cast<int32_t *>(base + o_perm);
+    QueryPlan pl;
+    pl.nq = 1;
+    pl.max_np = (int32_t)np;
+    pl.kq_max = k_q;
+    pl.nchunks = nchunks;
+    pl.npieces = (int)np;
+    pl.npartial = (int)npartial;
+    pl.contiguous = ldu == k_q;
+    pl.U = U;
+    QueryBufs qb;
+    qb.chunks = p.d_chunks;
+    qb.probs = p.d_prob;
+    qb.qds = p.d_qd;
+    qb.pidx = p.d_pidx;
+    qb.boff = nullptr;                   // one query: its pieces are in block order
+    qb.gsrc = p.d_gsrc;
+    qb.msrc = p.d_msrc;
+    qb.P = reinterpret_cast<Piece *>(base + o_P);
+    qb.perm = p.d_perm;
+    qb.bcount = nullptr;
+    qb.Mp = reinterpret_cast<double *>(base + o_Mp);
+    qb.T = reinterpret_cast<double *>(base + o_T);
+    qb.Vk = reinterpret_cast<double *>(base + o_Vk);
+    qb.Y = reinterpret_cast<double *>(base + o_Y);
+    qb.GY = reinterpret_cast<double *>(base + o_GY);
+    qb.F = reinterpret_cast<double *>(base + o_F);
+    qb.C = reinterpret_cast<double *>(base + o_C);
+    qb.big = reinterpret_cast<double *>(base + o_big);
+    // no timing events either: the launches below are all this call makes
+    const bool was_untimed = t_untimed;
+    t_untimed = true;
+    hipError_t e = launch_plan_single(p, stream);
+    s = e == hipSuccess ? query_kernels(st, pl, qb, stream)
+                        : fail(ZS_EDEVICE, "plan: %s", hipGetErrorString(e));
+    t_untimed = was_untimed;
+    return s;
 }
 
 static zs_status check_batch(const zs_store *cst, int32_t nq, const int64_t *t_s, const int64_t *t_e,

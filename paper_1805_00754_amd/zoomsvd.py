@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "ZS_OK", -1: "ZS_EINVAL", -2: "ZS_ERANGE", -3: "ZS_ENOMEM", -
 
 # Symbols the header declares (the CPU test checks the library exports all).
 EXPORTED = ["zs_store_blocks", "zs_store_blocks_xi", "zs_store_append", "zs_window_similarity",
-            "zs_query", "zs_query_batch", "zs_query_batch_graph",
+            "zs_query", "zs_query_noalloc", "zs_query_batch", "zs_query_batch_graph",
             "zs_batch_graph_launch", "zs_batch_graph_free", "zs_store_free", "zs_store_bytes",
             "zs_store_info", "zs_store_get_block", "zs_sync_status", "zs_last_error", "zs_version",
             "zs_timing_enable", "zs_timing_reset", "zs_timing_get"]
@@ -65,6 +65,7 @@ def load(path: str | None = None):
         lib.zs_store_blocks_xi.argtypes = [_vp, _i64, _i64, _i64, ctypes.c_int, _i64, _i32,
                                            ctypes.c_int, ctypes.c_double, _vp, ctypes.POINTER(_vp)]
         lib.zs_query.argtypes = [_vp, _i64, _i64, _i32, _vp, _i64, _vp, _vp, _i64, _vp, _vp]
+        lib.zs_query_noalloc.argtypes = lib.zs_query.argtypes
         lib.zs_window_similarity.argtypes = [_vp, _i64, _i64, _i64, _i32, _vp, _vp]
         lib.zs_store_append.argtypes = [_vp, _vp, _i64, _i64, ctypes.c_int, _vp]
         lib.zs_query_batch.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -88,7 +89,8 @@ def load(path: str | None = None):
         lib.zs_timing_reset.restype = None
         lib.zs_timing_get.argtypes = [ctypes.c_char_p, _vp, _vp]
         for name in ("zs_store_blocks", "zs_store_blocks_xi", "zs_store_append",
-                     "zs_window_similarity", "zs_query", "zs_query_batch", "zs_store_info",
+                     "zs_window_similarity", "zs_query", "zs_query_noalloc", "zs_query_batch",
+                     "zs_store_info",
                      "zs_store_get_block", "zs_sync_status", "zs_timing_get",
                      "zs_query_batch_graph", "zs_batch_graph_launch"):
             getattr(lib, name).restype = ctypes.c_int
@@ -189,9 +191,11 @@ def zs_store_append(st: Store, R: torch.Tensor, stream=None) -> Store:
 
 
 def zs_query(st: Store, t_s: int, t_e: int, k_q: int, U=None, S=None, V=None, k_out=None,
-             stream=None):
+             stream=None, noalloc: bool = False):
     """Query phase for [t_s, t_e).  Returns (U n x k_q, S k_q, V c x k_q,
-    k_out) as device tensors (allocated when not given)."""
+    k_out) as device tensors (allocated when not given).  With noalloc the
+    call goes to zs_query_noalloc (the library allocates nothing; its fixed
+    scratch is shared by every such call on the device)."""
     dev = torch.device("cuda", torch.cuda.current_device())
     n = t_e - t_s
     if U is None:
@@ -202,9 +206,9 @@ def zs_query(st: Store, t_s: int, t_e: int, k_q: int, U=None, S=None, V=None, k_
         V = torch.empty((st.c, k_q), dtype=st.out_dtype, device=dev)
     if k_out is None:
         k_out = torch.empty(1, dtype=torch.int32, device=dev)
-    _check(load().zs_query(_vp(st.handle), t_s, t_e, k_q, _vp(_ptr(U)), U.stride(0),
-                           _vp(_ptr(S)), _vp(_ptr(V)), V.stride(0), _vp(_ptr(k_out)),
-                           _vp(_stream(stream))))
+    fn = load().zs_query_noalloc if noalloc else load().zs_query
+    _check(fn(_vp(st.handle), t_s, t_e, k_q, _vp(_ptr(U)), U.stride(0), _vp(_ptr(S)), _vp(_ptr(V)),
+              V.stride(0), _vp(_ptr(k_out)), _vp(_stream(stream))))
     return U, S, V, k_out
 
 

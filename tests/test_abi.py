@@ -85,6 +85,8 @@ def test_query_rejects_null_store(zs):
     lib = zs.load()
     vp = ctypes.c_void_p
     assert lib.zs_query(vp(0), 0, 1, 1, vp(8), 1, vp(8), vp(8), 1, vp(8), vp(0)) == zs.ZS_EINVAL
+    assert lib.zs_query_noalloc(vp(0), 0, 1, 1, vp(8), 1, vp(8), vp(8), 1, vp(8), vp(0)) \
+        == zs.ZS_EINVAL
     assert lib.zs_query_batch(vp(0), 1, vp(8), vp(8), vp(8), vp(8), vp(8), vp(8), vp(8), vp(8),
                               vp(8), vp(8), vp(0)) == zs.ZS_EINVAL
     assert lib.zs_store_bytes(vp(0)) == 0
