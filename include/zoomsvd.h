@@ -50,7 +50,7 @@ typedef enum {
 } zs_status;
 
 typedef enum { ZS_F64 = 0, ZS_F32 = 1, ZS_BF16 = 2 } zs_dtype;          /* element type of A */
-typedef enum { ZS_MODE_FP64 = 0, ZS_MODE_FP32 = 1, ZS_MODE_BF16 = 2 } zs_mode; /* factor storage */
+typedef enum { ZS_MODE_FP64 = 0, ZS_MODE_FP32 = 1, ZS_MODE_BF16 = 2 } zs_mode; /* bulk arithmetic */
 
 typedef struct zs_store zs_store;   /* opaque; owns the device-resident U_(i), Sigma_(i), V_(i) */
 
@@ -69,13 +69,21 @@ typedef struct zs_store zs_store;   /* opaque; owns the device-resident U_(i), S
  *          Block i keeps k_i = min(k, rows_i, numerical rank) triplets.
  *   a_type ZS_F64, ZS_F32 or ZS_BF16; every mode reads every type and widens
  *          it exactly.
- *   mode   ZS_MODE_FP64: U_(i) and V_(i) stored in FP64, rank threshold
- *          1e-11.  ZS_MODE_FP32 and ZS_MODE_BF16: U_(i) and V_(i) stored in
- *          FP32 (half the memory and half the block-product traffic), rank
- *          threshold 1e-5; queries then return U and V in FP32.  In every
- *          mode the Gram, the eigen-solves and the Rayleigh-Ritz step run in
- *          FP64 (this build keeps no BF16 arithmetic: BF16 mode differs from
- *          FP32 mode only in the input type it is meant for).
+ *   mode   arithmetic of the bulk work and storage of the factors:
+ *          ZS_MODE_FP64: everything in FP64; U_(i) and V_(i) stored in FP64,
+ *            rank threshold 1e-11.
+ *          ZS_MODE_FP32: the block Gram A_(i)^T A_(i) (the O(b c^2) term) on
+ *            the FP32 matrix cores, A rounded to FP32; ZS_MODE_BF16: on the
+ *            BF16 matrix cores, A rounded to bf16 (bf16 input enters
+ *            exactly; FP32 mode also takes bf16 input on the BF16 cores).
+ *            Both accumulate in FP32 over runs of 32 (FP32) or 128 (BF16)
+ *            rows and add the runs in FP64.  The eigen-solve of the Gram
+ *            and one refinement sweep (Y = A_(i) V_k from the input values,
+ *            Y^T Y and its Jacobi solve, all FP64) follow in FP64, so sigma
+ *            is a Rayleigh-Ritz value of the input.  U_(i), V_(i) stored in
+ *            FP32, rank threshold 1e-5; queries return U and V in FP32.
+ *            Parity targets against FP64: 1e-5 (FP32), 1e-3 (BF16) relative
+ *            on sigma.
  *   out    receives the new store.  The library owns its device memory until
  *          zs_store_free.  The call synchronises `stream` once at the end to
  *          check the per-block Jacobi status; on ZS_ENOCONV the store is still

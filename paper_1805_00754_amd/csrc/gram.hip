@@ -181,6 +181,292 @@ __global__ __launch_bounds__(kThreads) void gram_mfma_kernel(const TA *__restric
     }
 }
 
+// ------------------------------------------------------ FP32 / BF16 arithmetic
+// The block Gram of the FP32 and BF16 modes on the matrix cores, widened to
+// FP64 for the eigen-solver (which, like the refinement after it, stays in
+// FP64):
+//   BF16: v_mfma_f32_16x16x32_bf16.  bf16 input enters exactly; wider input
+//         is rounded to bf16 (to nearest even; FP64 through FP32).
+//   FP32: v_mfma_f32_16x16x4f32 on the input rounded to FP32.
+// The matrix cores accumulate in FP32 over a short run of rows (32 in FP32,
+// 128 in BF16), and each run's sums are then added into FP64 accumulators: a
+// Gram summed in FP32 over a whole block moves the block's small singular
+// subspaces by more than the FP32 mode allows, and the short FP32 runs keep
+// that error well inside it.
+// A work-group (8 waves) owns a 128 x 128 tile (ti <= tj) of G over one chunk
+// of rows; wave (wr, wc) owns rows [32 wr, 32 wr + 32) and columns
+// [64 wc, 64 wc + 64) of the tile: 2 x 4 blocks of 16 x 16.  The rows go
+// through LDS in panels of 32; the next panel's global loads are in flight
+// while the current one is multiplied.  Operand layouts (decoded on the GPU):
+// lane l holds row l % 16 of A and column l % 16 of B, the same k for the same
+// (lane, element) of A and B, and D(i, j) sits in register i % 4 of lane
+// j + 16 (i / 4).
+//   * BF16 panels are stored transposed, one word per pair of rows (even row
+//     in the low half), 20 words per column, so that a lane reads its 8 rows
+//     of one column with one 16-byte LDS read.  The 16-byte quads of a column
+//     are swizzled by (column / 16) mod 4: writes are at most 2-way bank
+//     conflicts and reads conflict-free.
+//   * FP32 panels are row-major with 144 floats per row (reads conflict-free).
+// Work-groups are dispatched to the 8 XCDs round-robin; the tile pairs of one
+// chunk are given to work-groups of one XCD, so the chunk's rows are fetched
+// into one L2 and read from there by all its tiles.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLpThreads = 512;    // 8 waves
+constexpr int kLpTile = 128;       // output tile edge
+constexpr int kLpRows = 32;        // rows per LDS panel
+constexpr int kLpTWords = 20;      // words per column of a transposed bf16 panel (16 + pad)
+constexpr int kLpFStride = 144;    // floats per row of an FP32 panel (128 + pad)
+constexpr int kXcdsGram = 8;
+
+// 8 consecutive elements of one row, as loaded (16-byte words).
+template <typename TA> struct Raw8 {
+    static constexpr int N = (int)(8 * sizeof(TA) / 16);
+    u32x4 w[N];
+};
+
+// Loads elements [col0, col0 + 8) of a row.  VEC: one to four 16-byte loads
+// (the caller guarantees alignment and col0 + 8 <= c); otherwise element by
+// element with the column clamped (masked when converted).
+template <typename TA, bool VEC>
+__device__ __forceinline__ void raw_load(const TA *__restrict__ rowp, int col0, int c, Raw8<TA> &r)
+{
+    if constexpr (VEC) {
+        const u32x4 *p = reinterpret_cast<const u32x4 *>(rowp + col0);
+#pragma unroll
+        for (int i = 0; i < Raw8<TA>::N; ++i) r.w[i] = p[i];
+    } else {
+        TA v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = rowp[min(col0 + e, c - 1)];
+        __builtin_memcpy(&r, v, sizeof v);
+    }
+}
+
+__device__ __forceinline__ float raw_f32(const Raw8<uint16_t> &r, int e)
+{
+    return __uint_as_float(((r.w[0][e / 2] >> (16 * (e % 2))) & 0xFFFFu) << 16);
+}
+__device__ __forceinline__ float raw_f32(const Raw8<float> &r, int e) { return __uint_as_float(r.w[e / 4][e % 4]); }
+__device__ __forceinline__ float raw_f32(const Raw8<double> &r, int e)
+{
+    const uint64_t u = ((uint64_t)r.w[e / 2][2 * (e % 2) + 1] << 32) | r.w[e / 2][2 * (e % 2)];
+    return (float)__longlong_as_double((long long)u);
+}
+
+// bf16 bits rounded to nearest even from FP32 (finite values).
+__device__ __forceinline__ uint32_t bf16_rne(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ uint32_t raw_bf16(const Raw8<uint16_t> &r, int e)
+{
+    return (r.w[0][e / 2] >> (16 * (e % 2))) & 0xFFFFu;
+}
+template <typename TA>
+__device__ __forceinline__ uint32_t raw_bf16(const Raw8<TA> &r, int e) { return bf16_rne(raw_f32(r, e)); }
+
+template <bool BF16, typename TA, bool VEC>
+__global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(const TA *__restrict__ X, int64_t ld, int c,
+                                                             const Chunk *__restrict__ chunks, int nchunks,
+                                                             int npairs, double *__restrict__ Gpart)
+{
+    // LDS: two strips (columns of tile ti and of tile tj) of one panel
+    constexpr int BF_WORDS = 2 * kLpTile * kLpTWords;
+    constexpr int F_WORDS = 2 * kLpRows * kLpFStride;
+    __shared__ __align__(16) uint32_t lds[BF16 ? BF_WORDS : F_WORDS];
+    constexpr int FLUSH = BF16 ? 4 : 1;            // panels per FP32 run
+
+    const int per = (nchunks + kXcdsGram - 1) / kXcdsGram;
+    const int slot = (int)blockIdx.x / kXcdsGram;
+    const int chunk = (int)(blockIdx.x % kXcdsGram) * per + slot / npairs;
+    if (chunk >= nchunks) return;
+    int idx = slot % npairs, ti = 0;
+    const int ntile = (c + kLpTile - 1) / kLpTile;
+    while (idx >= ntile - ti) { idx -= ntile - ti; ++ti; }
+    const int tj = ti + idx;
+    const bool diag = ti == tj;
+    const Chunk ch = chunks[chunk];
+    const TA *__restrict__ Xc = X + ch.x_off;
+    const int rows = ch.rows;
+    const int tid = threadIdx.x, lane = tid % 64;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+    const int wr = wave / 2, wc = wave % 2;
+    // 16 x 16 block (a, b) of this wave is block (2 wr + a, 4 wc + b) of the
+    // tile; on a diagonal tile only blocks on or above the diagonal are formed
+    const bool active = !(diag && 2 * wr > 4 * wc + 3) && ti * kLpTile + wr * 32 < c &&
+                        tj * kLpTile + wc * 64 < c;
+
+    // loads of a panel: BF16: thread -> strip tid / 256, row pair p (rows 2p,
+    // 2p + 1) and 8-column group of that strip; FP32: thread -> rows tid / 16
+    // (0..31), 8-column group tid % 16, both strips
+    const int cg = tid % 16;
+    constexpr int NR = BF16 ? 2 : 2;               // raw items per thread
+    Raw8<TA> ra[NR];
+    const int bs = tid / 256, bp = (tid % 256) / 16;
+    auto item = [&](int h, int r0, int &row, int &col, int &s) {
+        if constexpr (BF16) {
+            s = bs;
+            row = r0 + 2 * bp + h;
+        } else {
+            s = h;
+            row = r0 + tid / 16;
+        }
+        col = (s == 0 ? ti : tj) * kLpTile + 8 * cg;
+    };
+    const bool loads = !(BF16 && diag && bs == 1);
+    auto issue = [&](int r0) {
+#pragma unroll
+        for (int h = 0; h < NR; ++h) {
+            int row, col, s;
+            item(h, r0, row, col, s);
+            if (!BF16 && diag && s == 1) continue;
+            const int colc = VEC ? min(col, c - 8) : col;
+            const int64_t rc = min(row, rows - 1);
+            if (loads) raw_load<TA, VEC>(Xc + rc * ld, colc, c, ra[h]);
+        }
+    };
+    auto stage = [&](int r0) {
+        if constexpr (BF16) {
+            if (!loads) return;
+            int row, col, s;
+            item(0, r0, row, col, s);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const bool cok = col + e < c;
+                const uint32_t lo = (cok && row < rows) ? raw_bf16(ra[0], e) : 0u;
+                const uint32_t hi = (cok && row + 1 < rows) ? raw_bf16(ra[1], e) : 0u;
+                const int lc = 8 * cg + e;                     // column within the strip
+                const int q = (bp >> 2) ^ ((lc >> 4) & 3);     // swizzled quad
+                lds[(s * kLpTile + lc) * kLpTWords + 4 * q + (bp & 3)] = lo | (hi << 16);
+            }
+        } else {
+#pragma unroll
+            for (int h = 0; h < NR; ++h) {
+                int row, col, s;
+                item(h, r0, row, col, s);
+                if (diag && s == 1) continue;
+                float v[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = (row < rows && col + e < c) ? raw_f32(ra[h], e) : 0.0f;
+                float *dst = reinterpret_cast<float *>(lds) + (s * kLpRows + tid / 16) * kLpFStride + 8 * cg;
+                *reinterpret_cast<v4f *>(dst) = (v4f){v[0], v[1], v[2], v[3]};
+                *reinterpret_cast<v4f *>(dst + 4) = (v4f){v[4], v[5], v[6], v[7]};
+            }
+        }
+    };
+
+    v4f acc[2][4];
+    double accd[2][4][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) accd[a][b][v] = 0.0;
+        }
+
+    const int sj = diag ? 0 : 1;                   // strip of the B operand
+    issue(0);
+    int panel = 0;
+    for (int r0 = 0; r0 < rows; r0 += kLpRows, ++panel) {
+        __syncthreads();                           // the previous panel has been read
+        stage(r0);
+        __syncthreads();
+        if (r0 + kLpRows < rows) issue(r0 + kLpRows);
+        if (!active) continue;
+        if constexpr (BF16) {
+            v8bf fa[2], fb[4];
+            const int g = lane / 16;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int ca = wr * 32 + 16 * a + lane % 16;
+                fa[a] = __builtin_bit_cast(v8bf, *reinterpret_cast<const u32x4 *>(
+                    lds + ca * kLpTWords + 4 * (g ^ ((ca >> 4) & 3))));
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int cb2 = wc * 64 + 16 * b + lane % 16;
+                fb[b] = __builtin_bit_cast(v8bf, *reinterpret_cast<const u32x4 *>(
+                    lds + (sj * kLpTile + cb2) * kLpTWords + 4 * (g ^ ((cb2 >> 4) & 3))));
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        } else {
+            const float *F = reinterpret_cast<const float *>(lds);
+#pragma unroll 2
+            for (int st = 0; st < kLpRows / 4; ++st) {
+                const int rr = 4 * st + lane / 16;
+                float fa[2], fb[4];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) fa[a] = F[rr * kLpFStride + wr * 32 + 16 * a + lane % 16];
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    fb[b] = F[(sj * kLpRows + rr) * kLpFStride + wc * 64 + 16 * b + lane % 16];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
+            }
+        }
+        if ((panel + 1) % FLUSH == 0 || r0 + kLpRows >= rows) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) accd[a][b][v] += (double)acc[a][b][v];
+                    acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+                }
+        }
+    }
+    if (!active) return;
+    // G(I, J) and its mirror; on a diagonal tile blocks below the diagonal are
+    // skipped and diagonal blocks write i <= j only
+    double *G = Gpart + (int64_t)ch.slot * c * c;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int A = 2 * wr + a, B = 4 * wc + b;
+            if (diag && A > B) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * A + 4 * (lane / 16) + v, j = 16 * B + lane % 16;
+                if (diag && A == B && i > j) continue;
+                const int I = ti * kLpTile + i, J = tj * kLpTile + j;
+                if (I < c && J < c) {
+                    G[(int64_t)I * c + J] = accd[a][b][v];
+                    G[(int64_t)J * c + I] = accd[a][b][v];
+                }
+            }
+        }
+}
+
+template <bool BF16, typename TA>
+void run_gram_lp(const TA *X, int64_t ld, int c, const Chunk *chunks, int nchunks, double *Gpart,
+                 hipStream_t stream)
+{
+    const int ntile = (c + kLpTile - 1) / kLpTile;
+    const int npairs = ntile * (ntile + 1) / 2;
+    const int per = (nchunks + kXcdsGram - 1) / kXcdsGram;
+    const unsigned grid = (unsigned)(kXcdsGram * per * npairs);
+    const bool vec = c % 8 == 0 && (ld * (int64_t)sizeof(TA)) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(X) % 16 == 0;
+    if (vec)
+        gram_lp_kernel<BF16, TA, true><<<grid, kLpThreads, 0, stream>>>(X, ld, c, chunks, nchunks, npairs, Gpart);
+    else
+        gram_lp_kernel<BF16, TA, false><<<grid, kLpThreads, 0, stream>>>(X, ld, c, chunks, nchunks, npairs, Gpart);
+}
+
 template <typename TA>
 void run_gram(const TA *X, int64_t ld, int c, const Chunk *chunks, int nchunks, double *Gpart,
               hipStream_t stream)
@@ -208,11 +494,23 @@ void run_gram(const TA *X, int64_t ld, int c, const Chunk *chunks, int nchunks, 
 }
 
 hipError_t launch_gram(const void *X, int x_type, int64_t ld, int c, const Chunk *chunks,
-                       int nchunks, double *Gpart, hipStream_t stream)
+                       int nchunks, double *Gpart, hipStream_t stream, int prec)
 {
     if (nchunks <= 0) return hipSuccess;
     timing_begin("gram", stream);
-    if (x_type == kElemF32)
+    // bf16 input goes through the BF16 matrix cores in both reduced modes
+    // (exact products); FP32 mode rounds wider input to FP32
+    const bool bf = prec == kGramBF16 || (prec == kGramF32 && x_type == kElemBF16);
+    if (prec != kGramF64) {
+        if (x_type == kElemBF16)
+            run_gram_lp<true>(static_cast<const uint16_t *>(X), ld, c, chunks, nchunks, Gpart, stream);
+        else if (x_type == kElemF32)
+            bf ? run_gram_lp<true>(static_cast<const float *>(X), ld, c, chunks, nchunks, Gpart, stream)
+               : run_gram_lp<false>(static_cast<const float *>(X), ld, c, chunks, nchunks, Gpart, stream);
+        else
+            bf ? run_gram_lp<true>(static_cast<const double *>(X), ld, c, chunks, nchunks, Gpart, stream)
+               : run_gram_lp<false>(static_cast<const double *>(X), ld, c, chunks, nchunks, Gpart, stream);
+    } else if (x_type == kElemF32)
         run_gram(static_cast<const float *>(X), ld, c, chunks, nchunks, Gpart, stream);
     else if (x_type == kElemBF16)
         run_gram(static_cast<const uint16_t *>(X), ld, c, chunks, nchunks, Gpart, stream);

@@ -165,8 +165,11 @@ hipError_t launch_plan_single(const SinglePlan &p, hipStream_t stream);
 
 // ---------------------------------------------------------------- launches
 // All launches are asynchronous on `stream` and return the launch status.
+// Arithmetic of the block Gram: FP64 (FP64 mode, and every Gram of stored
+// factors), FP32 or BF16 matrix cores (the reduced modes).
+enum GramPrec { kGramF64 = 0, kGramF32 = 1, kGramBF16 = 2 };
 hipError_t launch_gram(const void *X, int x_type, int64_t ld, int c, const Chunk *chunks,
-                       int nchunks, double *Gpart, hipStream_t stream);
+                       int nchunks, double *Gpart, hipStream_t stream, int prec = kGramF64);
 hipError_t launch_eig_tri(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
                           const double *const *msrc, double *Vk, hipStream_t stream);
 hipError_t launch_project(const void *X, int x_type, int64_t ld, int c, const Chunk *chunks,

@@ -722,7 +722,9 @@ zs_status zs_store_blocks_xi(const void *A, int64_t t, int64_t c, int64_t lda, z
     const Chunk *d_pchunks = (const Chunk *)(desc.as<char>() + o_pchunks);
     const int x_type = a_type == ZS_F32 ? kElemF32 : a_type == ZS_BF16 ? kElemBF16 : kElemF64;
     ST_TRY2(Big.ensure(sizeof(double) * std::max<size_t>(1, big_doubles(c, nb))));
-    ST_TRY2(launch_gram(A, x_type, lda, (int)c, d_chunks, nchunks, Gpart.as<double>(), stream));
+    // the bulk Gram in the mode's arithmetic; everything after it in FP64
+    const int gprec = mode == ZS_MODE_FP32 ? kGramF32 : mode == ZS_MODE_BF16 ? kGramBF16 : kGramF64;
+    ST_TRY2(launch_gram(A, x_type, lda, (int)c, d_chunks, nchunks, Gpart.as<double>(), stream, gprec));
     ST_TRY2(first_stage_eig((int)c, k, d_probs, (int)nb, d_gsrc, nullptr, Vk.as<double>(),
                             Big.as<double>(), stream));
     ST_TRY2(launch_project(A, x_type, lda, (int)c, d_pchunks, npchunks, k, Vk.as<double>(), Y,

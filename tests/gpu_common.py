@@ -13,8 +13,12 @@ from tests.helpers import check_sigma, joint_sign_errs, orth_err, subspace_errs
 # |error| / sigma_1 below 10 sqrt(c) u sigma_1; singular subspaces within
 # TOL / g_j where g_j = (sigma_j - sigma_{j+1}) / sigma_1.
 TOL_FP64 = 1e-10
-# FP32 / BF16 modes: factors stored in FP32 (unit roundoff 6e-8); same rules.
+# FP32 mode: block Gram on FP32 matrix cores, factors stored in FP32 (unit
+# roundoff 6e-8); same rules.
 TOL_FP32 = 1e-5
+# BF16 mode: block Gram on BF16 matrix cores with FP32 accumulation; the input
+# is rounded to bf16 (unit roundoff 3.9e-3) when it is wider.
+TOL_BF16 = 1e-3
 RANK_TOL_F32 = 1e-5
 
 
@@ -31,6 +35,14 @@ def to_dev(A: np.ndarray, dtype=None) -> torch.Tensor:
 
 
 F32_KW = dict(unit=6e-8, orth_v=1e-6, orth_u=1e-6)
+# BF16 mode on input wider than bf16: the rounding of A is the unit roundoff
+BF16_ROUND_KW = dict(unit=3.9e-3, orth_v=1e-6, orth_u=1e-6)
+
+
+def mode_tol(mode: int) -> float:
+    """Parity tolerance of a storage mode (relative error on sigma; subspaces
+    within tol / gap)."""
+    return {zs.ZS_MODE_FP64: TOL_FP64, zs.ZS_MODE_FP32: TOL_FP32, zs.ZS_MODE_BF16: TOL_BF16}[mode]
 
 
 def download_store(st: zs.Store):

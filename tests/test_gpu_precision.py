@@ -1,9 +1,13 @@
-"""FP32 and BF16 modes: the store keeps U and V in FP32 and answers in FP32.
+"""FP32 and BF16 modes: the block Gram runs on the FP32 or BF16 matrix cores
+(FP32 accumulation), the eigen-solves and the refinement (projection and
+Rayleigh-Ritz) in FP64; the store keeps U and V in FP32 and answers in FP32.
+Tolerances: 1e-5 (FP32 mode) and 1e-3 (BF16 mode).
 
 Input is exactly representable in the mode's input type (synthetic data
-rounded to float32 or bfloat16), so the oracle sees the same values in FP64.
-Store parity is block by block; query parity runs the oracle's query phase on
-the store downloaded from the GPU (decoupled, as in FP64 mode)."""
+rounded to float32 or bfloat16), so the oracle sees the same values in FP64;
+one case feeds float32 input to BF16 mode, which rounds it to bf16 for the
+Gram.  Store parity is block by block; query parity runs the oracle's query
+phase on the store downloaded from the GPU (decoupled, as in FP64 mode)."""
 import numpy as np
 import pytest
 import torch
@@ -11,8 +15,8 @@ import torch
 import oracle
 from paper_1805_00754_amd import synth
 from paper_1805_00754_amd import zoomsvd as zs
-from tests.gpu_common import (F32_KW, RANK_TOL_F32, TOL_FP32, compare_svd, download_store, say,
-                              to_dev)
+from tests.gpu_common import (BF16_ROUND_KW, F32_KW, RANK_TOL_F32, compare_svd, download_store,
+                              mode_tol, say, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -43,11 +47,12 @@ def test_store_and_query_parity(name, tdtype, mode, t, c, b, k):
     assert st.out_dtype == torch.float32
     U, S, V, kk = download_store(st)
     ost = oracle.store(A, b, k, rank_tol=RANK_TOL_F32)
+    tol = mode_tol(mode)
     for i in range(st.nb):
         r = st.block_rows(i)
         compare_svd((U[i * b:i * b + r], S[i], V[i], int(kk[i])),
                     (ost.U[i * b:i * b + r], ost.S[i], ost.V[i], int(ost.k_i[i])),
-                    TOL_FP32, c, "%s store block %d" % (name, i), **F32_KW)
+                    tol, c, "%s store block %d" % (name, i), **F32_KW)
     gst = oracle.store_from_arrays(st.t, st.c, st.b, st.k, U, S, V, kk, rank_tol=RANK_TOL_F32)
     rng = synth.rng_for(90 + c)
     ts, te = synth.queries_uniform(rng, t, 6, 1, t)
@@ -58,7 +63,7 @@ def test_store_and_query_parity(name, tdtype, mode, t, c, b, k):
         assert Ug.dtype == torch.float32 and Vg.dtype == torch.float32 and Sg.dtype == torch.float64
         got = (Ug.double().cpu().numpy(), Sg.cpu().numpy(), Vg.double().cpu().numpy(), int(kg.item()))
         ref = oracle.query(gst, int(ts[q]), int(te[q]), kq)
-        compare_svd(got, ref, TOL_FP32, c, "%s query [%d,%d) kq %d" % (name, ts[q], te[q], kq),
+        compare_svd(got, ref, tol, c, "%s query [%d,%d) kq %d" % (name, ts[q], te[q], kq),
                     **F32_KW)
     st.free()
 
@@ -117,11 +122,12 @@ def test_wide_geometry_parity(wide, name, tdtype, mode):
     torch.cuda.synchronize()
     assert st.nb == 3 and st.block_rows(2) == 1152
     U, S, V, kk = download_store(st)
+    tol = mode_tol(mode)
     for i in range(st.nb):
         r = st.block_rows(i)
         compare_svd((U[i * b:i * b + r], S[i], V[i], int(kk[i])),
                     (ost.U[i * b:i * b + r], ost.S[i], ost.V[i], int(ost.k_i[i])),
-                    TOL_FP32, c, "wide %s block %d" % (name, i), **F32_KW)
+                    tol, c, "wide %s block %d" % (name, i), **F32_KW)
     gst = oracle.store_from_arrays(st.t, st.c, st.b, st.k, U, S, V, kk, rank_tol=RANK_TOL_F32)
     # ranges over the tail, across both block edges, inside one block, and all rows
     for ts, te, kq in [(0, WIDE_T, k), (1_000, 9_000, k), (4_000, 4_200, 16), (8_200, WIDE_T, 32),
@@ -130,5 +136,34 @@ def test_wide_geometry_parity(wide, name, tdtype, mode):
         zs.zs_sync_status(st)
         got = (Ug.double().cpu().numpy(), Sg.cpu().numpy(), Vg.double().cpu().numpy(), int(kg.item()))
         ref = oracle.query(gst, ts, te, kq)
-        compare_svd(got, ref, TOL_FP32, c, "wide %s [%d,%d) kq %d" % (name, ts, te, kq), **F32_KW)
+        compare_svd(got, ref, tol, c, "wide %s [%d,%d) kq %d" % (name, ts, te, kq), **F32_KW)
+    st.free()
+
+
+def test_bf16_mode_rounds_wider_input():
+    """float32 input in BF16 mode (the 4M x 256 workload's geometry at reduced
+    t, with a short last block): the Gram sees A rounded to bf16, the
+    refinement the float32 values; parity at the BF16 tolerance against the
+    oracle on the float32 values."""
+    ser, cfg = synth.workload("sinmix_4m_x256_f32", t=2 * 2000 + 700)
+    A, b, k = ser.A, cfg["b"], cfg["k"]
+    c = A.shape[1]
+    st = zs.zs_store_blocks(to_dev(A, torch.float32), b, k, mode=zs.ZS_MODE_BF16)
+    torch.cuda.synchronize()
+    assert st.nb == 3 and st.block_rows(2) == 700
+    U, S, V, kk = download_store(st)
+    ost = oracle.store(A, b, k, rank_tol=RANK_TOL_F32)
+    tol = mode_tol(zs.ZS_MODE_BF16)
+    for i in range(st.nb):
+        r = st.block_rows(i)
+        compare_svd((U[i * b:i * b + r], S[i], V[i], int(kk[i])),
+                    (ost.U[i * b:i * b + r], ost.S[i], ost.V[i], int(ost.k_i[i])),
+                    tol, c, "bf16-rounded block %d" % i, **BF16_ROUND_KW)
+    gst = oracle.store_from_arrays(st.t, st.c, st.b, st.k, U, S, V, kk, rank_tol=RANK_TOL_F32)
+    for ts, te, kq in [(0, st.t, k), (1_500, 4_400, 16), (100, 1_900, 8)]:
+        Ug, Sg, Vg, kg = zs.zs_query(st, ts, te, kq)
+        zs.zs_sync_status(st)
+        got = (Ug.double().cpu().numpy(), Sg.cpu().numpy(), Vg.double().cpu().numpy(), int(kg.item()))
+        compare_svd(got, oracle.query(gst, ts, te, kq), tol, c, "bf16-rounded [%d,%d)" % (ts, te),
+                    **F32_KW)
     st.free()
