@@ -27,6 +27,15 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "sinmix_1m_x128_f64"
 QUERY_LEN = 320_000
 N_QUERIES = 1024
+# The query batch of each workload: (distribution, queries, range lengths).
+# fixed: every range QUERY_LEN rows; loguniform: lengths log-uniform in [lo, hi]
+# at random starts (uneven stacks of whole blocks plus partial boundaries).
+BATCHES = {
+    "sinmix_10k_x64_f64": ("uniform", 20, 150, 8_000),
+    "sinmix_1m_x128_f64": ("fixed", N_QUERIES, QUERY_LEN, QUERY_LEN),
+    "sinmix_4m_x256_f32": ("loguniform", 1024, 10_000, 320_000),
+    "decay_2m_x1024_bf16": ("loguniform", 512, 100_000, 1_000_000),
+}
 HBM_PEAK_GBPS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
@@ -40,7 +49,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--queries", type=int, default=N_QUERIES)
+    ap.add_argument("--queries", type=int, default=None,
+                    help="queries per batch (default: the workload's batch)")
+    ap.add_argument("--query-dist", default=None, choices=["fixed", "loguniform", "uniform"],
+                    help="range lengths of the batch (default: the workload's batch)")
     ap.add_argument("--latency-samples", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=32)
@@ -51,7 +63,8 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD,
                     help="named synthetic workload (synth.WORKLOADS); the default is the one "
                          "the headline metric is quoted on")
-    ap.add_argument("--query-len", type=int, default=QUERY_LEN)
+    ap.add_argument("--query-len", type=int, default=QUERY_LEN,
+                    help="range length of a fixed batch")
     ap.add_argument("--sweep-b", default=None,
                     help="comma-separated block sizes: instead of the benchmark, store the "
                          "workload at each b and time query batches at range lengths 1e3, 1e4 "
@@ -86,8 +99,22 @@ def main():
                            "f32": (torch.float32, zs.ZS_MODE_FP32, 4),
                            "bf16": (torch.bfloat16, zs.ZS_MODE_BF16, 2)}[cfg["dtype"]]
     usize = 8 if mode == zs.ZS_MODE_FP64 else 4       # stored U / V element size
-    qlen = min(args.query_len, t)
-    ts, te = synth.queries_fixed(ser.rng, t, args.queries, qlen)
+    dist, nq_default, lmin, lmax = BATCHES.get(wl, ("fixed", N_QUERIES, QUERY_LEN, QUERY_LEN))
+    dist = args.query_dist or dist
+    if args.queries is None:
+        args.queries = nq_default
+    if dist == "fixed":
+        qlen = min(args.query_len, t)
+        ts, te = synth.queries_fixed(ser.rng, t, args.queries, qlen)
+        batch_desc = "%d ranges of %d rows" % (args.queries, qlen)
+    elif dist == "loguniform":
+        ts, te = synth.queries_loguniform(ser.rng, t, args.queries, lmin, min(lmax, t))
+        qlen = int(np.median(te - ts))
+        batch_desc = "%d ranges, lengths log-uniform in [%g, %g] rows" % (args.queries, lmin, lmax)
+    else:
+        ts, te = synth.queries_uniform(ser.rng, t, args.queries, lmin, min(lmax, t))
+        qlen = int(np.median(te - ts))
+        batch_desc = "%d ranges, lengths uniform in [%d, %d] rows" % (args.queries, lmin, lmax)
     kq = np.full(args.queries, k, np.int32)
     A = torch.from_numpy(A_host).to(dev).to(tdtype)
     torch.cuda.synchronize()
@@ -153,6 +180,25 @@ def main():
         graph_ms.append(e0.elapsed_time(e1))
     g.free()
     log("graph replay %.2f ms" % float(np.mean(graph_ms)))
+
+    # The storage phase captured into a graph (zs_store_graph_create) and
+    # replayed on the same input: one graph launch per store, no host
+    # planning, allocation or synchronisation inside it.
+    sg = zs.zs_store_graph_create(A, b, k, mode=mode)
+    torch.cuda.synchronize()
+    gstore_ms = []
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sg.launch(stream)
+        e1.record(stream)
+        e1.synchronize()
+        gstore_ms.append(e0.elapsed_time(e1))
+    zs.zs_sync_status(sg.st)
+    sg.free()
+    sg.st.free()
+    log("store graph replay %.2f ms" % float(np.mean(gstore_ms)))
 
     # The case study of Sec. 5: u_1 of every earlier 20,000-row window (stride
     # 500) against u_1 of the last 20,000 rows, all windows as one batch.
@@ -224,7 +270,7 @@ def main():
 
     # Single-query latency (queries issued one at a time).
     lat = []
-    U1 = torch.empty((qlen, k), dtype=st.out_dtype, device=dev)
+    U1 = torch.empty((int((te - ts).max()), k), dtype=st.out_dtype, device=dev)
     S1 = torch.empty(k, dtype=torch.float64, device=dev)
     V1 = torch.empty((c, k), dtype=st.out_dtype, device=dev)
     ko = torch.empty(1, dtype=torch.int32, device=dev)
@@ -238,6 +284,11 @@ def main():
     if args.serve_rates is None:
         args.serve_rates = "500,2000,8000" if wl == WORKLOAD else ""
     serving = serve_runs(st, args) if args.serve_rates else None
+    # Reduced-precision modes: every query of the batch against the FP64 path
+    # (an FP64-mode store of the same input, the same batch), per result.
+    precision = None
+    if mode != zs.ZS_MODE_FP64:
+        precision = precision_vs_fp64(A, b, k, st, ts, te, kq, out, dev)
     st.free()
 
     q_ms = float(np.mean(query_ms))
@@ -289,6 +340,18 @@ def main():
             roof["output_write_gbps"] = out_bytes / avg_s / 1e9
             roof["fill_gbps_same_buffer"] = fill_gbps
             roof["output_frac_of_fill"] = out_bytes / avg_s / 1e9 / fill_gbps
+    elif dom == "eig":
+        # FP64 arithmetic of the eigen-solves: one c x c problem per block and
+        # per query, (4/3) c^3 flops of tridiagonalisation and 2 c^2 k of
+        # back-transformation each
+        n_eig = kernels["eig"]["launches"] / args.steps
+        flops = ((t + b - 1) // b + args.queries) * (4.0 / 3.0 * c ** 3 + 2.0 * c * c * k)
+        sec = kernels["eig"]["total_ms"] / args.steps / 1e3
+        roof = {"kernel": "eig", "bound": "fp64", "achieved": flops / sec / 1e12,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": flops / sec / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
+                "algorithmic_flops_per_step": flops, "launches_per_step": n_eig,
+                "ms_per_step": sec * 1e3}
     else:
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": None, "traffic": None}
@@ -353,13 +416,15 @@ def main():
         "storage": "f64" if usize == 8 else "f32",
         "data": "synthetic",
         "config": {"workload": wl, "t": t, "c": c, "b": b, "k": k, "input": cfg["dtype"],
-                   "queries": args.queries, "query_rows": qlen, "k_q": k,
-                   "parallelism": "single-gpu"},
+                   "queries": args.queries, "query_rows": qlen, "batch": batch_desc,
+                   "batch_rows": int((te - ts).sum()), "k_q": k, "parallelism": "single-gpu"},
         "query_batch_ms": q_ms,
         "graph_batch_ms": float(np.mean(graph_ms)),
         "graph_svds_per_s": args.queries / (float(np.mean(graph_ms)) / 1e3),
         "store_ms": s_ms,
         "store_gbps": store_gbps,
+        "graph_store_ms": float(np.mean(gstore_ms)),
+        "graph_store_gbps": t * c * esize / (float(np.mean(gstore_ms)) / 1e3) / 1e9,
         "store_frac_hbm": store_gbps / HBM_PEAK_GBPS,
         "p50_ms": float(np.percentile(lat, 50)) if lat else None,
         "p99_ms": float(np.percentile(lat, 99)) if lat else None,
@@ -370,9 +435,59 @@ def main():
         "serving": serving,
         "windows": windows,
         "ingest": ingest,
+        "precision_vs_fp64": precision,
+        "autotune": {k_: {"variant": v[0], "ms": v[1]} for k_, v in zs.zs_autotune_table().items()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
+
+
+def precision_vs_fp64(A, b, k, st, ts, te, kq, out, dev, chunk=64):
+    """Error of each result of a reduced-precision store against the FP64 path
+    on the same input: the FP64-mode store of A answers the same queries
+    (in chunks of `chunk`, so that its FP64 outputs stay small).  Per query:
+    the largest relative error over sigma_1..k_out (|error| / sigma_1 below
+    10 sqrt(c) 6e-8 sigma_1) and the sine of the largest principal angle
+    between the two V (leading k_out columns)."""
+    import numpy as np
+    import torch
+
+    from paper_1805_00754_amd import zoomsvd as zs
+
+    c = st.c
+    floor = 10.0 * np.sqrt(c) * 6e-8
+    st64 = zs.zs_store_blocks(A, b, k, mode=zs.ZS_MODE_FP64)
+    torch.cuda.synchronize()
+    sig, ang, kdiff = [], [], 0
+    for q0 in range(0, len(ts), chunk):
+        q1 = min(len(ts), q0 + chunk)
+        ref = zs.zs_query_batch(st64, ts[q0:q1], te[q0:q1], kq[q0:q1])
+        torch.cuda.synchronize()
+        for q in range(q0, q1):
+            _, S, V, ko = out.result(q)
+            _, S64, V64, ko64 = ref.result(q - q0)
+            S, S64 = S.cpu().numpy(), S64.cpu().numpy()
+            kk = int(ko.item())
+            kdiff += kk != int(ko64.item())
+            kk = min(kk, int(ko64.item()))
+            s1 = max(S64[0], 1e-300)
+            rel = [abs(S[j] - S64[j]) / (S64[j] if S64[j] > floor * s1 else s1) for j in range(kk)]
+            sig.append(max(rel) if rel else 0.0)
+            Va = V[:, :kk].double().cpu().numpy()
+            Vb = V64[:, :kk].cpu().numpy()
+            sv = np.linalg.svd(Va.T @ Vb, compute_uv=False) if kk else np.ones(1)
+            ang.append(float(np.sqrt(max(0.0, 1.0 - min(1.0, sv.min()) ** 2))))
+        del ref
+    st64.free()
+    sig, ang = np.array(sig), np.array(ang)
+    log("precision vs FP64: sigma rel max %.3g p50 %.3g; V angle max %.3g"
+        % (sig.max(), np.median(sig), ang.max()))
+    return {"reference": "FP64-mode store of the same input, same queries",
+            "sigma_rel_max": float(sig.max()), "sigma_rel_p50": float(np.median(sig)),
+            "sigma_rel_p99": float(np.percentile(sig, 99)),
+            "v_sin_angle_max": float(ang.max()), "v_sin_angle_p50": float(np.median(ang)),
+            "k_out_differs": int(kdiff),
+            "per_query_sigma_rel": [float("%.3g" % x) for x in sig]}
 
 
 def sweep_b(args):

@@ -232,6 +232,41 @@ zs_status zs_batch_graph_launch(zs_batch_graph *g, hipStream_t stream);
  * Every replay must have completed. */
 void zs_batch_graph_free(zs_batch_graph *g);
 
+/*
+ * zs_store_graph_create -- the storage phase of one fixed input captured into
+ * a HIP graph (Alg. 1 in batch form, as zs_store_blocks), for an input that
+ * the caller refreshes in place: e.g. a device window of the series that is
+ * rewritten and recompressed over and over.
+ *   Arguments as in zs_store_blocks (no energy threshold).  The call builds
+ *   the store from A once (eagerly on `stream`, which it synchronises), then
+ *   captures the storage phase's launches into a graph.
+ *   st      receives the store (queried as any store; freed with
+ *           zs_store_free after the graph).
+ *   g       receives the graph.  It owns private scratch (partial Grams,
+ *           eigenvector blocks, descriptors) and keeps the addresses of A and
+ *           of the store's arrays: A must stay allocated at the same address
+ *           with the same shape.
+ * Errors as in zs_store_blocks, plus ZS_EDEVICE when capture or instantiation
+ * fails (both outputs NULL).  ZS_ENOCONV: the eager run hit the sweep cap;
+ * both outputs are set.
+ */
+typedef struct zs_store_graph zs_store_graph;
+zs_status zs_store_graph_create(const void *A, int64_t t, int64_t c, int64_t lda, zs_dtype a_type,
+                                int64_t b, int32_t k, zs_mode mode, hipStream_t stream,
+                                zs_store **st, zs_store_graph **g);
+
+/* zs_store_graph_launch -- re-runs the storage phase from A's current contents
+ * into the same store (asynchronous on `stream`): no host planning,
+ * allocation or synchronisation.  Its results are bitwise those of
+ * zs_store_blocks on the same contents.  Queries on the store and other
+ * replays of the graph must not overlap a replay; zs_sync_status reports a
+ * replay's ZS_ENOCONV. */
+zs_status zs_store_graph_launch(zs_store_graph *g, hipStream_t stream);
+
+/* zs_store_graph_free -- releases the graph and its scratch (synchronises the
+ * device first); the store stays.  NULL is a no-op. */
+void zs_store_graph_free(zs_store_graph *g);
+
 /* Releases the store's device memory (synchronises the device first); NULL is
  * a no-op. */
 void zs_store_free(zs_store *st);
@@ -259,6 +294,27 @@ zs_status zs_store_get_block(const zs_store *st, int64_t i, void *U, double *S, 
  * eigen-solve enqueued by this store since the last call hit its sweep cap.
  */
 zs_status zs_sync_status(const zs_store *st, hipStream_t stream);
+
+/*
+ * Autotuner of launch variants.  Some kernels have launch variants that
+ * compute the same bits (tile edge of the reduced-precision block Gram,
+ * threads per matrix of the c <= 128 eigen-solver, work order of the block
+ * product).  The first call with a new shape times each variant once on the
+ * call's own data and keeps the fastest, per process and, when the
+ * environment variable ZS_AUTOTUNE_CACHE names a file, in that file (read
+ * once, appended on every new choice).  ZS_AUTOTUNE=0 in the environment or
+ * zs_autotune(0) turns the timing off (cached choices still apply, else each
+ * site's default); graph capture and zs_query_noalloc never time.
+ *   zs_autotune_force -- forces `variant` at `site` for every shape
+ *       (variant < 0 clears it); sites: "gram_lp_tile" (0: 128-column tiles,
+ *       1: 64), "eig_tri_threads" (0: 512 threads, 1: 1024),
+ *       "blockprod_order" (0: XCD runs, 1: dispatch order).  For tests.
+ *   zs_autotune_table -- the choices so far, one "site|key<TAB>variant<TAB>
+ *       times in ms" line each; valid until the calling thread's next call.
+ */
+void zs_autotune(int on);
+zs_status zs_autotune_force(const char *site, int variant);
+const char *zs_autotune_table(void);
 
 /* Thread-local message describing the last error of the calling thread. */
 const char *zs_last_error(void);

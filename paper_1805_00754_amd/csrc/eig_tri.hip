@@ -28,6 +28,7 @@
 // The total work is O(c^3) with a small constant, against O(50 c^3) for
 // one-sided Jacobi.
 #include <atomic>
+#include <cstdio>
 
 #include "zs_internal.h"
 #include "wave.h"
@@ -665,13 +666,20 @@ int device_cus()
     return n;
 }
 
-// Two matrices per CU once there are more matrices than CUs, else one.
+// 512 threads and two matrices per CU, or 1,024 threads and one: both forms
+// round identically, so the autotuner picks per shape; without a choice, two
+// per CU once there are more matrices than CUs, else one.
 template <int NMAX>
 hipError_t run_eig_tri(int c, int k, const Prob *probs, int nprob, const double *const *gsrc,
                        const double *const *msrc, double *Vk, hipStream_t stream)
 {
-    if (nprob <= device_cus()) return run_eig_tri<NMAX, 1024>(c, k, probs, nprob, gsrc, msrc, Vk, stream);
-    return run_eig_tri<NMAX, 512>(c, k, probs, nprob, gsrc, msrc, Vk, stream);
+    char key[64];
+    snprintf(key, sizeof key, "c=%d k=%d n=%d", c, k, tune_bucket(nprob));
+    const int dflt = nprob <= device_cus() ? 1 : 0;
+    return tuned_launch("eig_tri_threads", key, 2, dflt, stream, [&](int v) {
+        return v == 1 ? run_eig_tri<NMAX, 1024>(c, k, probs, nprob, gsrc, msrc, Vk, stream)
+                      : run_eig_tri<NMAX, 512>(c, k, probs, nprob, gsrc, msrc, Vk, stream);
+    });
 }
 
 }  // namespace

@@ -11,6 +11,8 @@
 // many other problems share the launch.
 #include "zs_internal.h"
 
+#include <cstdio>
+
 namespace zs {
 namespace {
 
@@ -214,11 +216,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kLpThreads = 512;    // 8 waves
-constexpr int kLpTile = 128;       // output tile edge
 constexpr int kLpRows = 32;        // rows per LDS panel
 constexpr int kLpTWords = 20;      // words per column of a transposed bf16 panel (16 + pad)
-constexpr int kLpFStride = 144;    // floats per row of an FP32 panel (128 + pad)
 constexpr int kXcdsGram = 8;
 
 // 8 consecutive elements of one row, as loaded (16-byte words).
@@ -269,14 +268,20 @@ __device__ __forceinline__ uint32_t raw_bf16(const Raw8<uint16_t> &r, int e)
 template <typename TA>
 __device__ __forceinline__ uint32_t raw_bf16(const Raw8<TA> &r, int e) { return bf16_rne(raw_f32(r, e)); }
 
-template <bool BF16, typename TA, bool VEC>
-__global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(const TA *__restrict__ X, int64_t ld, int c,
+// TILE = 128: 8 waves of 32 x 64; TILE = 64: 4 waves of 32 x 32.  Every output
+// element sees the same matrix-core operations in the same order in both (the
+// same panels, the same FP32 runs), so the two compute the same bits.
+template <int TILE, bool BF16, typename TA, bool VEC>
+__global__ __launch_bounds__(TILE * 4) void gram_lp_kernel(const TA *__restrict__ X, int64_t ld, int c,
                                                              const Chunk *__restrict__ chunks, int nchunks,
                                                              int npairs, double *__restrict__ Gpart)
 {
     // LDS: two strips (columns of tile ti and of tile tj) of one panel
-    constexpr int BF_WORDS = 2 * kLpTile * kLpTWords;
-    constexpr int F_WORDS = 2 * kLpRows * kLpFStride;
+    constexpr int FSTRIDE = TILE + 16;             // floats per row of an FP32 panel
+    constexpr int CG = TILE / 8;                   // 8-column groups per strip
+    constexpr int NBB = TILE / 32;                 // 16-column blocks per wave
+    constexpr int BF_WORDS = 2 * TILE * kLpTWords;
+    constexpr int F_WORDS = 2 * kLpRows * FSTRIDE;
     __shared__ __align__(16) uint32_t lds[BF16 ? BF_WORDS : F_WORDS];
     constexpr int FLUSH = BF16 ? 4 : 1;            // panels per FP32 run
 
@@ -285,7 +290,7 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(const TA *__restric
     const int chunk = (int)(blockIdx.x % kXcdsGram) * per + slot / npairs;
     if (chunk >= nchunks) return;
     int idx = slot % npairs, ti = 0;
-    const int ntile = (c + kLpTile - 1) / kLpTile;
+    const int ntile = (c + TILE - 1) / TILE;
     while (idx >= ntile - ti) { idx -= ntile - ti; ++ti; }
     const int tj = ti + idx;
     const bool diag = ti == tj;
@@ -295,27 +300,27 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(const TA *__restric
     const int tid = threadIdx.x, lane = tid % 64;
     const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
     const int wr = wave / 2, wc = wave % 2;
-    // 16 x 16 block (a, b) of this wave is block (2 wr + a, 4 wc + b) of the
+    // 16 x 16 block (a, b) of this wave is block (2 wr + a, NBB wc + b) of the
     // tile; on a diagonal tile only blocks on or above the diagonal are formed
-    const bool active = !(diag && 2 * wr > 4 * wc + 3) && ti * kLpTile + wr * 32 < c &&
-                        tj * kLpTile + wc * 64 < c;
+    const bool active = !(diag && 2 * wr > NBB * wc + NBB - 1) && ti * TILE + wr * 32 < c &&
+                        tj * TILE + wc * 16 * NBB < c;
 
-    // loads of a panel: BF16: thread -> strip tid / 256, row pair p (rows 2p,
-    // 2p + 1) and 8-column group of that strip; FP32: thread -> rows tid / 16
-    // (0..31), 8-column group tid % 16, both strips
-    const int cg = tid % 16;
-    constexpr int NR = BF16 ? 2 : 2;               // raw items per thread
+    // loads of a panel: BF16: thread -> strip, row pair bp (rows 2 bp,
+    // 2 bp + 1) and 8-column group of that strip; FP32: thread -> row tid / CG
+    // (0..31) and 8-column group tid % CG of both strips
+    const int cg = tid % CG;
+    constexpr int NR = 2;                          // raw items per thread
     Raw8<TA> ra[NR];
-    const int bs = tid / 256, bp = (tid % 256) / 16;
+    const int bs = tid / (16 * CG), bp = (tid % (16 * CG)) / CG;
     auto item = [&](int h, int r0, int &row, int &col, int &s) {
         if constexpr (BF16) {
             s = bs;
             row = r0 + 2 * bp + h;
         } else {
             s = h;
-            row = r0 + tid / 16;
+            row = r0 + tid / CG;
         }
-        col = (s == 0 ? ti : tj) * kLpTile + 8 * cg;
+        col = (s == 0 ? ti : tj) * TILE + 8 * cg;
     };
     const bool loads = !(BF16 && diag && bs == 1);
     auto issue = [&](int r0) {
@@ -341,7 +346,7 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(const TA *__restric
                 const uint32_t hi = (cok && row + 1 < rows) ? raw_bf16(ra[1], e) : 0u;
                 const int lc = 8 * cg + e;                     // column within the strip
                 const int q = (bp >> 2) ^ ((lc >> 4) & 3);     // swizzled quad
-                lds[(s * kLpTile + lc) * kLpTWords + 4 * q + (bp & 3)] = lo | (hi << 16);
+                lds[(s * TILE + lc) * kLpTWords + 4 * q + (bp & 3)] = lo | (hi << 16);
             }
         } else {
 #pragma unroll
@@ -352,19 +357,19 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(const TA *__restric
                 float v[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) v[e] = (row < rows && col + e < c) ? raw_f32(ra[h], e) : 0.0f;
-                float *dst = reinterpret_cast<float *>(lds) + (s * kLpRows + tid / 16) * kLpFStride + 8 * cg;
+                float *dst = reinterpret_cast<float *>(lds) + (s * kLpRows + tid / CG) * FSTRIDE + 8 * cg;
                 *reinterpret_cast<v4f *>(dst) = (v4f){v[0], v[1], v[2], v[3]};
                 *reinterpret_cast<v4f *>(dst + 4) = (v4f){v[4], v[5], v[6], v[7]};
             }
         }
     };
 
-    v4f acc[2][4];
-    double accd[2][4][4];
+    v4f acc[2][NBB];
+    double accd[2][NBB][4];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < NBB; ++b) {
             acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int v = 0; v < 4; ++v) accd[a][b][v] = 0.0;
@@ -380,7 +385,7 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(const TA *__restric
         if (r0 + kLpRows < rows) issue(r0 + kLpRows);
         if (!active) continue;
         if constexpr (BF16) {
-            v8bf fa[2], fb[4];
+            v8bf fa[2], fb[NBB];
             const int g = lane / 16;
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
@@ -389,31 +394,31 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(const TA *__restric
                     lds + ca * kLpTWords + 4 * (g ^ ((ca >> 4) & 3))));
             }
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int cb2 = wc * 64 + 16 * b + lane % 16;
+            for (int b = 0; b < NBB; ++b) {
+                const int cb2 = wc * 16 * NBB + 16 * b + lane % 16;
                 fb[b] = __builtin_bit_cast(v8bf, *reinterpret_cast<const u32x4 *>(
-                    lds + (sj * kLpTile + cb2) * kLpTWords + 4 * (g ^ ((cb2 >> 4) & 3))));
+                    lds + (sj * TILE + cb2) * kLpTWords + 4 * (g ^ ((cb2 >> 4) & 3))));
             }
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
+                for (int b = 0; b < NBB; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
         } else {
             const float *F = reinterpret_cast<const float *>(lds);
 #pragma unroll 2
             for (int st = 0; st < kLpRows / 4; ++st) {
                 const int rr = 4 * st + lane / 16;
-                float fa[2], fb[4];
+                float fa[2], fb[NBB];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) fa[a] = F[rr * kLpFStride + wr * 32 + 16 * a + lane % 16];
+                for (int a = 0; a < 2; ++a) fa[a] = F[rr * FSTRIDE + wr * 32 + 16 * a + lane % 16];
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    fb[b] = F[(sj * kLpRows + rr) * kLpFStride + wc * 64 + 16 * b + lane % 16];
+                for (int b = 0; b < NBB; ++b)
+                    fb[b] = F[(sj * kLpRows + rr) * FSTRIDE + wc * 16 * NBB + 16 * b + lane % 16];
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
+                    for (int b = 0; b < NBB; ++b)
                         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
             }
         }
@@ -421,7 +426,7 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(const TA *__restric
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
+                for (int b = 0; b < NBB; ++b) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) accd[a][b][v] += (double)acc[a][b][v];
                     acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
@@ -435,14 +440,14 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(const TA *__restric
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int A = 2 * wr + a, B = 4 * wc + b;
+        for (int b = 0; b < NBB; ++b) {
+            const int A = 2 * wr + a, B = NBB * wc + b;
             if (diag && A > B) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * A + 4 * (lane / 16) + v, j = 16 * B + lane % 16;
                 if (diag && A == B && i > j) continue;
-                const int I = ti * kLpTile + i, J = tj * kLpTile + j;
+                const int I = ti * TILE + i, J = tj * TILE + j;
                 if (I < c && J < c) {
                     G[(int64_t)I * c + J] = accd[a][b][v];
                     G[(int64_t)J * c + I] = accd[a][b][v];
@@ -451,20 +456,37 @@ __global__ __launch_bounds__(kLpThreads) void gram_lp_kernel(const TA *__restric
         }
 }
 
-template <bool BF16, typename TA>
-void run_gram_lp(const TA *X, int64_t ld, int c, const Chunk *chunks, int nchunks, double *Gpart,
-                 hipStream_t stream)
+template <int TILE, bool BF16, typename TA>
+void run_gram_lp_t(const TA *X, int64_t ld, int c, const Chunk *chunks, int nchunks, double *Gpart,
+                   hipStream_t stream)
 {
-    const int ntile = (c + kLpTile - 1) / kLpTile;
+    const int ntile = (c + TILE - 1) / TILE;
     const int npairs = ntile * (ntile + 1) / 2;
     const int per = (nchunks + kXcdsGram - 1) / kXcdsGram;
     const unsigned grid = (unsigned)(kXcdsGram * per * npairs);
     const bool vec = c % 8 == 0 && (ld * (int64_t)sizeof(TA)) % 16 == 0 &&
                      reinterpret_cast<uintptr_t>(X) % 16 == 0;
     if (vec)
-        gram_lp_kernel<BF16, TA, true><<<grid, kLpThreads, 0, stream>>>(X, ld, c, chunks, nchunks, npairs, Gpart);
+        gram_lp_kernel<TILE, BF16, TA, true><<<grid, TILE * 4, 0, stream>>>(X, ld, c, chunks, nchunks,
+                                                                           npairs, Gpart);
     else
-        gram_lp_kernel<BF16, TA, false><<<grid, kLpThreads, 0, stream>>>(X, ld, c, chunks, nchunks, npairs, Gpart);
+        gram_lp_kernel<TILE, BF16, TA, false><<<grid, TILE * 4, 0, stream>>>(X, ld, c, chunks, nchunks,
+                                                                            npairs, Gpart);
+}
+
+// Tile edge chosen by the autotuner (same bits either way).
+template <bool BF16, typename TA>
+hipError_t run_gram_lp(const TA *X, int64_t ld, int c, const Chunk *chunks, int nchunks, double *Gpart,
+                       hipStream_t stream)
+{
+    char key[96];
+    snprintf(key, sizeof key, "%s/%d c=%d n=%d", BF16 ? "bf16" : "f32", (int)sizeof(TA), c,
+             tune_bucket(nchunks));
+    return tuned_launch("gram_lp_tile", key, 2, 0, stream, [&](int v) {
+        if (v == 0) run_gram_lp_t<128, BF16>(X, ld, c, chunks, nchunks, Gpart, stream);
+        else run_gram_lp_t<64, BF16>(X, ld, c, chunks, nchunks, Gpart, stream);
+        return hipGetLastError();
+    });
 }
 
 template <typename TA>
@@ -502,14 +524,17 @@ hipError_t launch_gram(const void *X, int x_type, int64_t ld, int c, const Chunk
     // (exact products); FP32 mode rounds wider input to FP32
     const bool bf = prec == kGramBF16 || (prec == kGramF32 && x_type == kElemBF16);
     if (prec != kGramF64) {
+        hipError_t e;
         if (x_type == kElemBF16)
-            run_gram_lp<true>(static_cast<const uint16_t *>(X), ld, c, chunks, nchunks, Gpart, stream);
+            e = run_gram_lp<true>(static_cast<const uint16_t *>(X), ld, c, chunks, nchunks, Gpart, stream);
         else if (x_type == kElemF32)
-            bf ? run_gram_lp<true>(static_cast<const float *>(X), ld, c, chunks, nchunks, Gpart, stream)
-               : run_gram_lp<false>(static_cast<const float *>(X), ld, c, chunks, nchunks, Gpart, stream);
+            e = bf ? run_gram_lp<true>(static_cast<const float *>(X), ld, c, chunks, nchunks, Gpart, stream)
+                   : run_gram_lp<false>(static_cast<const float *>(X), ld, c, chunks, nchunks, Gpart, stream);
         else
-            bf ? run_gram_lp<true>(static_cast<const double *>(X), ld, c, chunks, nchunks, Gpart, stream)
-               : run_gram_lp<false>(static_cast<const double *>(X), ld, c, chunks, nchunks, Gpart, stream);
+            e = bf ? run_gram_lp<true>(static_cast<const double *>(X), ld, c, chunks, nchunks, Gpart, stream)
+                   : run_gram_lp<false>(static_cast<const double *>(X), ld, c, chunks, nchunks, Gpart, stream);
+        timing_end("gram", stream);
+        return e;
     } else if (x_type == kElemF32)
         run_gram(static_cast<const float *>(X), ld, c, chunks, nchunks, Gpart, stream);
     else if (x_type == kElemBF16)

@@ -13,6 +13,8 @@
 //    per query and is bound by memory bandwidth.
 #include "zs_internal.h"
 
+#include <cstdio>
+
 namespace zs {
 namespace {
 
@@ -229,7 +231,7 @@ template <int KM, bool CONTIG, typename TU>
 __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, const Piece *__restrict__ pieces,
                                                               const int32_t *__restrict__ perm, int npieces,
                                                               const double *__restrict__ C,
-                                                              TU *__restrict__ Uout)
+                                                              TU *__restrict__ Uout, int xcd)
 {
     constexpr int KS = KM / 4;                     // MFMA steps over l
     constexpr int NCB = (KM + 15) / 16;            // 16-column blocks (k_q <= k <= KM)
@@ -243,7 +245,7 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
     constexpr int NFA = NF > 0 ? NF : 1;
     extern __shared__ __align__(16) double tile[];    // 64 x KM
     const int per = (npieces + kXcds - 1) / kXcds;
-    const int pos = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+    const int pos = xcd ? (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds) : (int)blockIdx.x;
     if (pos >= npieces) return;
     const Piece pc = pieces[perm[pos]];
     const int k = st.k;
@@ -399,6 +401,9 @@ hipError_t launch_coef(int k, int kq_max, const Piece *pieces, const StackChunk 
     return e;
 }
 
+// Work order: block-major positions dealt to the XCDs in runs (0) or in
+// dispatch order (1); each piece's outputs are the same bits either way, so
+// the autotuner picks per shape.
 template <int KM, typename TU>
 hipError_t run_blockprod(StoreView st, const Piece *pieces, const int32_t *perm, int npieces,
                          const double *C, void *U, bool contiguous, hipStream_t stream)
@@ -406,11 +411,19 @@ hipError_t run_blockprod(StoreView st, const Piece *pieces, const int32_t *perm,
     const size_t lds = (size_t)kProdRows * KM * sizeof(double);
     const unsigned grid = (unsigned)(kXcds * ((npieces + kXcds - 1) / kXcds));
     TU *out = static_cast<TU *>(U);
-    if (contiguous)
-        blockprod_kernel<KM, true, TU><<<grid, kProdRows, lds, stream>>>(st, pieces, perm, npieces, C, out);
-    else
-        blockprod_kernel<KM, false, TU><<<grid, kProdRows, lds, stream>>>(st, pieces, perm, npieces, C, out);
-    return hipGetLastError();
+    char key[80];
+    snprintf(key, sizeof key, "k=%d f32=%d contig=%d n=%d", st.k, (int)(sizeof(TU) == 4),
+             (int)contiguous, tune_bucket(npieces));
+    return tuned_launch("blockprod_order", key, 2, 0, stream, [&](int v) {
+        const int xcd = v == 0 ? 1 : 0;
+        if (contiguous)
+            blockprod_kernel<KM, true, TU><<<grid, kProdRows, lds, stream>>>(st, pieces, perm, npieces, C,
+                                                                           out, xcd);
+        else
+            blockprod_kernel<KM, false, TU><<<grid, kProdRows, lds, stream>>>(st, pieces, perm, npieces, C,
+                                                                            out, xcd);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_order_pieces(const Piece *pieces, int npieces, int64_t nb, const int32_t *boff,

@@ -163,6 +163,58 @@ struct SinglePlan {
 hipError_t noalloc_scratch(void **ptr);
 hipError_t launch_plan_single(const SinglePlan &p, hipStream_t stream);
 
+// ------------------------------------------------------------- autotuner
+// Launch variants of one site compute the same bits; the tuner picks the
+// fastest per shape key (tune.cpp).
+int tune_bucket(int64_t n);              // n rounded up to a power of two
+bool tune_enabled();
+void tune_suspend(bool on);              // this thread times nothing while set
+bool tune_suspended();
+int tune_lookup(const char *site, const char *key);   // -1: not chosen yet
+void tune_record(const char *site, const char *key, int choice, const float *ms, int n);
+bool stream_capturing(hipStream_t stream);
+
+// Launches variant `run(v)` of a site: the cached choice, else (tuning on and
+// the stream not capturing) every variant once, timed with events, keeping
+// the fastest; else the default.  Every variant leaves the same outputs, so
+// the outputs are valid after the timed runs.
+template <class F>
+hipError_t tuned_launch(const char *site, const char *key, int ncand, int dflt, hipStream_t stream,
+                        F &&run)
+{
+    const int known = tune_lookup(site, key);
+    if (known >= 0 && known < ncand) return run(known);
+    if (ncand < 2 || !tune_enabled() || stream_capturing(stream)) return run(dflt);
+    constexpr int kMaxCand = 4;
+    if (ncand > kMaxCand) ncand = kMaxCand;
+    hipEvent_t ev[kMaxCand + 1];
+    int made = 0;
+    hipError_t e = hipSuccess;
+    for (; made <= ncand && e == hipSuccess; ++made) e = hipEventCreate(&ev[made]);
+    if (e != hipSuccess) {
+        for (int i = 0; i + 1 < made; ++i) (void)hipEventDestroy(ev[i]);
+        (void)hipGetLastError();
+        return run(dflt);
+    }
+    float ms[kMaxCand] = {0};
+    e = hipEventRecord(ev[0], stream);
+    for (int v = 0; v < ncand && e == hipSuccess; ++v) {
+        e = run(v);
+        if (e == hipSuccess) e = hipEventRecord(ev[v + 1], stream);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(ev[ncand]);
+    int best = dflt;
+    if (e == hipSuccess) {
+        for (int v = 0; v < ncand; ++v) (void)hipEventElapsedTime(&ms[v], ev[v], ev[v + 1]);
+        best = 0;
+        for (int v = 1; v < ncand; ++v)
+            if (ms[v] < ms[best]) best = v;
+        tune_record(site, key, best, ms, ncand);
+    }
+    for (int i = 0; i <= ncand; ++i) (void)hipEventDestroy(ev[i]);
+    return e;
+}
+
 // ---------------------------------------------------------------- launches
 // All launches are asynchronous on `stream` and return the launch status.
 // Arithmetic of the block Gram: FP64 (FP64 mode, and every Gram of stored

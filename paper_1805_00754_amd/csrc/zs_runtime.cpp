@@ -548,6 +548,238 @@ zs_status check_query(const zs_store *st, int64_t ts, int64_t te, int32_t kq)
     return ZS_OK;
 }
 
+// ------------------------------------------------------------ storage phase
+// The storage phase is split into its plan (argument checks, allocation, work
+// lists, descriptor upload) and its launches (kernels only, no host
+// synchronisation and no allocation), so that the launches can be captured
+// into a graph (zs_store_graph_create).
+
+zs_status check_store_args(const void *A, int64_t t, int64_t c, int64_t lda, zs_dtype a_type,
+                           int64_t b, int32_t k, zs_mode mode, double xi, void *out)
+{
+    if (!out) return fail(ZS_EINVAL, "out is null");
+    if (!(xi >= 0.0 && xi <= 1.0)) return fail(ZS_EINVAL, "xi = %g outside [0, 1]", xi);
+    if (!A) return fail(ZS_EINVAL, "A is null");
+    if (t < 1) return fail(ZS_EINVAL, "t = %lld < 1", (long long)t);
+    if (c < 1) return fail(ZS_EINVAL, "c = %lld < 1", (long long)c);
+    if (lda < c) return fail(ZS_EINVAL, "lda = %lld < c = %lld", (long long)lda, (long long)c);
+    if (b < 1) return fail(ZS_EINVAL, "b = %lld < 1", (long long)b);
+    if (k < 1 || k > c) return fail(ZS_EINVAL, "k = %d outside [1, c = %lld]", k, (long long)c);
+    if (c > ZS_MAX_C) return fail(ZS_EUNSUPPORTED, "c = %lld > %d", (long long)c, ZS_MAX_C);
+    if (k > ZS_MAX_K) return fail(ZS_EUNSUPPORTED, "k = %d > %d", k, ZS_MAX_K);
+    if (a_type != ZS_F64 && a_type != ZS_F32 && a_type != ZS_BF16)
+        return fail(ZS_EINVAL, "a_type %d is not a zs_dtype", (int)a_type);
+    if (mode != ZS_MODE_FP64 && mode != ZS_MODE_FP32 && mode != ZS_MODE_BF16)
+        return fail(ZS_EINVAL, "mode %d is not a zs_mode", (int)mode);
+    if (b > (int64_t)1 << 30) return fail(ZS_EINVAL, "b too large");
+    return ZS_OK;
+}
+
+// A new store with its device arrays (factors, Gram tree, status flag) in one
+// allocation; the status flag is cleared on `stream`.
+zs_status new_store(int64_t t, int64_t c, int64_t b, int32_t k, zs_mode mode, double xi,
+                    hipStream_t stream, zs_store **pst)
+{
+    zs_store *st = new zs_store();
+    st->t = t; st->c = c; st->b = b; st->k = k; st->mode = mode;
+    st->xi = xi > 0.0 && xi < 1.0 ? xi : 0.0;
+    st->f32 = mode == ZS_MODE_FP64 ? 0 : 1;
+    st->nb = (t + b - 1) / b;
+    const int64_t nb = st->nb;
+    auto bail = [&](zs_status s) {
+        zs_store_free(st);
+        return s;
+    };
+    if (hipGetDevice(&st->device) != hipSuccess) return bail(fail(ZS_EDEVICE, "no HIP device"));
+    while (st->n2 < nb) st->n2 *= 2;
+    const size_t sz[6] = {st->esize() * t * k, st->esize() * nb * k * c, sizeof(double) * nb * k,
+                          sizeof(int32_t) * nb, sizeof(double) * 2 * st->n2 * c * c, sizeof(int)};
+    size_t off[6], total = 0;
+    for (int i = 0; i < 6; ++i) {
+        off[i] = total;
+        total = align_up(total + sz[i], 256);
+    }
+    hipError_t e = hipMalloc(&st->base, total);
+    if (e != hipSuccess)
+        return bail(fail(e == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "store arrays: %s",
+                         hipGetErrorString(e)));
+    char *p = static_cast<char *>(st->base);
+    st->U = p + off[0];
+    st->Vt = p + off[1];
+    st->S = reinterpret_cast<double *>(p + off[2]);
+    st->kvec = reinterpret_cast<int32_t *>(p + off[3]);
+    st->tree = reinterpret_cast<double *>(p + off[4]);
+    st->conv = reinterpret_cast<int *>(p + off[5]);
+    e = hipMemsetAsync(st->conv, 0, sizeof(int), stream);
+    if (e != hipSuccess) return bail(fail(ZS_EDEVICE, "status flag: %s", hipGetErrorString(e)));
+    *pst = st;
+    return ZS_OK;
+}
+
+// What the launches of a planned storage phase need besides the workspace.
+struct StorePlan {
+    const void *A = nullptr;
+    int64_t lda = 0;
+    int x_type = kElemF64, gprec = kGramF64;
+    int nchunks = 0, npchunks = 0;
+    const Chunk *chunks = nullptr, *pchunks = nullptr, *leaf = nullptr;
+    const Prob *probs = nullptr;
+    const double *const *gsrc = nullptr;
+    double *Y = nullptr;
+};
+
+// Work lists of the storage phase of `st` from A, scratch sized in `sw`, and
+// the descriptors uploaded on `stream` (synchronously when `sync_upload`).
+// Work lists: one problem per block.  The Gram works on chunks of at most
+// kStoreChunkRows rows (one c x c partial Gram each; one chunk per block for
+// c > 128); the projection and the U formation on chunks of kProjChunkRows
+// rows (one wave each, one k x k partial G_Y each).
+zs_status store_plan(zs_store *st, const void *A, int64_t lda, zs_dtype a_type, StoreWork &sw,
+                     hipStream_t stream, bool sync_upload, StorePlan &pl)
+{
+    const int64_t t = st->t, c = st->c, b = st->b, k = st->k, nb = st->nb;
+    std::vector<Chunk> chunks, pchunks;
+    std::vector<Prob> probs(nb);
+    int32_t slot = 0, pslot = 0;
+    for (int64_t i = 0; i < nb; ++i) {
+        const int64_t rows = st->block_rows(i);
+        Prob pr;
+        std::memset(&pr, 0, sizeof pr);
+        pr.g0 = slot;
+        pr.y0 = pslot;
+        const int64_t crows = c > kMaxC ? std::max<int64_t>(kStoreChunkRowsWide, b) : kStoreChunkRows;
+        for (int64_t r = 0; r < rows; r += crows) {
+            Chunk ch;
+            ch.x_off = (i * b + r) * lda;
+            ch.y_off = (i * b + r) * k;
+            ch.rows = (int32_t)std::min<int64_t>(crows, rows - r);
+            ch.prob = (int32_t)i;
+            ch.slot = slot++;
+            ch.kk = (int32_t)k;
+            chunks.push_back(ch);
+        }
+        for (int64_t r = 0; r < rows; r += kProjChunkRows) {
+            Chunk ch;
+            ch.x_off = (i * b + r) * lda;
+            ch.y_off = (i * b + r) * k;
+            ch.rows = (int32_t)std::min<int64_t>(kProjChunkRows, rows - r);
+            ch.prob = (int32_t)i;
+            ch.slot = pslot++;
+            ch.kk = (int32_t)k;
+            pchunks.push_back(ch);
+        }
+        pr.ng = slot - pr.g0;
+        pr.ny = pslot - pr.y0;
+        pr.kk = (int32_t)k;
+        pr.v_dst = static_cast<char *>(st->Vt) + i * k * c * (int64_t)st->esize();  // V_(i)^T
+        pr.v_f32 = st->f32;                 // element (a, j) at j * c + a
+        pr.v_rs = 1;
+        pr.v_cs = c;
+        pr.s_dst = st->S + i * k;
+        pr.k_dst = st->kvec + i;
+        probs[i] = pr;
+    }
+    pl.nchunks = (int)chunks.size();
+    pl.npchunks = (int)pchunks.size();
+    HIP_TRY(sw.Gpart.ensure(sizeof(double) * (size_t)pl.nchunks * c * c));
+    HIP_TRY(sw.Vk.ensure(sizeof(double) * (size_t)nb * c * kMaxK));
+    HIP_TRY(sw.GY.ensure(sizeof(double) * (size_t)pl.npchunks * kSlotK));
+    HIP_TRY(sw.F.ensure(sizeof(double) * (size_t)nb * kSlotK));
+    // Y = A V_k in FP64: in place in U for an FP64 store, in scratch otherwise
+    if (st->f32) HIP_TRY(sw.Ysc.ensure(sizeof(double) * (size_t)t * k));
+    pl.Y = st->f32 ? sw.Ysc.as<double>() : static_cast<double *>(st->U);
+    HIP_TRY(sw.Big.ensure(sizeof(double) * std::max<size_t>(1, big_doubles(c, nb))));
+    if (c > kMaxC) HIP_TRY(sw.Rows.ensure(sizeof(double) * (size_t)nb * k * c));
+    std::vector<const double *> gsrc(pl.nchunks);
+    for (int s2 = 0; s2 < pl.nchunks; ++s2) gsrc[s2] = sw.Gpart.as<double>() + (int64_t)s2 * c * c;
+    std::vector<Chunk> leaf_chunks;           // c > 128: block i's k scaled rows -> leaf i
+    if (c > kMaxC) {
+        for (int64_t i = 0; i < nb; ++i) {
+            Chunk ch;
+            ch.x_off = i * k * c;
+            ch.y_off = 0;
+            ch.rows = (int32_t)k;
+            ch.prob = (int32_t)i;
+            ch.slot = (int32_t)i;
+            ch.kk = (int32_t)k;
+            leaf_chunks.push_back(ch);
+        }
+    }
+    Blob blob;
+    const size_t o_chunks = blob.add(chunks), o_probs = blob.add(probs), o_gsrc = blob.add(gsrc);
+    const size_t o_leaf = blob.add(leaf_chunks), o_pchunks = blob.add(pchunks);
+    HIP_TRY(sw.desc.ensure(blob.bytes.size()));
+    if (sync_upload)
+        HIP_TRY(hipMemcpy(sw.desc.p, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice));
+    else
+        HIP_TRY(hipMemcpyAsync(sw.desc.p, blob.bytes.data(), blob.bytes.size(),
+                               hipMemcpyHostToDevice, stream));
+    const char *d = sw.desc.as<char>();
+    pl.chunks = (const Chunk *)(d + o_chunks);
+    pl.probs = (const Prob *)(d + o_probs);
+    pl.gsrc = (const double *const *)(d + o_gsrc);
+    pl.leaf = (const Chunk *)(d + o_leaf);
+    pl.pchunks = (const Chunk *)(d + o_pchunks);
+    pl.A = A;
+    pl.lda = lda;
+    pl.x_type = a_type == ZS_F32 ? kElemF32 : a_type == ZS_BF16 ? kElemBF16 : kElemF64;
+    // the bulk Gram in the mode's arithmetic; everything after it in FP64
+    pl.gprec = st->mode == ZS_MODE_FP32 ? kGramF32 : st->mode == ZS_MODE_BF16 ? kGramBF16 : kGramF64;
+    if (!sync_upload) HIP_TRY(hipStreamSynchronize(stream));   // the host blob goes out of scope
+    return ZS_OK;
+}
+
+// Enqueues the kernels of a planned storage phase on `stream`.
+hipError_t store_kernels(zs_store *st, const StorePlan &pl, StoreWork &sw, hipStream_t stream)
+{
+    const int64_t c = st->c, k = st->k, nb = st->nb;
+#define SK_TRY(expr)                    \
+    do {                                \
+        hipError_t e_ = (expr);         \
+        if (e_ != hipSuccess) return e_; \
+    } while (0)
+    SK_TRY(launch_gram(pl.A, pl.x_type, pl.lda, (int)c, pl.chunks, pl.nchunks, sw.Gpart.as<double>(),
+                       stream, pl.gprec));
+    SK_TRY(first_stage_eig((int)c, (int)k, pl.probs, (int)nb, pl.gsrc, nullptr, sw.Vk.as<double>(),
+                           sw.Big.as<double>(), stream));
+    SK_TRY(launch_project(pl.A, pl.x_type, pl.lda, (int)c, pl.pchunks, pl.npchunks, (int)k,
+                          sw.Vk.as<double>(), pl.Y, sw.GY.as<double>(), stream));
+    SK_TRY(launch_finalize((int)c, (int)k, pl.probs, (int)nb, (int)k, sw.GY.as<double>(),
+                           sw.Vk.as<double>(), sw.F.as<double>(), st->rank_tol(), pl.gsrc, nullptr,
+                           st->xi, st->conv, stream));
+    SK_TRY(launch_utransform(pl.Y, st->U, st->f32, (int)k, pl.pchunks, pl.npchunks, sw.F.as<double>(),
+                             stream));
+    // Gram tree over the stored blocks: leaves, then one launch per level.  For
+    // c > 128 a leaf is the Gram of the block's rows sigma_ij v_ij^T, formed by
+    // the Gram kernel (one chunk of k rows per block); leaves past nb are zero.
+    if (c <= kMaxC) {
+        SK_TRY(launch_leaf_gram(st->view(), st->n2, st->tree, st->n2, stream));
+    } else {
+        SK_TRY(launch_scale_rows(st->view(), nb, sw.Rows.as<double>(), stream));
+        double *leaves = st->tree + st->n2 * c * c;
+        SK_TRY(launch_gram(sw.Rows.as<double>(), kElemF64, c, (int)c, pl.leaf, (int)nb, leaves,
+                           stream));
+        SK_TRY(launch_zero(leaves + nb * c * c, (st->n2 - nb) * c * c, stream));
+    }
+    for (int64_t lev = st->n2 / 2; lev >= 1; lev /= 2)
+        SK_TRY(launch_tree_level((int)c, st->tree, lev, lev, stream));
+#undef SK_TRY
+    return hipSuccess;
+}
+
+// Reads and clears the store's Jacobi status flag (the stream has synchronised).
+zs_status take_conv(zs_store *st, const char *what)
+{
+    int conv = 0;
+    HIP_TRY(hipMemcpy(&conv, st->conv, sizeof(int), hipMemcpyDeviceToHost));
+    if (conv) {
+        int zero = 0;
+        (void)hipMemcpy(st->conv, &zero, sizeof(int), hipMemcpyHostToDevice);
+        return fail(ZS_ENOCONV, "%s", what);
+    }
+    return ZS_OK;
+}
+
 }  // namespace
 
 // =============================================================== C ABI
@@ -567,200 +799,31 @@ zs_status zs_store_blocks_xi(const void *A, int64_t t, int64_t c, int64_t lda, z
                              int64_t b, int32_t k, zs_mode mode, double xi, hipStream_t stream,
                              zs_store **out)
 {
-    if (!out) return fail(ZS_EINVAL, "out is null");
-    if (!(xi >= 0.0 && xi <= 1.0)) return fail(ZS_EINVAL, "xi = %g outside [0, 1]", xi);
-    *out = nullptr;
-    if (!A) return fail(ZS_EINVAL, "A is null");
-    if (t < 1) return fail(ZS_EINVAL, "t = %lld < 1", (long long)t);
-    if (c < 1) return fail(ZS_EINVAL, "c = %lld < 1", (long long)c);
-    if (lda < c) return fail(ZS_EINVAL, "lda = %lld < c = %lld", (long long)lda, (long long)c);
-    if (b < 1) return fail(ZS_EINVAL, "b = %lld < 1", (long long)b);
-    if (k < 1 || k > c) return fail(ZS_EINVAL, "k = %d outside [1, c = %lld]", k, (long long)c);
-    if (c > ZS_MAX_C) return fail(ZS_EUNSUPPORTED, "c = %lld > %d", (long long)c, ZS_MAX_C);
-    if (k > ZS_MAX_K) return fail(ZS_EUNSUPPORTED, "k = %d > %d", k, ZS_MAX_K);
-    if (a_type != ZS_F64 && a_type != ZS_F32 && a_type != ZS_BF16)
-        return fail(ZS_EINVAL, "a_type %d is not a zs_dtype", (int)a_type);
-    if (mode != ZS_MODE_FP64 && mode != ZS_MODE_FP32 && mode != ZS_MODE_BF16)
-        return fail(ZS_EINVAL, "mode %d is not a zs_mode", (int)mode);
-    if (b > (int64_t)1 << 30) return fail(ZS_EINVAL, "b too large");
-
-    zs_store *st = new zs_store();
-    st->t = t; st->c = c; st->b = b; st->k = k; st->mode = mode;
-    st->xi = xi > 0.0 && xi < 1.0 ? xi : 0.0;
-    st->f32 = mode == ZS_MODE_FP64 ? 0 : 1;
-    st->nb = (t + b - 1) / b;
-    const int64_t nb = st->nb;
-    auto cleanup = [&](zs_status s) {
-        zs_store_free(st);
-        return s;
-    };
-    if (hipGetDevice(&st->device) != hipSuccess) return cleanup(fail(ZS_EDEVICE, "no HIP device"));
-#define ST_TRY(expr)                                                                        \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return cleanup(fail(e_ == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "%s: %s", \
-                                #expr, hipGetErrorString(e_)));                             \
-    } while (0)
-    // the store's arrays share one allocation (one driver call per store)
-    while (st->n2 < nb) st->n2 *= 2;
-    {
-        const size_t sz[6] = {st->esize() * t * k, st->esize() * nb * k * c, sizeof(double) * nb * k,
-                              sizeof(int32_t) * nb, sizeof(double) * 2 * st->n2 * c * c, sizeof(int)};
-        size_t off[6], total = 0;
-        for (int i = 0; i < 6; ++i) {
-            off[i] = total;
-            total = align_up(total + sz[i], 256);
-        }
-        ST_TRY(hipMalloc(&st->base, total));
-        char *p = static_cast<char *>(st->base);
-        st->U = p + off[0];
-        st->Vt = p + off[1];
-        st->S = reinterpret_cast<double *>(p + off[2]);
-        st->kvec = reinterpret_cast<int32_t *>(p + off[3]);
-        st->tree = reinterpret_cast<double *>(p + off[4]);
-        st->conv = reinterpret_cast<int *>(p + off[5]);
-    }
-    ST_TRY(hipMemsetAsync(st->conv, 0, sizeof(int), stream));
-
-    // Work lists: one problem per block.  The Gram works on chunks of at most
-    // kStoreChunkRows rows (one c x c partial Gram each); the projection and the
-    // U formation on chunks of kProjChunkRows rows (one wave each, one k x k
-    // partial G_Y each).
-    std::vector<Chunk> chunks, pchunks;
-    std::vector<Prob> probs(nb);
-    int32_t slot = 0, pslot = 0;
-    for (int64_t i = 0; i < nb; ++i) {
-        const int64_t rows = st->block_rows(i);
-        Prob pr;
-        std::memset(&pr, 0, sizeof pr);
-        pr.g0 = slot;
-        pr.y0 = pslot;
-        // one chunk per block for c > 128 (each chunk holds a c x c partial Gram)
-        const int64_t crows = c > kMaxC ? std::max<int64_t>(kStoreChunkRowsWide, b) : kStoreChunkRows;
-        for (int64_t r = 0; r < rows; r += crows) {
-            Chunk ch;
-            ch.x_off = (i * b + r) * lda;
-            ch.y_off = (i * b + r) * k;
-            ch.rows = (int32_t)std::min<int64_t>(crows, rows - r);
-            ch.prob = (int32_t)i;
-            ch.slot = slot++;
-            ch.kk = k;
-            chunks.push_back(ch);
-        }
-        for (int64_t r = 0; r < rows; r += kProjChunkRows) {
-            Chunk ch;
-            ch.x_off = (i * b + r) * lda;
-            ch.y_off = (i * b + r) * k;
-            ch.rows = (int32_t)std::min<int64_t>(kProjChunkRows, rows - r);
-            ch.prob = (int32_t)i;
-            ch.slot = pslot++;
-            ch.kk = k;
-            pchunks.push_back(ch);
-        }
-        pr.ng = slot - pr.g0;
-        pr.ny = pslot - pr.y0;
-        pr.kk = k;
-        pr.v_dst = static_cast<char *>(st->Vt) + i * k * c * (int64_t)st->esize();  // V_(i)^T
-        pr.v_f32 = st->f32;                 // element (a, j) at j * c + a
-        pr.v_rs = 1;
-        pr.v_cs = c;
-        pr.s_dst = st->S + i * k;
-        pr.k_dst = st->kvec + i;
-        probs[i] = pr;
-    }
-    const int nchunks = (int)chunks.size();
-    const int npchunks = (int)pchunks.size();
+    if (out) *out = nullptr;
+    zs_status s = check_store_args(A, t, c, lda, a_type, b, k, mode, xi, out);
+    if (s != ZS_OK) return s;
+    zs_store *st = nullptr;
+    s = new_store(t, c, b, k, mode, xi, stream, &st);
+    if (s != ZS_OK) return s;
     StoreWork *sw = store_work(st->device, stream);
     std::lock_guard<std::mutex> swlk(sw->mu);
-    DevBuf &Gpart = sw->Gpart, &Vk = sw->Vk, &GY = sw->GY, &F = sw->F, &Ysc = sw->Ysc,
-           &Big = sw->Big, &Rows = sw->Rows, &desc = sw->desc;
     // the workspace stays allocated; on an error the stream is drained so that
     // no kernel of this call still uses it when the next call reuses it
-    auto release = [&]() { (void)hipStreamSynchronize(stream); };
-#define ST_TRY2(expr)                                                                       \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess) {                                                             \
-            release();                                                                      \
-            return cleanup(fail(e_ == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "%s: %s", \
-                                #expr, hipGetErrorString(e_)));                             \
-        }                                                                                   \
-    } while (0)
-    ST_TRY2(Gpart.ensure(sizeof(double) * (size_t)nchunks * c * c));
-    ST_TRY2(Vk.ensure(sizeof(double) * (size_t)nb * c * kMaxK));
-    ST_TRY2(GY.ensure(sizeof(double) * (size_t)npchunks * kSlotK));
-    ST_TRY2(F.ensure(sizeof(double) * (size_t)nb * kSlotK));
-    // Y = A V_k in FP64: in place in U for an FP64 store, in scratch otherwise
-    if (st->f32) ST_TRY2(Ysc.ensure(sizeof(double) * (size_t)t * k));
-    double *Y = st->f32 ? Ysc.as<double>() : static_cast<double *>(st->U);
-    std::vector<const double *> gsrc(nchunks);
-    for (int s2 = 0; s2 < nchunks; ++s2) gsrc[s2] = Gpart.as<double>() + (int64_t)s2 * c * c;
-    std::vector<Chunk> leaf_chunks;           // c > 128: block i's k scaled rows -> leaf i
-    if (c > kMaxC) {
-        for (int64_t i = 0; i < nb; ++i) {
-            Chunk ch;
-            ch.x_off = i * k * c;
-            ch.y_off = 0;
-            ch.rows = k;
-            ch.prob = (int32_t)i;
-            ch.slot = (int32_t)i;
-            ch.kk = k;
-            leaf_chunks.push_back(ch);
-        }
-    }
-    Blob blob;
-    const size_t o_chunks = blob.add(chunks), o_probs = blob.add(probs), o_gsrc = blob.add(gsrc);
-    const size_t o_leaf = blob.add(leaf_chunks), o_pchunks = blob.add(pchunks);
-    ST_TRY2(desc.ensure(blob.bytes.size()));
-    ST_TRY2(hipMemcpyAsync(desc.p, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice,
-                           stream));
-    const Chunk *d_chunks = (const Chunk *)(desc.as<char>() + o_chunks);
-    const Prob *d_probs = (const Prob *)(desc.as<char>() + o_probs);
-    const double *const *d_gsrc = (const double *const *)(desc.as<char>() + o_gsrc);
-    const Chunk *d_leaf_chunks = (const Chunk *)(desc.as<char>() + o_leaf);
-    const Chunk *d_pchunks = (const Chunk *)(desc.as<char>() + o_pchunks);
-    const int x_type = a_type == ZS_F32 ? kElemF32 : a_type == ZS_BF16 ? kElemBF16 : kElemF64;
-    ST_TRY2(Big.ensure(sizeof(double) * std::max<size_t>(1, big_doubles(c, nb))));
-    // the bulk Gram in the mode's arithmetic; everything after it in FP64
-    const int gprec = mode == ZS_MODE_FP32 ? kGramF32 : mode == ZS_MODE_BF16 ? kGramBF16 : kGramF64;
-    ST_TRY2(launch_gram(A, x_type, lda, (int)c, d_chunks, nchunks, Gpart.as<double>(), stream, gprec));
-    ST_TRY2(first_stage_eig((int)c, k, d_probs, (int)nb, d_gsrc, nullptr, Vk.as<double>(),
-                            Big.as<double>(), stream));
-    ST_TRY2(launch_project(A, x_type, lda, (int)c, d_pchunks, npchunks, k, Vk.as<double>(), Y,
-                           GY.as<double>(), stream));
-    ST_TRY2(launch_finalize((int)c, k, d_probs, (int)nb, k, GY.as<double>(), Vk.as<double>(),
-                            F.as<double>(), st->rank_tol(), d_gsrc, nullptr, st->xi, st->conv,
-                            stream));
-    ST_TRY2(launch_utransform(Y, st->U, st->f32, k, d_pchunks, npchunks, F.as<double>(), stream));
-    // Gram tree over the stored blocks: leaves, then one launch per level.  For
-    // c > 128 a leaf is the Gram of the block's rows sigma_ij v_ij^T, formed by
-    // the Gram kernel (one chunk of k rows per block); leaves past nb are zero.
-    if (c <= kMaxC) {
-        ST_TRY2(launch_leaf_gram(st->view(), st->n2, st->tree, st->n2, stream));
-    } else {
-        ST_TRY2(Rows.ensure(sizeof(double) * (size_t)nb * k * c));
-        ST_TRY2(launch_scale_rows(st->view(), nb, Rows.as<double>(), stream));
-        double *leaves = st->tree + st->n2 * c * c;
-        ST_TRY2(launch_gram(Rows.as<double>(), kElemF64, c, (int)c, d_leaf_chunks, (int)nb, leaves,
-                            stream));
-        ST_TRY2(launch_zero(leaves + nb * c * c, (st->n2 - nb) * c * c, stream));
-    }
-    for (int64_t lev = st->n2 / 2; lev >= 1; lev /= 2)
-        ST_TRY2(launch_tree_level((int)c, st->tree, lev, lev, stream));
-    ST_TRY2(hipStreamSynchronize(stream));
-    int conv = 0;
-    ST_TRY2(hipMemcpy(&conv, st->conv, sizeof(int), hipMemcpyDeviceToHost));
-    release();
+    auto bail = [&](zs_status e) {
+        (void)hipStreamSynchronize(stream);
+        zs_store_free(st);
+        return e;
+    };
+    StorePlan pl;
+    s = store_plan(st, A, lda, a_type, *sw, stream, false, pl);
+    if (s != ZS_OK) return bail(s);
+    hipError_t e = store_kernels(st, pl, *sw, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess)
+        return bail(fail(e == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "storage phase: %s",
+                         hipGetErrorString(e)));
     *out = st;
-    if (conv) {
-        int zero = 0;
-        (void)hipMemcpy(st->conv, &zero, sizeof(int), hipMemcpyHostToDevice);
-        return fail(ZS_ENOCONV, "a block eigen-solve hit the sweep cap");
-    }
-    return ZS_OK;
-#undef ST_TRY
-#undef ST_TRY2
+    return take_conv(st, "a block eigen-solve hit the sweep cap");
 }
 
 zs_status zs_query(const zs_store *cst, int64_t t_s, int64_t t_e, int32_t k_q, void *U,
@@ -864,12 +927,14 @@ zs_status zs_query_noalloc(const zs_store *cst, int64_t t_s, int64_t t_e, int32_
     qb.C = reinterpret_cast<double *>(base + o_C);
     qb.big = reinterpret_cast<double *>(base + o_big);
     // no timing events either: the launches below are all this call makes
-    const bool was_untimed = t_untimed;
+    const bool was_untimed = t_untimed, was_suspended = tune_suspended();
     t_untimed = true;
+    tune_suspend(true);                  // cached or default launch variants only
     hipError_t e = launch_plan_single(p, stream);
     s = e == hipSuccess ? query_kernels(st, pl, qb, stream)
                         : fail(ZS_EDEVICE, "plan: %s", hipGetErrorString(e));
     t_untimed = was_untimed;
+    tune_suspend(was_suspended);
     return s;
 }
 
@@ -1185,6 +1250,91 @@ zs_status zs_query_batch_graph(const zs_store *cst, int32_t nq, const int64_t *t
 }
 
 zs_status zs_batch_graph_launch(zs_batch_graph *g, hipStream_t stream)
+{
+    if (!g || !g->exec) return fail(ZS_EINVAL, "graph is null");
+    HIP_TRY(hipGraphLaunch(g->exec, stream));
+    return ZS_OK;
+}
+
+struct zs_store_graph {
+    zs_store *st = nullptr;
+    StoreWork *w = nullptr;            // private: the graph's buffers stay put
+    StorePlan pl;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+void zs_store_graph_free(zs_store_graph *g)
+{
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->w) {
+        g->w->Gpart.release(); g->w->Vk.release(); g->w->GY.release(); g->w->F.release();
+        g->w->Ysc.release(); g->w->Big.release(); g->w->Rows.release(); g->w->desc.release();
+        delete g->w;
+    }
+    delete g;
+}
+
+zs_status zs_store_graph_create(const void *A, int64_t t, int64_t c, int64_t lda, zs_dtype a_type,
+                                int64_t b, int32_t k, zs_mode mode, hipStream_t stream,
+                                zs_store **st_out, zs_store_graph **g_out)
+{
+    if (st_out) *st_out = nullptr;
+    if (g_out) *g_out = nullptr;
+    if (!g_out) return fail(ZS_EINVAL, "null graph pointer");
+    zs_status s = check_store_args(A, t, c, lda, a_type, b, k, mode, 0.0, st_out);
+    if (s != ZS_OK) return s;
+    zs_store *st = nullptr;
+    s = new_store(t, c, b, k, mode, 0.0, stream, &st);
+    if (s != ZS_OK) return s;
+    zs_store_graph *g = new zs_store_graph();
+    g->st = st;
+    g->w = new StoreWork();
+    auto bail = [&](zs_status e) {
+        (void)hipStreamSynchronize(stream);
+        zs_store_graph_free(g);
+        zs_store_free(st);
+        return e;
+    };
+#define SG_TRY(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return bail(fail(e_ == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "%s: %s",    \
+                             #expr, hipGetErrorString(e_)));                                \
+    } while (0)
+    s = store_plan(st, A, lda, a_type, *g->w, stream, true, g->pl);
+    if (s != ZS_OK) return bail(s);
+    // One eager run builds the store and sets the kernels' LDS limits, so
+    // that the captured launches neither allocate nor configure anything.
+    SG_TRY(store_kernels(st, g->pl, *g->w, stream));
+    SG_TRY(hipStreamSynchronize(stream));
+    const zs_status conv = take_conv(st, "a block eigen-solve hit the sweep cap");
+    hipStream_t cs = nullptr;
+    SG_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    t_untimed = true;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        e = store_kernels(st, g->pl, *g->w, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        g->graph = graph;
+        if (e == hipSuccess) e = e2;
+    }
+    t_untimed = false;
+    (void)hipStreamDestroy(cs);
+    SG_TRY(e);
+    SG_TRY(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+#undef SG_TRY
+    *st_out = st;
+    *g_out = g;
+    return conv;
+}
+
+zs_status zs_store_graph_launch(zs_store_graph *g, hipStream_t stream)
 {
     if (!g || !g->exec) return fail(ZS_EINVAL, "graph is null");
     HIP_TRY(hipGraphLaunch(g->exec, stream));

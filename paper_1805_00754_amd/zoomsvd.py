@@ -31,9 +31,11 @@ STATUS_NAMES = {0: "ZS_OK", -1: "ZS_EINVAL", -2: "ZS_ERANGE", -3: "ZS_ENOMEM", -
 # Symbols the header declares (the CPU test checks the library exports all).
 EXPORTED = ["zs_store_blocks", "zs_store_blocks_xi", "zs_store_append", "zs_window_similarity",
             "zs_query", "zs_query_noalloc", "zs_query_batch", "zs_query_batch_graph",
-            "zs_batch_graph_launch", "zs_batch_graph_free", "zs_store_free", "zs_store_bytes",
+            "zs_batch_graph_launch", "zs_batch_graph_free", "zs_store_graph_create",
+            "zs_store_graph_launch", "zs_store_graph_free", "zs_store_free", "zs_store_bytes",
             "zs_store_info", "zs_store_get_block", "zs_sync_status", "zs_last_error", "zs_version",
-            "zs_timing_enable", "zs_timing_reset", "zs_timing_get"]
+            "zs_timing_enable", "zs_timing_reset", "zs_timing_get", "zs_autotune",
+            "zs_autotune_force", "zs_autotune_table"]
 
 
 class ZSError(RuntimeError):
@@ -73,6 +75,12 @@ def load(path: str | None = None):
         lib.zs_query_batch_graph.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                              _vp, _vp, _vp, ctypes.POINTER(_vp)]
         lib.zs_batch_graph_launch.argtypes = [_vp, _vp]
+        lib.zs_store_graph_create.argtypes = [_vp, _i64, _i64, _i64, ctypes.c_int, _i64, _i32,
+                                              ctypes.c_int, _vp, ctypes.POINTER(_vp),
+                                              ctypes.POINTER(_vp)]
+        lib.zs_store_graph_launch.argtypes = [_vp, _vp]
+        lib.zs_store_graph_free.argtypes = [_vp]
+        lib.zs_store_graph_free.restype = None
         lib.zs_batch_graph_free.argtypes = [_vp]
         lib.zs_batch_graph_free.restype = None
         lib.zs_store_free.argtypes = [_vp]
@@ -88,11 +96,17 @@ def load(path: str | None = None):
         lib.zs_timing_enable.restype = None
         lib.zs_timing_reset.restype = None
         lib.zs_timing_get.argtypes = [ctypes.c_char_p, _vp, _vp]
+        lib.zs_autotune.argtypes = [ctypes.c_int]
+        lib.zs_autotune.restype = None
+        lib.zs_autotune_force.argtypes = [ctypes.c_char_p, ctypes.c_int]
+        lib.zs_autotune_force.restype = ctypes.c_int
+        lib.zs_autotune_table.restype = ctypes.c_char_p
         for name in ("zs_store_blocks", "zs_store_blocks_xi", "zs_store_append",
                      "zs_window_similarity", "zs_query", "zs_query_noalloc", "zs_query_batch",
                      "zs_store_info",
                      "zs_store_get_block", "zs_sync_status", "zs_timing_get",
-                     "zs_query_batch_graph", "zs_batch_graph_launch"):
+                     "zs_query_batch_graph", "zs_batch_graph_launch", "zs_store_graph_create",
+                     "zs_store_graph_launch"):
             getattr(lib, name).restype = ctypes.c_int
         if path is None:
             _lib = lib
@@ -172,6 +186,50 @@ def zs_store_blocks(A: torch.Tensor, b: int, k: int, mode: int = ZS_MODE_FP64, s
         load().zs_store_free(h)
     _check(st)
     return Store(h.value, t, c, b, k, mode, float(xi))
+
+
+class StoreGraph:
+    """The storage phase of a fixed input captured into a HIP graph
+    (zs_store_graph_create): launch() recompresses the input's current
+    contents into the same store.  Keeps the input tensor alive."""
+
+    def __init__(self, st: Store, A: torch.Tensor, handle):
+        self.st = st
+        self.A = A
+        self.handle = handle
+
+    def launch(self, stream=None):
+        _check(load().zs_store_graph_launch(_vp(self.handle), _vp(_stream(stream))))
+
+    def free(self):
+        if self.handle:
+            load().zs_store_graph_free(_vp(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def zs_store_graph_create(A: torch.Tensor, b: int, k: int, mode: int = ZS_MODE_FP64,
+                          stream=None) -> StoreGraph:
+    """Builds the store of A (t x c, on the GPU) and captures its storage phase
+    into a graph; returns the StoreGraph (its .st is the store).  Free the
+    graph before the store."""
+    if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
+        raise ValueError("A must be a 2-D CUDA/HIP tensor with unit column stride")
+    a_type = {torch.float64: ZS_F64, torch.float32: ZS_F32, torch.bfloat16: ZS_BF16}[A.dtype]
+    t, c = A.shape
+    hs, hg = _vp(), _vp()
+    s = load().zs_store_graph_create(_vp(_ptr(A)), t, c, A.stride(0), a_type, b, k, mode,
+                                     _vp(_stream(stream)), ctypes.byref(hs), ctypes.byref(hg))
+    if s == ZS_ENOCONV and hg.value:
+        load().zs_store_graph_free(hg)
+        load().zs_store_free(hs)
+    _check(s)
+    return StoreGraph(Store(hs.value, t, c, b, k, mode), A, hg.value)
 
 
 def zs_store_append(st: Store, R: torch.Tensor, stream=None) -> Store:
@@ -365,3 +423,23 @@ def zs_timing_get(name: str):
     ms = ctypes.c_double()
     _check(load().zs_timing_get(name.encode(), ctypes.byref(n), ctypes.byref(ms)))
     return int(n.value), float(ms.value)
+
+
+def zs_autotune(on: bool = True):
+    """Turns the timing of launch variants on or off (cached choices apply)."""
+    load().zs_autotune(1 if on else 0)
+
+
+def zs_autotune_force(site: str, variant: int):
+    """Forces a launch variant at a tuned site for every shape (< 0 clears)."""
+    _check(load().zs_autotune_force(site.encode(), variant))
+
+
+def zs_autotune_table() -> dict:
+    """{'site|key': (variant, 'ms,ms')} of the choices made so far."""
+    out = {}
+    for line in load().zs_autotune_table().decode().splitlines():
+        parts = line.split("\t")
+        if len(parts) >= 2:
+            out[parts[0]] = (int(parts[1]), parts[2] if len(parts) > 2 else "")
+    return out

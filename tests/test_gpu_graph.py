@@ -1,13 +1,14 @@
-"""The batched query form captured into a HIP graph (zs_query_batch_graph):
-every replay equals the eager zs_query_batch result bitwise, with the
-program's own eager work and synchronisations between replays."""
+"""The batched query form and the storage phase captured into HIP graphs
+(zs_query_batch_graph, zs_store_graph_create): every replay equals the eager
+result bitwise, with the program's own eager work and synchronisations
+between replays."""
 import numpy as np
 import pytest
 import torch
 
 from paper_1805_00754_amd import synth
 from paper_1805_00754_amd import zoomsvd as zs
-from tests.gpu_common import say, to_dev
+from tests.gpu_common import download_store, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -63,3 +64,41 @@ def test_graph_rejects_bad_range():
     with pytest.raises(zs.ZSError):
         zs.zs_query_batch_graph(st, [0, 5], [10, st.t + 1], 3)
     st.free()
+
+
+@pytest.mark.parametrize("name,mode,tdtype", [("fp64", zs.ZS_MODE_FP64, torch.float64),
+                                              ("bf16", zs.ZS_MODE_BF16, torch.bfloat16)])
+def test_store_graph_replays_equal_eager_store(name, mode, tdtype):
+    """The storage phase captured once: each replay recompresses the input's
+    current contents, bitwise as zs_store_blocks on the same contents.  The
+    input is rewritten in place between replays (three different series of
+    one shape, a short last block, c > 128 so the wide eigen-solver and the
+    Gram-tree leaves of that path are in the graph too)."""
+    zs.load()
+    t, c, b, k = 5_300, 160, 1_000, 12
+    series = [synth.sinusoid_mixture(t, c, sources=10, seed=60 + i, noise="iid",
+                                     noise_sigma=0.1, dtype="bf16" if name == "bf16" else "f64").A
+              for i in range(3)]
+    A = to_dev(series[0], tdtype)
+    g = zs.zs_store_graph_create(A, b, k, mode=mode)
+    torch.cuda.synchronize()
+    say("store graph", name, (t, c, b, k))
+    for rep in range(4):
+        i = rep % 3
+        ref_st = zs.zs_store_blocks(to_dev(series[i], tdtype), b, k, mode=mode)
+        ref = download_store(ref_st)
+        qref = [x.cpu() for x in zs.zs_query(ref_st, 123, 4_567, k)]
+        ref_st.free()
+        if rep > 0:
+            A.copy_(to_dev(series[i], tdtype))     # the caller refreshes the input in place
+            torch.cuda.synchronize()
+            g.launch()
+        zs.zs_sync_status(g.st)
+        got = download_store(g.st)
+        for x, y in zip(got, ref):
+            np.testing.assert_array_equal(x, y)
+        q = [x.cpu() for x in zs.zs_query(g.st, 123, 4_567, k)]
+        for x, y in zip(q, qref):
+            assert torch.equal(x, y)
+    g.free()
+    g.st.free()
