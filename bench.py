@@ -60,6 +60,8 @@ def main():
                     help="arrival rates (queries/s) of the serving runs; empty to skip "
                          "(default 500,2000,8000 on the default workload, none on others)")
     ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--serve-single", type=int, default=128,
+                    help="sample of one-at-a-time FP64 queries timed for the serving baseline")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="named synthetic workload (synth.WORKLOADS); the default is the one "
                          "the headline metric is quoted on")
@@ -283,7 +285,7 @@ def main():
             lat.append((time.perf_counter() - a) * 1e3)
     if args.serve_rates is None:
         args.serve_rates = "500,2000,8000" if wl == WORKLOAD else ""
-    serving = serve_runs(st, args) if args.serve_rates else None
+    serving = serve_runs(st, args, A, b, k, mode) if args.serve_rates else None
     # Reduced-precision modes: every query of the batch against the FP64 path
     # (an FP64-mode store of the same input, the same batch), per result.
     precision = None
@@ -557,12 +559,51 @@ def sweep_b(args):
                       "range_lengths": lengths, "sweep": rows}), flush=True)
 
 
-def serve_runs(st, args):
+def serve_runs(st, args, A, b, k, mode):
     """Open-loop serving on the resident store: Poisson arrivals at each rate,
-    lengths log-uniform in [1e4, 3.2e5] rows, k_q uniform over {8, 16, k}."""
+    lengths log-uniform in [1e4, 3.2e5] rows, k_q uniform over {8, 16, k};
+    two batches in flight on two streams.  Beside it, one-at-a-time FP64
+    queries (an FP64-mode store of the same input): their service times are
+    measured on the GPU for a sample of the stream's queries, and the stream
+    is replayed through a single first-come first-served server with those
+    times (the service time of a request: the measured query of the nearest
+    length)."""
     import numpy as np
+    import torch
 
     from paper_1805_00754_amd import serve, synth
+    from paper_1805_00754_amd import zoomsvd as zs
+
+    dev = torch.device("cuda", 0)
+    # one-at-a-time FP64 service times
+    st64 = st if mode == zs.ZS_MODE_FP64 else zs.zs_store_blocks(A, b, k, mode=zs.ZS_MODE_FP64)
+    rng = synth.rng_for(synth.SEED_BASE + 4)
+    sample = serve.make_requests(rng, st.t, args.serve_single, 1.0, 1e4, 3.2e5, [8, 16, st.k])
+    nmax = max(r.t_e - r.t_s for r in sample)
+    U1 = torch.empty((nmax, st.k), dtype=torch.float64, device=dev)
+    S1 = torch.empty(st.k, dtype=torch.float64, device=dev)
+    V1 = torch.empty((st.c, st.k), dtype=torch.float64, device=dev)
+    ko = torch.empty(1, dtype=torch.int32, device=dev)
+    for r in sample[:4]:                                   # warm-up
+        zs.zs_query(st64, r.t_s, r.t_e, r.k_q, U1[:, :r.k_q], S1[:r.k_q], V1[:, :r.k_q], ko)
+    svc_len, svc_s = [], []
+    for r in sample:
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        zs.zs_query(st64, r.t_s, r.t_e, r.k_q, U1[:, :r.k_q], S1[:r.k_q], V1[:, :r.k_q], ko)
+        torch.cuda.synchronize()
+        svc_s.append(time.perf_counter() - a)
+        svc_len.append(r.t_e - r.t_s)
+    if st64 is not st:
+        st64.free()
+    order = np.argsort(svc_len)
+    svc_len = np.asarray(svc_len)[order]
+    svc_s = np.asarray(svc_s)[order]
+    single = {"store": "fp64", "sample": len(sample), "p50_ms": float(np.median(svc_s) * 1e3),
+              "p99_ms": float(np.percentile(svc_s, 99) * 1e3),
+              "capacity_per_s": float(1.0 / np.mean(svc_s))}
+    log("one-at-a-time FP64: p50 %.2f ms, capacity %.0f queries/s"
+        % (single["p50_ms"], single["capacity_per_s"]))
 
     out = []
     for rate in [float(x) for x in args.serve_rates.split(",") if x]:
@@ -573,13 +614,29 @@ def serve_runs(st, args):
         log("serving %d requests at %g/s" % (len(reqs), rate))
         res = srv.run(reqs)
         served = len(reqs) - len(res["rejected"])
+        # the same stream served one query at a time in FP64
+        L = np.array([r.t_e - r.t_s for r in reqs])
+        idx = np.clip(np.searchsorted(svc_len, L), 0, len(svc_len) - 1)
+        idx0 = np.clip(idx - 1, 0, len(svc_len) - 1)
+        near = np.where(np.abs(svc_len[idx0] - L) < np.abs(svc_len[idx] - L), idx0, idx)
+        arr = np.array([r.arrival for r in reqs])
+        done = serve.fifo_replay(arr, svc_s[near])
+        lat1 = done - arr
         out.append({"rate_per_s": rate, "requests": len(reqs), "served": served,
                     "p50_ms": res["p50"] * 1e3, "p99_ms": res["p99"] * 1e3,
                     "throughput_per_s": served / res["span"],
                     "batches": len(res["batches"]),
-                    "mean_batch": float(np.mean(res["batches"]))})
+                    "mean_batch": float(np.mean(res["batches"])),
+                    "batch_p50_ms": float(np.median(res["batch_ms"])),
+                    "batch_p99_ms": float(np.percentile(res["batch_ms"], 99)),
+                    "one_at_a_time_fp64": {"p50_ms": float(np.median(lat1) * 1e3),
+                                           "p99_ms": float(np.percentile(lat1, 99) * 1e3),
+                                           "throughput_per_s": len(reqs) / float(done[-1])}})
+        log("  p50 %.2f ms p99 %.2f ms (one at a time FP64: p50 %.1f ms p99 %.1f ms)"
+            % (out[-1]["p50_ms"], out[-1]["p99_ms"], out[-1]["one_at_a_time_fp64"]["p50_ms"],
+               out[-1]["one_at_a_time_fp64"]["p99_ms"]))
         del srv
-    return out
+    return {"single_fp64": single, "rates": out}
 
 
 def prod_ld(k):

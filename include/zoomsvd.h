@@ -168,6 +168,17 @@ zs_status zs_query_noalloc(const zs_store *st, int64_t t_s, int64_t t_e, int32_t
                            hipStream_t stream);
 
 /*
+ * zs_query_scratch_bytes -- device scratch (bytes) that the query [t_s, t_e)
+ * at rank k_q adds to its stream's workspace in zs_query / zs_query_batch
+ * (stacked-matrix projections, coefficient blocks, eigenvector blocks,
+ * descriptors): with the outputs, what an admission policy must budget per
+ * query.  The workspace of a stream grows to the largest batch it has run
+ * and is kept until the store is freed.  Returns -1 for a null store or a
+ * range or rank that zs_query would reject.
+ */
+int64_t zs_query_scratch_bytes(const zs_store *st, int64_t t_s, int64_t t_e, int32_t k_q);
+
+/*
  * zs_query_batch -- nq independent queries in one set of launches.
  *   t_s, t_e, k_q   host arrays of nq ranges and ranks (same rules as zs_query).
  *   U, S, V         device base pointers (element types as in zs_query); query q writes

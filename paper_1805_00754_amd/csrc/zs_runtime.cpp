@@ -938,6 +938,29 @@ zs_status zs_query_noalloc(const zs_store *cst, int64_t t_s, int64_t t_e, int32_
     return s;
 }
 
+int64_t zs_query_scratch_bytes(const zs_store *cst, int64_t t_s, int64_t t_e, int32_t k_q)
+{
+    if (!cst || check_query(cst, t_s, t_e, k_q) != ZS_OK) return -1;
+    zs_store *st = const_cast<zs_store *>(cst);
+    const int64_t c = st->c, k = st->k;
+    SinglePlan p;
+    std::memset(&p, 0, sizeof p);
+    PlanSink sink{p};
+    int32_t nchunks = 0;
+    QueryDesc d;
+    Prob pr;
+    plan_one(st, 0, t_s, t_e, k_q, 0, k_q, nullptr, nullptr, k_q, nullptr, 0, 0, 0, nchunks, sink,
+             d, pr);
+    const int64_t np = d.np, npartial = p.npidx;
+    // the query's share of its stream's workspace (the buffers of query_plan)
+    // and of the descriptors
+    return 8 * (npartial * k * c + c * kMaxK + np * k * k_q + (int64_t)nchunks * kSlotK + kSlotK +
+                npartial * k * k + np * prod_ld((int)k) * k_q + (int64_t)big_doubles(c, 1)) +
+           np * (int64_t)(sizeof(Piece) + sizeof(int32_t)) +
+           (int64_t)nchunks * sizeof(StackChunk) + (int64_t)(sizeof(Prob) + sizeof(QueryDesc)) +
+           8 * (p.ngsrc + 2) + 8;
+}
+
 static zs_status check_batch(const zs_store *cst, int32_t nq, const int64_t *t_s, const int64_t *t_e,
                       const int32_t *k_q, void *U, const int64_t *u_off, double *S,
                       const int64_t *s_off, void *V, const int64_t *v_off, int32_t *k_out)

@@ -4,16 +4,20 @@ Range queries (t_s, t_e, k_q) arrive over time.  The loop keeps the store in
 HBM and answers the queries in batches through ``zs_query_batch``:
 
 * admission: a batch takes pending requests first-come first-served while it
-  stays within ``max_queries`` and an HBM byte budget for its outputs
-  (U n x k_q and V c x k_q in the store's output type, Sigma k_q in FP64,
-  k_out); a request whose outputs alone exceed the budget is rejected;
-* continuous batching: up to ``depth`` batches are in flight on one stream, so
-  the host plans and enqueues the next batch while the GPU runs the current
+  stays within ``max_queries`` and an HBM byte budget per batch: each
+  request's outputs (U n x k_q and V c x k_q in the store's output type,
+  Sigma k_q in FP64, k_out) plus the device scratch the library adds for it
+  (``zs_query_scratch_bytes``); a request that alone exceeds the budget is
+  rejected;
+* continuous batching: up to ``depth`` batches are in flight, each on its own
+  stream (default priority) with its own output arena and its own library
+  workspace, so batches overlap on the device while the host plans the next
   one; a new batch is formed as soon as a slot is free and requests wait;
-* timing: a HIP event recorded at the start of the run is the time origin, and
-  each batch records an event when its kernels finish, so a request's latency
-  is GPU completion time minus its arrival time (open loop: arrivals do not
-  wait for completions).
+* timing: a HIP event recorded at the start of the run is the time origin,
+  and each batch records events when its kernels start and finish, so a
+  request's latency is GPU completion time minus its arrival time (open loop:
+  arrivals do not wait for completions) and a batch's service time is its
+  own device time.
 
 The batch policy is plain host logic (``BatchPolicy``); every query is answered
 by the library's kernels.
@@ -43,18 +47,23 @@ class Request:
 
 
 class BatchPolicy:
-    """First-come first-served packing under a query count and a byte budget."""
+    """First-come first-served packing under a query count and a byte budget.
+    A request costs its outputs plus `scratch_fn(request)` bytes (the library's
+    device scratch for it; none when not given)."""
 
-    def __init__(self, c: int, max_queries: int, budget_bytes: int, esize: int = 8):
+    def __init__(self, c: int, max_queries: int, budget_bytes: int, esize: int = 8,
+                 scratch_fn=None):
         if max_queries < 1 or budget_bytes < 1:
             raise ValueError("max_queries and budget_bytes must be positive")
         self.c = c
         self.max_queries = max_queries
         self.budget_bytes = budget_bytes
         self.esize = esize
+        self.scratch_fn = scratch_fn
 
     def bytes_of(self, r: Request) -> int:
-        return output_bytes(r.t_e - r.t_s, r.k_q, self.c, self.esize)
+        out = output_bytes(r.t_e - r.t_s, r.k_q, self.c, self.esize)
+        return out + (int(self.scratch_fn(r)) if self.scratch_fn is not None else 0)
 
     def fits_alone(self, r: Request) -> bool:
         return self.bytes_of(r) <= self.budget_bytes
@@ -80,8 +89,7 @@ def poisson_arrivals(rng: np.random.Generator, rate: float, n: int) -> np.ndarra
 class Server:
     """Serves range queries on one store with continuous batching."""
 
-    def __init__(self, st, max_queries: int = 256, budget_bytes: int = 1 << 30, depth: int = 2,
-                 stream=None):
+    def __init__(self, st, max_queries: int = 256, budget_bytes: int = 1 << 30, depth: int = 2):
         import torch
 
         from . import zoomsvd as zs
@@ -90,9 +98,13 @@ class Server:
         self.torch = torch
         self.st = st
         esize = torch.empty((), dtype=st.out_dtype).element_size()
-        self.policy = BatchPolicy(st.c, max_queries, budget_bytes, esize)
+        self.policy = BatchPolicy(st.c, max_queries, budget_bytes, esize,
+                                  scratch_fn=lambda r: zs.zs_query_scratch_bytes(st, r.t_s, r.t_e,
+                                                                                  r.k_q))
         self.depth = depth
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        # one stream per in-flight slot, all at the default priority
+        self.streams = [torch.cuda.Stream() for _ in range(depth)]
+        self.stream = torch.cuda.current_stream()          # the time origin's stream
         dev = torch.device("cuda", torch.cuda.current_device())
         # one output arena per in-flight slot: U and V share a flat buffer of the
         # store's output type, Sigma has an FP64 one
@@ -113,12 +125,16 @@ class Server:
         v_base = int(sizes_u.sum())
         v_off = v_base + np.concatenate(([0], np.cumsum(c * kq.astype(np.int64))[:-1])).astype(np.int64)
         a = self.arena[slot]
+        stream = self.streams[slot]
+        start = self.torch.cuda.Event(enable_timing=True)
+        start.record(stream)
         self.zs.zs_query_batch_into(self.st, [r.t_s for r in batch], [r.t_e for r in batch], kq,
                                     a, u_off, self.sarena[slot], s_off, a, v_off, self.kout[slot],
-                                    stream=self.stream)
+                                    stream=stream)
         done = self.torch.cuda.Event(enable_timing=True)
-        done.record(self.stream)
-        return dict(slot=slot, batch=batch, done=done, u_off=u_off, s_off=s_off, v_off=v_off)
+        done.record(stream)
+        return dict(slot=slot, batch=batch, start=start, done=done, u_off=u_off, s_off=s_off,
+                    v_off=v_off)
 
     def run(self, requests: list, on_batch=None) -> dict:
         """Serves `requests` (sorted by arrival) in real time.  Returns per-request
@@ -141,10 +157,13 @@ class Server:
         nxt = 0
         finished = 0
 
+        batch_ms = []
+
         def retire(info):
             nonlocal finished
             info["done"].synchronize()
             t_done = origin.elapsed_time(info["done"]) / 1e3
+            batch_ms.append(info["start"].elapsed_time(info["done"]))
             for r in info["batch"]:
                 completion[r.idx] = t_done
             finished += len(info["batch"])
@@ -182,9 +201,22 @@ class Server:
         lat = completion - arrival
         ok = ~np.isnan(lat)
         return dict(completion=completion, latency=lat, rejected=rejected, batches=batches,
+                    batch_ms=batch_ms,
                     p50=float(np.percentile(lat[ok], 50)) if ok.any() else None,
                     p99=float(np.percentile(lat[ok], 99)) if ok.any() else None,
                     span=float(np.nanmax(completion)) if ok.any() else 0.0)
+
+
+def fifo_replay(arrival: np.ndarray, service: np.ndarray) -> np.ndarray:
+    """Completion times of requests served one at a time in arrival order
+    (a single server, first-come first-served) with the given service times:
+    each starts when it has arrived and the previous one has finished."""
+    done = np.empty(len(arrival))
+    t = 0.0
+    for i in range(len(arrival)):
+        t = max(t, float(arrival[i])) + float(service[i])
+        done[i] = t
+    return done
 
 
 def make_requests(rng: np.random.Generator, t: int, n: int, rate: float, lmin: float, lmax: float,

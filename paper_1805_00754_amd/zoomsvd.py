@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "ZS_OK", -1: "ZS_EINVAL", -2: "ZS_ERANGE", -3: "ZS_ENOMEM", -
 
 # Symbols the header declares (the CPU test checks the library exports all).
 EXPORTED = ["zs_store_blocks", "zs_store_blocks_xi", "zs_store_append", "zs_window_similarity",
-            "zs_query", "zs_query_noalloc", "zs_query_batch", "zs_query_batch_graph",
+            "zs_query", "zs_query_noalloc", "zs_query_scratch_bytes", "zs_query_batch",
+            "zs_query_batch_graph",
             "zs_batch_graph_launch", "zs_batch_graph_free", "zs_store_graph_create",
             "zs_store_graph_launch", "zs_store_graph_free", "zs_store_free", "zs_store_bytes",
             "zs_store_info", "zs_store_get_block", "zs_sync_status", "zs_last_error", "zs_version",
@@ -68,6 +69,8 @@ def load(path: str | None = None):
                                            ctypes.c_int, ctypes.c_double, _vp, ctypes.POINTER(_vp)]
         lib.zs_query.argtypes = [_vp, _i64, _i64, _i32, _vp, _i64, _vp, _vp, _i64, _vp, _vp]
         lib.zs_query_noalloc.argtypes = lib.zs_query.argtypes
+        lib.zs_query_scratch_bytes.argtypes = [_vp, _i64, _i64, _i32]
+        lib.zs_query_scratch_bytes.restype = _i64
         lib.zs_window_similarity.argtypes = [_vp, _i64, _i64, _i64, _i32, _vp, _vp]
         lib.zs_store_append.argtypes = [_vp, _vp, _i64, _i64, ctypes.c_int, _vp]
         lib.zs_query_batch.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -399,6 +402,11 @@ def zs_store_get_block(st: Store, i: int, stream=None):
     _check(load().zs_store_get_block(_vp(st.handle), i, _vp(_ptr(U)), _vp(_ptr(S)), _vp(_ptr(V)),
                                      _vp(_ptr(ki)), _vp(_stream(stream))))
     return U, S, V, ki
+
+
+def zs_query_scratch_bytes(st: Store, t_s: int, t_e: int, k_q: int) -> int:
+    """Device scratch a query adds to its stream's workspace (-1: rejected)."""
+    return int(load().zs_query_scratch_bytes(_vp(st.handle), t_s, t_e, k_q))
 
 
 def zs_store_bytes(st: Store) -> int:

@@ -82,3 +82,23 @@ def test_make_requests_ranges():
     assert L.min() >= 1e4 - 1 and L.max() <= 3.2e5 + 1
     assert set(r.k_q for r in rs) <= {8, 16, 20}
     assert [r.idx for r in rs] == list(range(500))
+
+
+def test_budget_counts_the_scratch():
+    c = 4
+    one = serve.output_bytes(100, 2, c)
+    scratch = lambda r: 1000 * (r.idx + 1)
+    pol = serve.BatchPolicy(c=c, max_queries=100, budget_bytes=2 * one + 3000, scratch_fn=scratch)
+    assert pol.bytes_of(req(0, 100, 2)) == one + 1000
+    pending = collections.deque([req(0, 100, 2), req(1, 100, 2), req(2, 100, 2)])
+    # 0 and 1 cost 2 one + 3000: they fit; 2 would add one + 3000 more
+    assert [r.idx for r in pol.take(pending)] == [0, 1]
+    assert not serve.BatchPolicy(c=c, max_queries=100, budget_bytes=one + 999,
+                                 scratch_fn=scratch).fits_alone(req(0, 100, 2))
+
+
+def test_fifo_replay():
+    arrival = np.array([0.0, 0.1, 0.15, 1.0])
+    service = np.array([0.2, 0.2, 0.2, 0.05])
+    # 0: 0 -> 0.2; 1 waits: 0.2 -> 0.4; 2: 0.4 -> 0.6; 3 arrives after: 1.0 -> 1.05
+    np.testing.assert_allclose(serve.fifo_replay(arrival, service), [0.2, 0.4, 0.6, 1.05])
