@@ -67,6 +67,9 @@ def main():
                          "the headline metric is quoted on")
     ap.add_argument("--query-len", type=int, default=QUERY_LEN,
                     help="range length of a fixed batch")
+    ap.add_argument("--sweep-queries", type=int, default=256,
+                    help="queries per batch of the block-size study in the default run "
+                         "(0 skips it)")
     ap.add_argument("--sweep-b", default=None,
                     help="comma-separated block sizes: instead of the benchmark, store the "
                          "workload at each b and time query batches at range lengths 1e3, 1e4 "
@@ -286,6 +289,10 @@ def main():
     if args.serve_rates is None:
         args.serve_rates = "500,2000,8000" if wl == WORKLOAD else ""
     serving = serve_runs(st, args, A, b, k, mode) if args.serve_rates else None
+    # The block-size study of Sec. 4.5 on the benchmark series (b = 10 to 10^5).
+    sweep = None
+    if wl == WORKLOAD and args.sweep_queries > 0:
+        sweep = block_size_sweep(A, k, [10, 100, 1_000, 10_000, 100_000], args.sweep_queries)
     # Reduced-precision modes: every query of the batch against the FP64 path
     # (an FP64-mode store of the same input, the same batch), per result.
     precision = None
@@ -438,6 +445,7 @@ def main():
         "windows": windows,
         "ingest": ingest,
         "precision_vs_fp64": precision,
+        "block_size_sweep": sweep,
         "autotune": {k_: {"variant": v[0], "ms": v[1]} for k_, v in zs.zs_autotune_table().items()},
         "cpu_baseline": cpu,
     }
@@ -492,27 +500,21 @@ def precision_vs_fp64(A, b, k, st, ts, te, kq, out, dev, chunk=64):
             "per_query_sigma_rel": [float("%.3g" % x) for x in sig]}
 
 
-def sweep_b(args):
-    """The paper's block-size study on the synthetic workload: for each b, the
-    store time, the stored elements against the raw matrix (Thm. 3:
-    sum_i k_i (b_i + 1 + c) with k_i = min(k, b_i) on full-rank noisy blocks)
-    and the time of a batch of queries at each range length."""
+def block_size_sweep(A, k, bs, nq, lengths=(1_000, 10_000, 100_000)):
+    """The paper's block-size study (Sec. 4.5, Fig. 6) on the device series A:
+    for each b, the store time, the stored elements against the raw matrix
+    (Thm. 3: sum_i k_i (b_i + 1 + c), k_i = min(k, b_i) on these full-rank
+    noisy blocks) and the time of a batch of nq queries at each range length
+    (medians of three after one untimed run)."""
     import numpy as np
     import torch
 
     from paper_1805_00754_amd import synth
     from paper_1805_00754_amd import zoomsvd as zs
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    zs.load()
-    dev = torch.device("cuda", 0)
+    dev = A.device
     stream = torch.cuda.current_stream()
-    ser, cfg = synth.workload(args.workload)
-    t, c = ser.A.shape
-    k = cfg["k"]
-    A = torch.from_numpy(ser.A).to(dev)
-    lengths = [1_000, 10_000, 100_000]
-    nq = args.queries
+    t, c = A.shape
 
     def timed(fn, reps=3):
         fn()
@@ -529,8 +531,8 @@ def sweep_b(args):
         return float(np.median(ms))
 
     rows = []
-    for b in [int(x) for x in args.sweep_b.split(",") if x]:
-        log("b = %d" % b)
+    for b in bs:
+        log("block-size sweep: b = %d" % b)
         holder = {}
 
         def store():
@@ -550,13 +552,31 @@ def sweep_b(args):
             q[str(L)] = {"batch_ms": qms, "svds_per_s": nq / (qms / 1e3)}
             del out
         rows.append({"b": b, "blocks": nb, "store_ms": store_ms,
-                     "store_gbps": t * c * 8 / (store_ms / 1e3) / 1e9,
-                     "stored_elements": elems, "compression": t * c / elems, "queries": q})
+                     "store_gbps": t * c * A.element_size() / (store_ms / 1e3) / 1e9,
+                     "stored_elements": elems, "compression": t * c / elems,
+                     "store_bytes": zs.zs_store_bytes(st), "queries": q})
         st.free()
         torch.cuda.empty_cache()
-    print(json.dumps({"metric": "block-size sweep (store time, compression, query batches)",
-                      "workload": args.workload, "t": t, "c": c, "k": k, "queries_per_batch": nq,
-                      "range_lengths": lengths, "sweep": rows}), flush=True)
+    return {"workload_rows": t, "c": c, "k": k, "queries_per_batch": nq,
+            "range_lengths": list(lengths), "sweep": rows}
+
+
+def sweep_b(args):
+    """--sweep-b: the block-size study alone, one JSON line."""
+    import torch
+
+    from paper_1805_00754_amd import synth
+    from paper_1805_00754_amd import zoomsvd as zs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    zs.load()
+    ser, cfg = synth.workload(args.workload)
+    A = torch.from_numpy(ser.A).to(torch.device("cuda", 0))
+    res = block_size_sweep(A, cfg["k"], [int(x) for x in args.sweep_b.split(",") if x],
+                           args.queries or N_QUERIES)
+    res.update(metric="block-size sweep (store time, compression, query batches)",
+               workload=args.workload)
+    print(json.dumps(res), flush=True)
 
 
 def serve_runs(st, args, A, b, k, mode):

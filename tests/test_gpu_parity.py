@@ -139,15 +139,17 @@ def test_large_c_store_and_query_parity(t, c, b, k):
 
 
 # Block sizes of the paper's sensitivity study (Sec. 4.5, Fig. 6) beyond the
-# default 10^3: 10^4 and 10^5 rows per block, each with a short last block.
-@pytest.mark.parametrize("t,c,b,k", [(25_000, 128, 10_000, 20), (230_000, 128, 100_000, 20)])
+# default 10^3: 10 (fewer rows per block than the rank k, so k_i = 10), 10^4
+# and 10^5 rows per block, each with a short last block.
+@pytest.mark.parametrize("t,c,b,k", [(2_003, 128, 10, 20), (25_000, 128, 10_000, 20),
+                                     (230_000, 128, 100_000, 20)])
 def test_large_block_sizes(t, c, b, k):
     ser = synth.sinusoid_mixture(t, c, sources=16, seed=61 + b // 1000, noise="ar1",
                                  noise_sigma=0.05)
     st, (U, S, V, kk) = check_store(ser.A, b, k, "b %d" % b)
     gst = oracle.store_from_arrays(st.t, st.c, st.b, st.k, U, S, V, kk)
     rng = synth.rng_for(b)
-    ts, te = synth.queries_loguniform(rng, t, 4, 1e3, t)
+    ts, te = synth.queries_loguniform(rng, t, 4, min(1e3, t // 4), t)
     for q in range(4):
         kq = [k, 7][q % 2]
         say("b %d query" % b, int(ts[q]), int(te[q]), kq)
