@@ -43,7 +43,7 @@ typedef enum {
     ZS_OK = 0,
     ZS_EINVAL = -1,    /* bad argument: null pointer, b < 1, k < 1, k > c, lda < c, ...   */
     ZS_ERANGE = -2,    /* bad query: t_s < 0, t_e > t, t_s >= t_e, k_q < 1 or k_q > k       */
-    ZS_ENOMEM = -3,    /* device allocation failed                                          */
+    ZS_ENOMEM = -3,    /* device allocation failed, or the arrays exceed the device memory  */
     ZS_ENOCONV = -4,   /* a Jacobi eigen-solve hit its sweep cap (reported by zs_sync_status) */
     ZS_EDEVICE = -5,   /* a HIP runtime call failed                                         */
     ZS_EUNSUPPORTED = -6 /* a size this build does not handle (c or k above the limits)    */
@@ -326,6 +326,15 @@ zs_status zs_sync_status(const zs_store *st, hipStream_t stream);
 void zs_autotune(int on);
 zs_status zs_autotune_force(const char *site, int variant);
 const char *zs_autotune_table(void);
+
+/*
+ * zs_set_sweep_cap -- the sweep cap of every Jacobi solve (Rayleigh-Ritz
+ * and Partial-SVD steps) on the current device; 40 by default.  For tests of
+ * the ZS_ENOCONV path: with a cap of 1, any solve that needs a second sweep
+ * stops there and the store call or zs_sync_status reports ZS_ENOCONV (the
+ * results are then not converged).  ZS_EINVAL for cap < 1.
+ */
+zs_status zs_set_sweep_cap(int cap);
 
 /* Thread-local message describing the last error of the calling thread. */
 const char *zs_last_error(void);

@@ -38,6 +38,10 @@ __device__ __forceinline__ void rr_pair(int step, int pi, int N, int &p, int &q)
 // numerically zero and are not rotated.
 // Returns the number of sweeps, or -1 if the cap was hit.  All threads of
 // the block must call it; cs/sn/dp/dq need n/2 entries.
+// Sweep cap of every Jacobi solve on this device (kMaxSweeps unless a test
+// lowers it to force ZS_ENOCONV).
+__device__ int d_sweep_cap = kMaxSweeps;
+
 __device__ int sym_jacobi(double *G, double *W, int n, int ld, double *cs_sh, double *sn_sh,
                           double *dp_sh, double *dq_sh, int *flag_sh, double *tr_sh)
 {
@@ -52,7 +56,8 @@ __device__ int sym_jacobi(double *G, double *W, int n, int ld, double *cs_sh, do
     const double floor = ((double)n * __DBL_EPSILON__) * ((double)n * __DBL_EPSILON__) * (*tr_sh);
     const int N = (n + 1) & ~1;
     const int np = N / 2;
-    for (int sweep = 1; sweep <= kMaxSweeps; ++sweep) {
+    const int cap = d_sweep_cap;
+    for (int sweep = 1; sweep <= cap; ++sweep) {
         if (tid == 0) *flag_sh = 0;
         __syncthreads();
         for (int step = 0; step < N - 1; ++step) {
@@ -420,6 +425,11 @@ void partial_kernel(StoreView st,
 }
 
 }  // namespace
+
+hipError_t set_sweep_cap(int cap)
+{
+    return hipMemcpyToSymbol(HIP_SYMBOL(d_sweep_cap), &cap, sizeof(int), 0, hipMemcpyHostToDevice);
+}
 
 hipError_t launch_finalize(int c, int k, const Prob *probs, int nprob, int kk_max,
                            const double *GYpart, double *Vk, double *F, double rank_tol,

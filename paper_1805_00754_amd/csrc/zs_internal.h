@@ -18,6 +18,9 @@ __device__ __forceinline__ double load_as_double(const uint16_t *p, int64_t i)
     return (double)__uint_as_float((uint32_t)p[i] << 16);
 }
 
+// Jacobi sweep cap of the current device (tests lower it to force ZS_ENOCONV).
+hipError_t set_sweep_cap(int cap);
+
 // Device address of this device's scratch (looked up once per device).
 hipError_t noalloc_scratch(void **ptr);
 hipError_t launch_plan_single(const SinglePlan &p, hipStream_t stream);

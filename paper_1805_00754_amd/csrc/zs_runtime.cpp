@@ -489,6 +489,11 @@ zs_status new_store(int64_t t, int64_t c, int64_t b, int32_t k, zs_mode mode, do
         off[i] = total;
         total = align_up(total + sz[i], 256);
     }
+    size_t mem_free = 0, mem_total = 0;
+    if (hipMemGetInfo(&mem_free, &mem_total) == hipSuccess && total > mem_total)
+        return bail(fail(ZS_ENOMEM, "store arrays need %zu bytes; the device has %zu", total,
+                         mem_total));
+    (void)hipGetLastError();
     hipError_t e = hipMalloc(&st->base, total);
     if (e != hipSuccess)
         return bail(fail(e == hipErrorOutOfMemory ? ZS_ENOMEM : ZS_EDEVICE, "store arrays: %s",
@@ -1319,6 +1324,13 @@ zs_status zs_sync_status(const zs_store *cst, hipStream_t stream)
         HIP_TRY(hipMemcpy(cst->conv, &zero, sizeof(int), hipMemcpyHostToDevice));
         return fail(ZS_ENOCONV, "an eigen-solve hit the sweep cap");
     }
+    return ZS_OK;
+}
+
+zs_status zs_set_sweep_cap(int cap)
+{
+    if (cap < 1) return fail(ZS_EINVAL, "sweep cap %d < 1", cap);
+    HIP_TRY(set_sweep_cap(cap));
     return ZS_OK;
 }
 

@@ -35,7 +35,7 @@ EXPORTED = ["zs_store_blocks", "zs_store_blocks_xi", "zs_store_append", "zs_wind
             "zs_batch_graph_launch", "zs_batch_graph_free", "zs_store_graph_create",
             "zs_store_graph_launch", "zs_store_graph_free", "zs_store_free", "zs_store_bytes",
             "zs_store_info", "zs_store_get_block", "zs_sync_status", "zs_last_error", "zs_version",
-            "zs_timing_enable", "zs_timing_reset", "zs_timing_get", "zs_autotune",
+            "zs_timing_enable", "zs_timing_reset", "zs_timing_get", "zs_set_sweep_cap", "zs_autotune",
             "zs_autotune_force", "zs_autotune_table"]
 
 
@@ -99,6 +99,8 @@ def load(path: str | None = None):
         lib.zs_timing_enable.restype = None
         lib.zs_timing_reset.restype = None
         lib.zs_timing_get.argtypes = [ctypes.c_char_p, _vp, _vp]
+        lib.zs_set_sweep_cap.argtypes = [ctypes.c_int]
+        lib.zs_set_sweep_cap.restype = ctypes.c_int
         lib.zs_autotune.argtypes = [ctypes.c_int]
         lib.zs_autotune.restype = None
         lib.zs_autotune_force.argtypes = [ctypes.c_char_p, ctypes.c_int]
@@ -451,3 +453,8 @@ def zs_autotune_table() -> dict:
         if len(parts) >= 2:
             out[parts[0]] = (int(parts[1]), parts[2] if len(parts) > 2 else "")
     return out
+
+
+def zs_set_sweep_cap(cap: int):
+    """Jacobi sweep cap of the current device (tests of the ZS_ENOCONV path)."""
+    _check(load().zs_set_sweep_cap(cap))
