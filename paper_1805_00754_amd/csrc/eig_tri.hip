@@ -29,6 +29,7 @@
 // one-sided Jacobi.
 #include <atomic>
 #include <cstdio>
+#include <type_traits>
 
 #include "zs_internal.h"
 #include "wave.h"
@@ -240,7 +241,14 @@ void eig_tri_kernel(int c, int k, int region, const Prob *__restrict__ probs,
         const double d1 = readlane_d(x[0], 1);
         if (lane == 0) d[1] = d1;
     }
-    for (int j = 0; j + 2 < c; ++j) {
+    // Step j only touches the trailing block (j, c): v and w are zero outside
+    // it, so the register rows m < M0 (rows below kWaves M0) and the 64-column
+    // chunks s < S0 would only add exact zeros once j reaches them.  The
+    // steps run in phases with compile-time M0, S0 (no branches in the
+    // unrolled loops) that leave those registers out: the same bits with less
+    // per-step element work.
+    auto step = [&](int j, auto m0c, auto s0c) {
+        constexpr int M0 = decltype(m0c)::value, S0 = decltype(s0c)::value;
         __syncthreads();                           // v_j and tau_j are visible
         const double *vc = vbuf + (j & 1) * NMAX;
         const double t = tau[j];
@@ -250,7 +258,7 @@ void eig_tri_kernel(int c, int k, int region, const Prob *__restrict__ probs,
         // which keeps the registers for the matrix)
         double vcl[CPL];
 #pragma unroll
-        for (int s = 0; s < CPL; ++s) vcl[s] = vc[min(lane + 64 * s, NMAX - 1)];
+        for (int s = 0; s < CPL; ++s) vcl[s] = vc[min(lane + 64 * s, NMAX - 1)];   // 0 below S0
         // partial A v over this wave's rows (A symmetric: column sums = row sums)
         // and this wave's share of v^T A v, in kSplit chains (rows w + kWaves m
         // with m of one parity each)
@@ -260,16 +268,16 @@ void eig_tri_kernel(int c, int k, int region, const Prob *__restrict__ probs,
 #pragma unroll
             for (int s = 0; s < CPL; ++s) pp[x][s] = 0.0;
 #pragma unroll
-        for (int m = 0; m < RPW; ++m) {
+        for (int m = M0; m < RPW; ++m) {
             const double vr = vc[wave + kWaves * m];
 #pragma unroll
-            for (int s = 0; s < CPL; ++s) pp[m % kSplit][s] = fma(a[m][s], vr, pp[m % kSplit][s]);
+            for (int s = S0; s < CPL; ++s) pp[m % kSplit][s] = fma(a[m][s], vr, pp[m % kSplit][s]);
         }
 #pragma unroll
         for (int x = 0; x < kSplit; ++x) {
             double vav = 0.0;
 #pragma unroll
-            for (int s = 0; s < CPL; ++s)
+            for (int s = S0; s < CPL; ++s)
                 if (lane + 64 * s < c) vav = fma(pp[x][s], vcl[s], vav);
             vav = wave_sum64(vav);
             if (lane == 0) kpart[wave + kWaves * x] = vav;
@@ -311,12 +319,12 @@ void eig_tri_kernel(int c, int k, int region, const Prob *__restrict__ probs,
             wcol[s] = (C > j && C < c) ? pc - K * vcl[s] : 0.0;
         }
 #pragma unroll
-        for (int m = 0; m < RPW; ++m) {
+        for (int m = M0; m < RPW; ++m) {
             const int R = wave + kWaves * m;
             const double vr = vc[R], pr = psh[R];   // unconditional reads: a select, no branch
             const double wr = (R > j && R < c) ? pr - K * vr : 0.0;
 #pragma unroll
-            for (int s = 0; s < CPL; ++s) {
+            for (int s = S0; s < CPL; ++s) {
                 a[m][s] = fma(-vr, wcol[s], a[m][s]);
                 a[m][s] = fma(-wr, vcl[s], a[m][s]);
             }
@@ -337,6 +345,18 @@ void eig_tri_kernel(int c, int k, int region, const Prob *__restrict__ probs,
             const double xd = readlane_d(v, (c - 1) & 63);
             if (lane == 0) d[c - 1] = xd;
         }
+    
+    };
+    {
+        // two phases: all registers while j < NMAX / 2, then only the trailing
+        // quarter (rows and columns >= NMAX / 2); more phases make the
+        // 512-thread form spill
+        using std::integral_constant;
+        const int jend = c - 2;
+        int j = 0;
+        for (; j < jend && j < NMAX / 2; ++j) step(j, integral_constant<int, 0>(), integral_constant<int, 0>());
+        for (; j < jend; ++j)
+            step(j, integral_constant<int, NMAX / 2 / kWaves>(), integral_constant<int, (NMAX / 2) / 64>());
     }
     __syncthreads();
     if (tid == 0) {

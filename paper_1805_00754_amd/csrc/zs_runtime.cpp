@@ -114,6 +114,9 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct StoreWork {
     std::mutex mu;
     DevBuf Gpart, Vk, GY, F, Ysc, Big, Rows, desc;
+    void *host = nullptr;        // pinned staging of the descriptors
+    size_t host_bytes = 0;
+    hipEvent_t copied = nullptr; // the last upload from `host` has completed
 };
 std::mutex g_swmu;
 std::map<std::pair<int, hipStream_t>, StoreWork *> g_sw;
@@ -203,23 +206,31 @@ constexpr int kStoreChunkRows = 512;       // Gram chunk rows, c <= 128
 constexpr int kStoreChunkRowsWide = 2048;  // c > 128: at least a whole block
 constexpr int kProjChunkRows = 256;   // rows per projection wave (storage phase)
 
-// Upload `bytes` of host data through the workspace's pinned staging buffer.
+// Upload `bytes` of host data to `desc` through a pinned staging buffer
+// (grow-only; `copied` marks the end of its last upload, so that it is not
+// overwritten while a copy from it may still be in flight).
+zs_status upload(DevBuf &desc, void *&host, size_t &host_bytes, hipEvent_t &copied, const void *src,
+                 size_t bytes, hipStream_t stream)
+{
+    if (copied) HIP_TRY(hipEventSynchronize(copied));
+    if (bytes > host_bytes) {
+        if (host) HIP_TRY(hipHostFree(host));
+        host = nullptr;
+        size_t want = std::max(bytes, host_bytes * 2);
+        HIP_TRY(hipHostMalloc(&host, want, hipHostMallocDefault));
+        host_bytes = want;
+    }
+    if (!copied) HIP_TRY(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
+    HIP_TRY(desc.ensure(bytes));
+    std::memcpy(host, src, bytes);
+    HIP_TRY(hipMemcpyAsync(desc.p, host, bytes, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(copied, stream));
+    return ZS_OK;
+}
+
 zs_status upload(Workspace &w, const void *src, size_t bytes, hipStream_t stream)
 {
-    if (w.copied) HIP_TRY(hipEventSynchronize(w.copied));
-    if (bytes > w.host_bytes) {
-        if (w.host) HIP_TRY(hipHostFree(w.host));
-        w.host = nullptr;
-        size_t want = std::max(bytes, w.host_bytes * 2);
-        HIP_TRY(hipHostMalloc(&w.host, want, hipHostMallocDefault));
-        w.host_bytes = want;
-    }
-    if (!w.copied) HIP_TRY(hipEventCreateWithFlags(&w.copied, hipEventDisableTiming));
-    HIP_TRY(w.desc.ensure(bytes));
-    std::memcpy(w.host, src, bytes);
-    HIP_TRY(hipMemcpyAsync(w.desc.p, w.host, bytes, hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipEventRecord(w.copied, stream));
-    return ZS_OK;
+    return upload(w.desc, w.host, w.host_bytes, w.copied, src, bytes, stream);
 }
 
 // Descriptor blob: several typed arrays packed at 256-byte boundaries.
@@ -603,12 +614,14 @@ zs_status store_plan(zs_store *st, const void *A, int64_t lda, zs_dtype a_type, 
     Blob blob;
     const size_t o_chunks = blob.add(chunks), o_probs = blob.add(probs), o_gsrc = blob.add(gsrc);
     const size_t o_leaf = blob.add(leaf_chunks), o_pchunks = blob.add(pchunks);
-    HIP_TRY(sw.desc.ensure(blob.bytes.size()));
-    if (sync_upload)
+    if (sync_upload) {
+        HIP_TRY(sw.desc.ensure(blob.bytes.size()));
         HIP_TRY(hipMemcpy(sw.desc.p, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice));
-    else
-        HIP_TRY(hipMemcpyAsync(sw.desc.p, blob.bytes.data(), blob.bytes.size(),
-                               hipMemcpyHostToDevice, stream));
+    } else {
+        zs_status s = upload(sw.desc, sw.host, sw.host_bytes, sw.copied, blob.bytes.data(),
+                             blob.bytes.size(), stream);
+        if (s != ZS_OK) return s;
+    }
     const char *d = sw.desc.as<char>();
     pl.chunks = (const Chunk *)(d + o_chunks);
     pl.probs = (const Prob *)(d + o_probs);
@@ -620,7 +633,6 @@ zs_status store_plan(zs_store *st, const void *A, int64_t lda, zs_dtype a_type, 
     pl.x_type = a_type == ZS_F32 ? kElemF32 : a_type == ZS_BF16 ? kElemBF16 : kElemF64;
     // the bulk Gram in the mode's arithmetic; everything after it in FP64
     pl.gprec = st->mode == ZS_MODE_FP32 ? kGramF32 : st->mode == ZS_MODE_BF16 ? kGramBF16 : kGramF64;
-    if (!sync_upload) HIP_TRY(hipStreamSynchronize(stream));   // the host blob goes out of scope
     return ZS_OK;
 }
 
@@ -1191,6 +1203,8 @@ void zs_store_graph_free(zs_store_graph *g)
     if (g->w) {
         g->w->Gpart.release(); g->w->Vk.release(); g->w->GY.release(); g->w->F.release();
         g->w->Ysc.release(); g->w->Big.release(); g->w->Rows.release(); g->w->desc.release();
+        if (g->w->host) (void)hipHostFree(g->w->host);
+        if (g->w->copied) (void)hipEventDestroy(g->w->copied);
         delete g->w;
     }
     delete g;
