@@ -31,8 +31,6 @@
 namespace zs {
 namespace {
 
-constexpr int NTH = 1024;
-constexpr int kWaves = NTH / 64;
 constexpr int kBigMax = 1024;             // largest c
 constexpr int kWU = 8;                    // matrix entries per thread in flight in phase 1
 
@@ -44,6 +42,7 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // Sum over the work-group; red holds kWaves doubles.  All threads call it.
+template <int kWaves>
 __device__ __forceinline__ double block_sum(double v, double *red)
 {
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -68,17 +67,21 @@ __device__ __forceinline__ double start_value(int i, int g, int attempt)
     return (double)(x & 0xFFFFFF) / 8388608.0 - 1.0;
 }
 
-// VPL: vector entries per lane in phase 5 (c <= 64 VPL).
-template <int VPL>
-__global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *__restrict__ probs,
+// VPL: vector entries per lane in phase 5 (c <= 64 VPL); NTH threads; CMAX:
+// the largest c of the instantiation (sizes the LDS vectors); NB: steps per
+// panel of the tridiagonal reduction; LCL: the panel's reflector columns in
+// LDS (else in the problem's global scratch).
+template <int VPL, int NTH, int CMAX, int NB, bool LCL>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void eig_big_kernel(int c, int k, const Prob *__restrict__ probs,
                                                       const double *const *__restrict__ gsrc,
                                                       const double *const *__restrict__ msrc,
                                                       double *__restrict__ scratch,
                                                       double *__restrict__ Vk)
 {
-    __shared__ double d[kBigMax], e[kBigMax], e2[kBigMax], tau[kBigMax];
-    __shared__ double vbuf[2][kBigMax], wbuf[2][kBigMax];   // v and p / w of two steps
-    __shared__ double rowb[kBigMax];      // the next row to reduce, from its diagonal on
+    constexpr int kWaves = NTH / 64;
+    __shared__ double d[CMAX], e[CMAX], e2[CMAX], tau[CMAX];
+    __shared__ double vbuf[2][CMAX], wbuf[2][CMAX];   // v and p / w of two steps
+    __shared__ double rowb[CMAX];         // the next row to reduce, from its diagonal on
     __shared__ double xs[NTH];
     __shared__ int cs[NTH];
     __shared__ double lam[kMaxK], glo[kMaxK], ghi[kMaxK], red[kWaves];
@@ -155,16 +158,39 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
         }
     }
 
-    // ---- 2. tridiagonalisation ---------------------------------------------------
-    // Reflector of row jr (final, entries jr .. c-1 in rowb): tau, e, d of jr
-    // and v (length c - jr - 1, v(0) = 1) into vdst and over the dead part of
-    // row jr in W.
+    // ---- 2. tridiagonalisation, blocked ------------------------------------------
+    // Panels of NB Householder steps (the blocked reduction of Golub & Van
+    // Loan 8.3 / LAPACK's latrd).  Within a panel the trailing block of W is
+    // not updated: step j works with A_eff = W - V Wp^T - Wp V^T, where the
+    // columns of V and Wp are the panel's reflectors v and w so far, kept
+    // column-major in Lc (2 NB x c: V then Wp, absolute row index, zero
+    // outside (j, c)).  Step j
+    //   (1) forms row j of A_eff (panel-start row j minus the corrections),
+    //   (2) derives the reflector (tau, e, d of j; v over the dead part of row j),
+    //   (3) q = W v over the trailing block (read only) and the 2t dots
+    //       x = Wp^T v, y = V^T v,
+    //   (4) p = tau (q - V x - Wp y), w = p - (tau/2)(p.v) v, appended to Lc.
+    // After the panel the trailing block takes the whole rank-2NB update
+    // W -= [V Wp] [Wp V]^T on the FP64 matrix cores.  Each step reads the
+    // trailing block once (the unblocked form read and wrote it), and the
+    // panel update reads and writes it once per NB steps.
+    constexpr int RU = 4;                           // rows per wave in flight (3)
+    constexpr int CU = 4;                           // 64-column chunks per row in flight (3)
+    static_assert((NB & (NB - 1)) == 0 && NB >= 2, "NB a power of two");
+    __shared__ double lcs[LCL ? 2 * NB * CMAX : 1];
+    double *Lc = LCL ? lcs : Z;                     // 2 NB x c (Z is free until phase 4)
+    double *vv = vbuf[0];                           // v of the step, local index u = i - j - 1
+    double *qw = wbuf[0];                           // q, then p and w (local index)
+    double *xy = xs;                                // the 2t correction dots
+    // Reflector of row jr (the row of A_eff in rowb, from its diagonal on):
+    // tau, e, d of jr and v (length c - jr - 1, v(0) = 1) into vdst and over
+    // the dead part of row jr in W.
     auto make_reflector = [&](int jr, double *vdst) {
         const int n = c - jr - 1;
         double *rowj = W + (int64_t)jr * c;
         double part = 0.0;
         for (int i = tid + 1; i < n; i += NTH) part = fma(rowb[1 + i], rowb[1 + i], part);
-        const double s = block_sum(part, red);
+        const double s = block_sum<kWaves>(part, red);
         const double alpha = rowb[1];
         double t = 0.0, beta = alpha, scal = 0.0;
         if (s > 0.0) {
@@ -183,106 +209,138 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
         // v_jr replaces the dead entries of row jr (read back in phase 5)
         for (int i = tid; i < n; i += NTH) rowj[jr + 1 + i] = vdst[i];
     };
-    // Step j runs with v_j = vbuf[j & 1] and p_j = t_j W22 v_j in wbuf[j & 1];
-    // j = -1 only forms reflector 0 and p_0.  Row j+1 lives in rowb from the
-    // pass of step j-1 on (the pass that updates it also keeps it there), so
-    // its last update and its reflector take no global round trip.
-    constexpr int RU = 4;                          // rows per wave in flight
-    constexpr int CU = 4;                          // 64-column chunks per row in flight
-    for (int i = tid; i < c; i += NTH) rowb[i] = W[i];   // row 0
-    __syncthreads();
-    for (int j = -1; j + 2 < c; ++j) {
-        const int n1 = c - j - 1;                  // trailing size of step j
-        const double *vc = vbuf[j & 1];
-        double *wc = wbuf[j & 1];
-        double *vn = vbuf[(j + 1) & 1];
-        double *wn = wbuf[(j + 1) & 1];
-        const double t = j >= 0 ? tau[j] : 0.0;
-        const bool upd = t != 0.0;
-        if (upd) {
-            // w = p - K v, K = (t/2) p.v
-            double pk = 0.0;
-            for (int i = tid; i < n1; i += NTH) pk = fma(wc[i], vc[i], pk);
-            const double K = 0.5 * t * block_sum(pk, red);
-            for (int i = tid; i < n1; i += NTH) wc[i] -= K * vc[i];
-            __syncthreads();
-            // row j+1 first: it gives the next reflector
-            const double v0 = vc[0], w0 = wc[0];
-            for (int i = tid; i < n1; i += NTH) rowb[i] -= v0 * wc[i] + w0 * vc[i];
-            __syncthreads();
+    typedef double v4d __attribute__((ext_vector_type(4)));
+    for (int j0 = 0; j0 + 2 < c; j0 += NB) {
+        const int nbp = min(NB, c - 2 - j0);       // steps of this panel
+        // columns of an incomplete panel stay zero in the update
+        for (int q = tid; q < (NB - nbp) * c; q += NTH) {
+            const int t = nbp + q / c, i = q % c;
+            Lc[(int64_t)t * c + i] = 0.0;
+            Lc[(int64_t)(NB + t) * c + i] = 0.0;
         }
-        const bool next = j + 3 < c;
-        if (!next && tid == 0) {                   // row c-2 is final: d and e of it
-            d[c - 2] = rowb[0];
-            e[c - 2] = rowb[1];
-        }
-        if (next) {
-            make_reflector(j + 1, vn);
+        for (int t = 0; t < nbp; ++t) {
+            const int j = j0 + t;
+            const int n = c - j - 1;               // trailing size
+            // (1) row j of A_eff, columns j .. c-1
+            for (int k = j + tid; k < c; k += NTH) {
+                double r = W[(int64_t)j * c + k];
+                for (int s2 = 0; s2 < t; ++s2)
+                    r -= Lc[(int64_t)s2 * c + j] * Lc[(int64_t)(NB + s2) * c + k] +
+                         Lc[(int64_t)(NB + s2) * c + j] * Lc[(int64_t)s2 * c + k];
+                rowb[k - j] = r;
+            }
             __syncthreads();
-        }
-        const double tn = next ? tau[j + 1] : 0.0;
-        const bool dot = tn != 0.0;
-        // rows j+2 .. c-1, columns j+2 .. c-1: update of step j, then p_{j+1}
-        const int nr = n1 - 1;
-        double *Wt = W + (int64_t)(j + 2) * c + j + 2;
-        if (upd || dot) {
-            for (int q0 = wave * RU; q0 < nr; q0 += kWaves * RU) {
-                double vr[RU], wr[RU], acc[RU];
+            // (2) the reflector of row j
+            make_reflector(j, vv);
+            __syncthreads();                       // v is visible; row j of W holds v
+            const double tj = tau[j];
+            // (3) q = W v over rows and columns (j, c) of the panel-start block
+            const double *Wt = W + (int64_t)(j + 1) * c + (j + 1);
+            for (int q0 = wave * RU; q0 < n; q0 += kWaves * RU) {
+                double acc[RU];
 #pragma unroll
-                for (int u = 0; u < RU; ++u) {
-                    const bool live = q0 + u < nr;
-                    vr[u] = (upd && live) ? vc[q0 + u + 1] : 0.0;
-                    wr[u] = (upd && live) ? wc[q0 + u + 1] : 0.0;
-                    acc[u] = 0.0;
-                }
-                for (int i0 = 0; i0 < nr; i0 += 64 * CU) {
-                    double vi[CU], wi[CU], vx[CU], x[RU][CU];
+                for (int u = 0; u < RU; ++u) acc[u] = 0.0;
+                for (int i0 = 0; i0 < n; i0 += 64 * CU) {
+                    double vx[CU], x[RU][CU];
 #pragma unroll
                     for (int h = 0; h < CU; ++h) {
                         const int ip = i0 + 64 * h + lane;
-                        const bool in = ip < nr;
-                        vi[h] = (upd && in) ? vc[ip + 1] : 0.0;
-                        wi[h] = (upd && in) ? wc[ip + 1] : 0.0;
-                        vx[h] = (dot && in) ? vn[ip] : 0.0;
+                        vx[h] = ip < n ? vv[ip] : 0.0;
                     }
 #pragma unroll
                     for (int u = 0; u < RU; ++u)
 #pragma unroll
                         for (int h = 0; h < CU; ++h) {
                             const int ip = i0 + 64 * h + lane;
-                            x[u][h] = (ip < nr && q0 + u < nr) ? Wt[(int64_t)(q0 + u) * c + ip] : 0.0;
+                            x[u][h] = (ip < n && q0 + u < n) ? Wt[(int64_t)(q0 + u) * c + ip] : 0.0;
                         }
 #pragma unroll
                     for (int u = 0; u < RU; ++u)
 #pragma unroll
-                        for (int h = 0; h < CU; ++h) {
-                            const int ip = i0 + 64 * h + lane;
-                            if (upd) {
-                                x[u][h] -= vr[u] * wi[h] + wr[u] * vi[h];
-                                if (ip < nr && q0 + u < nr) Wt[(int64_t)(q0 + u) * c + ip] = x[u][h];
-                            }
-                            acc[u] = fma(x[u][h], vx[h], acc[u]);
-                        }
-                    if (q0 == 0)                   // row j+2, the next row to reduce
-#pragma unroll
-                        for (int h = 0; h < CU; ++h) {
-                            const int ip = i0 + 64 * h + lane;
-                            if (ip < nr) rowb[ip] = x[0][h];
-                        }
+                        for (int h = 0; h < CU; ++h) acc[u] = fma(x[u][h], vx[h], acc[u]);
                 }
-                if (dot) {
 #pragma unroll
-                    for (int u = 0; u < RU; ++u) {
-                        const double sdot = wave_sum64(acc[u]);
-                        if (lane == 0 && q0 + u < nr) wn[q0 + u] = tn * sdot;
-                    }
+                for (int u = 0; u < RU; ++u) {
+                    const double sdot = wave_sum64(acc[u]);
+                    if (lane == 0 && q0 + u < n) qw[q0 + u] = sdot;
                 }
             }
-        } else {
-            for (int i = tid; i < nr; i += NTH) rowb[i] = Wt[i];   // row j+2 as it is
+            // the 2t dots: x_s = Wp(:, s)^T v (dd < t), y_s = V(:, s)^T v
+            // (t <= dd < 2t), half a wave per dot
+            for (int dd = tid / 32; dd < 2 * t; dd += NTH / 32) {
+                const double *col = dd < t ? Lc + (int64_t)(NB + dd) * c : Lc + (int64_t)(dd - t) * c;
+                double acc = 0.0;
+                for (int u = tid % 32; u < n; u += 32) acc = fma(col[j + 1 + u], vv[u], acc);
+                acc = row16_sum(acc);
+                // the two halves' sums, read with wave-uniform lanes
+                const double s0 = readlane_d(acc, 0) + readlane_d(acc, 16);
+                const double s1 = readlane_d(acc, 32) + readlane_d(acc, 48);
+                if ((tid % 32) == 0) xy[dd] = lane < 32 ? s0 : s1;
+            }
+            // both halves of a wave must take part in the lane reads above
+            __syncthreads();
+            // (4) p = tau (q - V x - Wp y), then K = (tau/2) p.v and w = p - K v
+            double pk = 0.0;
+            for (int u = tid; u < n; u += NTH) {
+                const int i = j + 1 + u;
+                double pv = qw[u];
+                for (int s2 = 0; s2 < t; ++s2)
+                    pv -= Lc[(int64_t)s2 * c + i] * xy[s2] + Lc[(int64_t)(NB + s2) * c + i] * xy[t + s2];
+                pv *= tj;
+                qw[u] = pv;
+                pk = fma(pv, vv[u], pk);
+            }
+            const double K = 0.5 * tj * block_sum<kWaves>(pk, red);
+            for (int i = tid; i < c; i += NTH) {
+                const int u = i - j - 1;
+                const double vi = u >= 0 ? vv[u] : 0.0;
+                const double wi = u >= 0 ? qw[u] - K * vi : 0.0;
+                Lc[(int64_t)t * c + i] = vi;
+                Lc[(int64_t)(NB + t) * c + i] = wi;
+            }
+            __syncthreads();                       // the panel's columns are complete
         }
-        __syncthreads();
+        // (5) W(m0:c, m0:c) -= [V Wp] [Wp V]^T: strips of 16 rows x 64 columns,
+        // 4 blocks of 16 x 16, on the FP64 16x16x4 shape.  A(i, s) =
+        // Lc(s, i) in lane i + 16 s, B(s, jj) = Lc(s ^ NB, jj) in lane jj + 16 s,
+        // D(i, jj) in register i / 4 of lane jj + 16 (i mod 4).
+        {
+            const int m0 = j0 + nbp, nt = c - m0;
+            const int nrs = (nt + 15) / 16, ncs = (nt + 63) / 64;
+            for (int st = wave; st < nrs * ncs; st += kWaves) {
+                const int i0 = m0 + 16 * (st / ncs), k0 = m0 + 64 * (st % ncs);
+                v4d acc[4];
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) acc[cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+                const int ia = i0 + lane % 16;
+#pragma unroll 2
+                for (int q = 0; q < 2 * NB / 4; ++q) {
+                    const int sa = 4 * q + lane / 16;
+                    const double a = ia < c ? Lc[(int64_t)sa * c + ia] : 0.0;
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb) {
+                        const int kb = k0 + 16 * cb + lane % 16;
+                        const double bv = kb < c ? Lc[(int64_t)(sa ^ NB) * c + kb] : 0.0;
+                        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[cb], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = i0 + 4 * v + lane / 16, kx = k0 + 16 * cb + lane % 16;
+                        if (i < c && kx < c) W[(int64_t)i * c + kx] -= acc[cb][v];
+                    }
+            }
+        }
+        __syncthreads();                           // the trailing block is updated
     }
+    if (tid == 0) {                                // the last 2 x 2 block
+        d[c - 2] = W[(int64_t)(c - 2) * c + c - 2];
+        e[c - 2] = W[(int64_t)(c - 2) * c + c - 1];
+        rowb[0] = W[(int64_t)(c - 1) * c + c - 1];
+    }
+    __syncthreads();
     if (tid == 0) {
         d[c - 1] = rowb[0];                        // row c-1, kept by the last pass
         double gl = d[0], gu = d[0], emax2 = 0.0;
@@ -510,7 +568,7 @@ __global__ __launch_bounds__(NTH) void eig_big_kernel(int c, int k, const Prob *
                 Z[(int64_t)i * kk + g] = v;
                 sn = fma(v, v, sn);
             }
-            const double nrm2 = block_sum(sn, red);
+            const double nrm2 = block_sum<kWaves>(sn, red);
             if (pass == 1 && nrm2 < 0.25 && attempt < c) {
                 for (int i = tid; i < c; i += NTH)
                     Z[(int64_t)i * kk + g] = (i == (g + attempt) % c) ? 1.0 : 0.0;
@@ -539,9 +597,18 @@ hipError_t launch_eig_big(int c, int k, const Prob *probs, int nprob, const doub
     if (nprob <= 0) return hipSuccess;
     if (c > kBigMax) return hipErrorInvalidValue;
     timing_begin("eig", stream);
-    if (c <= 256) eig_big_kernel<4><<<nprob, NTH, 0, stream>>>(c, k, probs, gsrc, msrc, scratch, Vk);
-    else if (c <= 512) eig_big_kernel<8><<<nprob, NTH, 0, stream>>>(c, k, probs, gsrc, msrc, scratch, Vk);
-    else eig_big_kernel<16><<<nprob, NTH, 0, stream>>>(c, k, probs, gsrc, msrc, scratch, Vk);
+    // c <= 256: 512 threads and LDS sized for 256, so that two matrices share
+    // a CU (the steps of one matrix are latency-bound at this size); the same
+    // form for every launch, so a problem's bits do not depend on the batch
+    if (c <= 256)
+        eig_big_kernel<4, 512, 256, 8, true><<<nprob, 512, 0, stream>>>(c, k, probs, gsrc, msrc,
+                                                                         scratch, Vk);
+    else if (c <= 512)
+        eig_big_kernel<8, 1024, kBigMax, 16, false><<<nprob, 1024, 0, stream>>>(c, k, probs, gsrc,
+                                                                                msrc, scratch, Vk);
+    else
+        eig_big_kernel<16, 1024, kBigMax, 16, false><<<nprob, 1024, 0, stream>>>(c, k, probs, gsrc,
+                                                                                 msrc, scratch, Vk);
     hipError_t e = hipGetLastError();
     timing_end("eig", stream);
     return e;
