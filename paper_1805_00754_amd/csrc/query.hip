@@ -166,22 +166,23 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void *p, int bytes)
     return __builtin_amdgcn_make_buffer_rsrc(q, 0, __builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 
-// aux 2: nontemporal; the output is written once and not read back here
-__device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, int off, double v)
+// Plain stores (aux 0): with the nontemporal hint (aux 2) the product of the
+// 1,024-query batch of 320,000-row ranges (52 GB of output) ran 4 % slower.
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, double v)
 {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v),
-                                          r, off, 0, 2);
+                                          r, off, 0, 0);
 }
-__device__ __forceinline__ void buf_store2_nt(__amdgpu_buffer_rsrc_t r, int off, double a, double b)
+__device__ __forceinline__ void buf_store2(__amdgpu_buffer_rsrc_t r, int off, double a, double b)
 {
     typedef unsigned u4 __attribute__((ext_vector_type(4)));
     typedef double d2 __attribute__((ext_vector_type(2)));
     const d2 v = {a, b};
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, off, 0, 2);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, off, 0, 0);
 }
-__device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, int off, float v)
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 2);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
 }
 
 // Element e of a buffer of TU, as double; the pinned form is volatile (aux bit
@@ -204,7 +205,7 @@ __device__ __forceinline__ double buf_elem(__amdgpu_buffer_rsrc_t r, int e)
 //   2. A fragments (16 rows x 4 columns) come from LDS; four row blocks times
 //      ceil(k_q / 16) column blocks of 16 x 16 accumulators, KM / 4 steps;
 //   3. the accumulators go back through LDS (row stride k_q) and are written
-//      with coalesced nontemporal stores.
+//      with coalesced 16-byte stores.
 // Operand layout of v_mfma_f64_16x16x4f64 (wave of 64 lanes): A(i, s) in lane
 // i + 16 s, B(s, j) in lane j + 16 s, D(i, j) in register i / 4 of lane
 // j + 16 (i mod 4).
@@ -286,10 +287,10 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
         const __amdgpu_buffer_rsrc_t none = buf(out, 0);
         if constexpr (CONTIG && sizeof(TU) == 8) {
 #pragma unroll
-            for (int i = 0; i < KM / 2; ++i) buf_store2_nt(none, (lane + i * kProdRows) * 16, 0.0, 0.0);
+            for (int i = 0; i < KM / 2; ++i) buf_store2(none, (lane + i * kProdRows) * 16, 0.0, 0.0);
         } else {
 #pragma unroll
-            for (int i = 0; i < KM; ++i) buf_store_nt(none, (lane + i * kProdRows) * (int)sizeof(TU), (TU)0);
+            for (int i = 0; i < KM; ++i) buf_store(none, (lane + i * kProdRows) * (int)sizeof(TU), (TU)0);
         }
     }
     for (int t = 0; t < ntiles; ++t) {
@@ -350,14 +351,14 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
 #pragma unroll
                 for (int i = 0; i < KM / 2; ++i) {
                     const int e = 2 * (lane + i * kProdRows);
-                    buf_store2_nt(r, e * 8, tile[e], tile[e + 1]);
+                    buf_store2(r, e * 8, tile[e], tile[e + 1]);
                 }
                 const int n = nr * kq;
-                if (n & 1) buf_store_nt(r, (n - 1) * 8, tile[n - 1]);
+                if (n & 1) buf_store(r, (n - 1) * 8, tile[n - 1]);
             } else {
 #pragma unroll
                 for (int i = 0; i < KM; ++i)
-                    buf_store_nt(r, (lane + i * kProdRows) * (int)sizeof(TU), (TU)tile[lane + i * kProdRows]);
+                    buf_store(r, (lane + i * kProdRows) * (int)sizeof(TU), (TU)tile[lane + i * kProdRows]);
             }
         } else {
             const int n = nr * kq;
