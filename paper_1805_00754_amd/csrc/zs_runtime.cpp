@@ -290,6 +290,23 @@ zs_status query_plan(zs_store *st, int32_t nq, const int64_t *ts, const int64_t 
         c_elems += (int64_t)np * kp * kq[q];
         npieces64 += np;
     }
+    // Chunks in the order of their first block (a counting sort, stable): the
+    // chunks of different queries that read the same store rows Sigma_(i)
+    // V_(i)^T then run together and find them in L2.  Every chunk writes only
+    // through its own offsets and slot, so the order changes no result.
+    {
+        std::vector<int32_t> first(st->nb + 1, 0);
+        std::vector<int64_t> key(chunks.size());
+        for (size_t i = 0; i < chunks.size(); ++i) {
+            const StackChunk &ch = chunks[i];
+            key[i] = qds[ch.prob].S + (ch.piece0 - (int64_t)qds[ch.prob].piece0);
+            ++first[key[i] + 1];
+        }
+        for (int64_t b = 0; b < st->nb; ++b) first[b + 1] += first[b];
+        std::vector<StackChunk> sorted(chunks.size());
+        for (size_t i = 0; i < chunks.size(); ++i) sorted[first[key[i]]++] = chunks[i];
+        chunks.swap(sorted);
+    }
     std::vector<int32_t> &pidx = sink.pidx;
     std::vector<int64_t> &gsrc_off = sink.gsrc;
     std::vector<int32_t> &msrc_idx = sink.msrc;
