@@ -1,20 +1,16 @@
 // Leading eigenvectors of a symmetric positive semi-definite c x c Gram matrix
-// for 128 < c <= 1024, one work-group of 1024 threads per matrix, with the
-// matrix in a global scratch slot (L2 / Infinity Cache resident) and the
-// vectors of each step in LDS.  Same method as the solver for c <= 128
+// for 128 < c <= 1024, one work-group per matrix (512 threads up to c = 256,
+// 1024 above), with the matrix in a global scratch slot and the vectors of
+// each step in LDS.  Same method as the solver for c <= 128
 // (eig_tri.hip), whose matrix fits in registers:
 //
 //   1. W <- the problem's Gram terms (tree nodes / block chunk Grams, then the
 //      Grams of its Partial-SVD rows), in a fixed order.
-//   2. Householder tridiagonalisation Q^T W Q = T, one reflector per step:
-//      the reflector of row j (rows are contiguous, the matrix is kept
-//      symmetric) is formed in LDS and saved over the dead part of row j;
-//      p = t W22 v, W22 -= v w^T + w v^T.  The update of step j and the
-//      product of step j+1 share one pass over the trailing rows: row j+1
-//      (kept in LDS by the previous pass) is updated first and gives the next
-//      reflector, then every other trailing row is updated and multiplied by
-//      it while in registers (each wave takes several rows at a time, so
-//      their loads overlap).
+//   2. Householder tridiagonalisation Q^T W Q = T in panels of NB steps
+//      (blocked, below): the reflector of row j is formed in LDS and saved
+//      over the dead part of row j; within a panel the trailing block is
+//      only read (one matrix-vector product per step), and after the panel
+//      it takes the panel's rank-2NB update on the FP64 matrix cores.
 //   3. The kk largest eigenvalues of T by multisection on Sturm counts.
 //   4. Eigenvectors of T by inverse iteration (tridiagonal LU with partial
 //      pivoting, two solves, one thread per cluster of eigenvalues closer
