@@ -76,7 +76,8 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void e
 {
     constexpr int kWaves = NTH / 64;
     __shared__ double d[CMAX], e[CMAX], e2[CMAX], tau[CMAX];
-    __shared__ double vbuf[2][CMAX], wbuf[2][CMAX];   // v and p / w of two steps
+    __shared__ double vbuf[CMAX], wbuf[CMAX];   // v and p / w of a step
+    __shared__ double colb[CMAX];         // the next step's panel-start column
     __shared__ double rowb[CMAX];         // the next row to reduce, from its diagonal on
     __shared__ double xs[NTH];
     __shared__ int cs[NTH];
@@ -160,23 +161,27 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void e
     // not updated: step j works with A_eff = W - V Wp^T - Wp V^T, where the
     // columns of V and Wp are the panel's reflectors v and w so far, kept
     // column-major in Lc (2 NB x c: V then Wp, absolute row index, zero
-    // outside (j, c)).  Step j
-    //   (1) forms row j of A_eff (panel-start row j minus the corrections),
+    // outside (j, c)).  Only the lower triangle of the trailing block is
+    // kept (W is symmetric); the upper part of row j is free for v_j.
+    // Step j
+    //   (1) forms row j of A_eff (panel-start column j minus the corrections),
     //   (2) derives the reflector (tau, e, d of j; v over the dead part of row j),
-    //   (3) q = W v over the trailing block (read only) and the 2t dots
-    //       x = Wp^T v, y = V^T v,
+    //   (3) q = W v over the lower triangle of the trailing block (read only)
+    //       and the 2t dots x = Wp^T v, y = V^T v,
     //   (4) p = tau (q - V x - Wp y), w = p - (tau/2)(p.v) v, appended to Lc.
-    // After the panel the trailing block takes the whole rank-2NB update
-    // W -= [V Wp] [Wp V]^T on the FP64 matrix cores.  Each step reads the
-    // trailing block once (the unblocked form read and wrote it), and the
-    // panel update reads and writes it once per NB steps.
+    // After the panel the lower triangle of the trailing block takes the
+    // whole rank-2NB update W -= [V Wp] [Wp V]^T on the FP64 matrix cores.
+    // Each step reads half the trailing block once (the unblocked form read
+    // and wrote all of it), and the panel update reads and writes half of
+    // it once per NB steps.
     constexpr int RU = 4;                           // rows per wave in flight (3)
-    constexpr int CU = 4;                           // 64-column chunks per row in flight (3)
+    constexpr int HM = CMAX / 64;                   // 64-column chunks of a row, at most
     static_assert((NB & (NB - 1)) == 0 && NB >= 2, "NB a power of two");
     __shared__ double lcs[LCL ? 2 * NB * CMAX : 1];
     double *Lc = LCL ? lcs : Z;                     // 2 NB x c (Z is free until phase 4)
-    double *vv = vbuf[0];                           // v of the step, local index u = i - j - 1
-    double *qw = wbuf[0];                           // q, then p and w (local index)
+    double *vv = vbuf;                              // v of the step, local index u = i - j - 1
+    double *qw = wbuf;                              // q, then p and w (local index)
+    double *Pw = Z + (LCL ? 0 : (int64_t)2 * NB * c);   // kWaves x c column sums of step (3)
     double *xy = xs;                                // the 2t correction dots
     // Reflector of row jr (the row of A_eff in rowb, from its diagonal on):
     // tau, e, d of jr and v (length c - jr - 1, v(0) = 1) into vdst and over
@@ -217,9 +222,11 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void e
         for (int t = 0; t < nbp; ++t) {
             const int j = j0 + t;
             const int n = c - j - 1;               // trailing size
-            // (1) row j of A_eff, columns j .. c-1
+            // (1) row j of A_eff, columns j .. c-1, from the panel-start column j
+            // (lower triangle: read at the panel's first step, else saved by
+            // the previous step's product)
             for (int k = j + tid; k < c; k += NTH) {
-                double r = W[(int64_t)j * c + k];
+                double r = t == 0 ? W[(int64_t)k * c + j] : colb[k];
                 for (int s2 = 0; s2 < t; ++s2)
                     r -= Lc[(int64_t)s2 * c + j] * Lc[(int64_t)(NB + s2) * c + k] +
                          Lc[(int64_t)(NB + s2) * c + j] * Lc[(int64_t)s2 * c + k];
@@ -230,36 +237,54 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void e
             make_reflector(j, vv);
             __syncthreads();                       // v is visible; row j of W holds v
             const double tj = tau[j];
-            // (3) q = W v over rows and columns (j, c) of the panel-start block
+            // (3) q = W v over rows and columns (j, c) of the panel-start block,
+            // from its lower triangle: element (i, l), l <= i, adds W(i, l) v_l
+            // to q_i (row sum, one wave sum per row) and, for l < i, W(i, l) v_i
+            // to q_l (column sums kept per lane over the wave's rows, then
+            // added across the waves in a fixed order in step (4)).
             const double *Wt = W + (int64_t)(j + 1) * c + (j + 1);
+            double colacc[HM];
+#pragma unroll
+            for (int h = 0; h < HM; ++h) colacc[h] = 0.0;
             for (int q0 = wave * RU; q0 < n; q0 += kWaves * RU) {
-                double acc[RU];
+                double acc[RU], vi[RU];
 #pragma unroll
-                for (int u = 0; u < RU; ++u) acc[u] = 0.0;
-                for (int i0 = 0; i0 < n; i0 += 64 * CU) {
-                    double vx[CU], x[RU][CU];
+                for (int u = 0; u < RU; ++u) {
+                    acc[u] = 0.0;
+                    vi[u] = q0 + u < n ? vv[q0 + u] : 0.0;
+                }
+                const int hl = min(q0 + RU, n) - 1;        // the group's last (longest) row
 #pragma unroll
-                    for (int h = 0; h < CU; ++h) {
-                        const int ip = i0 + 64 * h + lane;
-                        vx[h] = ip < n ? vv[ip] : 0.0;
-                    }
+                for (int h = 0; h < HM; ++h) {
+                    if (64 * h <= hl) {
+                        const int l = 64 * h + lane;
+                        const double vl = l < n ? vv[l] : 0.0;
+                        double x[RU];
 #pragma unroll
-                    for (int u = 0; u < RU; ++u)
+                        for (int u = 0; u < RU; ++u)
+                            x[u] = (l <= q0 + u && q0 + u < n) ? Wt[(int64_t)(q0 + u) * c + l] : 0.0;
 #pragma unroll
-                        for (int h = 0; h < CU; ++h) {
-                            const int ip = i0 + 64 * h + lane;
-                            x[u][h] = (ip < n && q0 + u < n) ? Wt[(int64_t)(q0 + u) * c + ip] : 0.0;
+                        for (int u = 0; u < RU; ++u) {
+                            acc[u] = fma(x[u], vl, acc[u]);
+                            colacc[h] = fma(l < q0 + u ? x[u] : 0.0, vi[u], colacc[h]);
                         }
+                        if (h == 0 && lane == 0) {         // column j + 1 for the next step
 #pragma unroll
-                    for (int u = 0; u < RU; ++u)
-#pragma unroll
-                        for (int h = 0; h < CU; ++h) acc[u] = fma(x[u][h], vx[h], acc[u]);
+                            for (int u = 0; u < RU; ++u)
+                                if (q0 + u < n) colb[j + 1 + q0 + u] = x[u];
+                        }
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < RU; ++u) {
                     const double sdot = wave_sum64(acc[u]);
                     if (lane == 0 && q0 + u < n) qw[q0 + u] = sdot;
                 }
+            }
+#pragma unroll
+            for (int h = 0; h < HM; ++h) {
+                const int l = 64 * h + lane;
+                if (l < n) Pw[(int64_t)wave * c + l] = colacc[h];
             }
             // the 2t dots: x_s = Wp(:, s)^T v (dd < t), y_s = V(:, s)^T v
             // (t <= dd < 2t), half a wave per dot
@@ -280,6 +305,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void e
             for (int u = tid; u < n; u += NTH) {
                 const int i = j + 1 + u;
                 double pv = qw[u];
+                for (int w2 = 0; w2 < kWaves; ++w2) pv += Pw[(int64_t)w2 * c + u];
                 for (int s2 = 0; s2 < t; ++s2)
                     pv -= Lc[(int64_t)s2 * c + i] * xy[s2] + Lc[(int64_t)(NB + s2) * c + i] * xy[t + s2];
                 pv *= tj;
@@ -305,6 +331,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void e
             const int nrs = (nt + 15) / 16, ncs = (nt + 63) / 64;
             for (int st = wave; st < nrs * ncs; st += kWaves) {
                 const int i0 = m0 + 16 * (st / ncs), k0 = m0 + 64 * (st % ncs);
+                if (k0 > i0 + 15) continue;             // above the diagonal: not kept
                 v4d acc[4];
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) acc[cb] = (v4d){0.0, 0.0, 0.0, 0.0};
@@ -333,7 +360,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void e
     }
     if (tid == 0) {                                // the last 2 x 2 block
         d[c - 2] = W[(int64_t)(c - 2) * c + c - 2];
-        e[c - 2] = W[(int64_t)(c - 2) * c + c - 1];
+        e[c - 2] = W[(int64_t)(c - 1) * c + c - 2];
         rowb[0] = W[(int64_t)(c - 1) * c + c - 1];
     }
     __syncthreads();
@@ -600,8 +627,8 @@ hipError_t launch_eig_big(int c, int k, const Prob *probs, int nprob, const doub
         eig_big_kernel<4, 512, 256, 8, true><<<nprob, 512, 0, stream>>>(c, k, probs, gsrc, msrc,
                                                                          scratch, Vk);
     else if (c <= 512)
-        eig_big_kernel<8, 1024, kBigMax, 16, false><<<nprob, 1024, 0, stream>>>(c, k, probs, gsrc,
-                                                                                msrc, scratch, Vk);
+        eig_big_kernel<8, 1024, 512, 16, false><<<nprob, 1024, 0, stream>>>(c, k, probs, gsrc, msrc,
+                                                                            scratch, Vk);
     else
         eig_big_kernel<16, 1024, kBigMax, 16, false><<<nprob, 1024, 0, stream>>>(c, k, probs, gsrc,
                                                                                  msrc, scratch, Vk);
