@@ -178,6 +178,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void e
     constexpr int HM = CMAX / 64;                   // 64-column chunks of a row, at most
     static_assert((NB & (NB - 1)) == 0 && NB >= 2, "NB a power of two");
     __shared__ double lcs[LCL ? 2 * NB * CMAX : 1];
+    __shared__ double gsh[LCL ? 1 : kMaxK * kMaxK];   // phase 6 (lcs serves when LCL)
     double *Lc = LCL ? lcs : Z;                     // 2 NB x c (Z is free until phase 4)
     double *vv = vbuf;                              // v of the step, local index u = i - j - 1
     double *qw = wbuf;                              // q, then p and w (local index)
@@ -521,7 +522,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void e
     //      next reflector is loaded while this one is applied (above, the
     //      registers are not there for it).
     {
-        constexpr int CPP = VPL <= 4 ? 4 : (VPL <= 8 ? 2 : 1);
+        constexpr int CPP = VPL <= 4 ? 4 : 2;
         constexpr bool PRE = VPL <= 8;
         auto vload = [&](int j, double (&v)[VPL]) {
             const double *vj = W + (int64_t)max(j, 0) * c + max(j, 0) + 1;   // v_j(i') at vj[i']
@@ -572,8 +573,130 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void e
     }
     __syncthreads();
 
-    // ---- 6. classical Gram-Schmidt, twice -----------------------------------------
-    for (int g = 0; g < kk; ++g) {
+    // ---- 6. orthonormalisation: Cholesky QR, twice ----------------------------------
+    //      G = Z^T Z (4 x 4 blocks of its upper triangle, P threads of one wave
+    //      per block, summed by a fixed butterfly), G = R^T R by one wave,
+    //      R^-1 by one wave (row a of R^-1 is lane a's), Z <- Z R^-1 one row
+    //      per thread (16-column blocks from the last, in place).  Z R^-1 is
+    //      the Gram-Schmidt basis of Z; a pivot below 1/4 (a column that
+    //      collapses, only in a degenerate eigenspace) sends the vectors to
+    //      classical Gram-Schmidt below instead.
+    double *Gs = LCL ? lcs : gsh;                   // kk x kk: R above the diagonal, R^-1 below
+    double *rdi = xs;                               // diagonal of R^-1
+    bool chol_ok = true;
+    for (int round = 0; round < 2 && chol_ok; ++round) {
+        {
+            const int nb4 = (kk + 3) / 4, nblk = nb4 * (nb4 + 1) / 2;
+            int P = 64;
+            while (P > 1 && P * nblk > NTH) P >>= 1;
+            const int blk = tid / P, part = tid % P;
+            double acc[4][4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+            int ba = 0, bb = 0;
+            if (blk < nblk) {
+                int r = blk;
+                while (r >= nb4 - ba) {
+                    r -= nb4 - ba;
+                    ++ba;
+                }
+                bb = ba + r;
+                for (int i = part; i < c; i += P) {
+                    const double *zr = Z + (int64_t)i * kk;
+                    double za[4], zb[4];
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) {
+                        za[x] = 4 * ba + x < kk ? zr[4 * ba + x] : 0.0;
+                        zb[x] = 4 * bb + x < kk ? zr[4 * bb + x] : 0.0;
+                    }
+#pragma unroll
+                    for (int x = 0; x < 4; ++x)
+#pragma unroll
+                        for (int y = 0; y < 4; ++y) acc[x][y] = fma(za[x], zb[y], acc[x][y]);
+                }
+            }
+            for (int off = P / 2; off >= 1; off >>= 1)
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] += __shfl_xor(acc[x][y], off, 64);
+            if (blk < nblk && part == 0)
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) {
+                        const int a = 4 * ba + x, b = 4 * bb + y;
+                        if (a < kk && b < kk) Gs[a * kk + b] = acc[x][y];
+                    }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // right-looking Cholesky on the upper triangle, lane l owns column l
+            int good = 1;
+            for (int jj = 0; jj < kk; ++jj) {
+                const double djj = Gs[jj * kk + jj];
+                good &= djj > 0.25;
+                const double rjj = sqrt(fmax(djj, 0.25));
+                const double rjl = (lane > jj && lane < kk) ? Gs[jj * kk + lane] / rjj : 0.0;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (lane == jj) Gs[jj * kk + jj] = rjj;
+                if (lane > jj && lane < kk) Gs[jj * kk + lane] = rjl;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int lp = jj + 1; lp < kk; ++lp) {
+                    const double r1 = Gs[jj * kk + lp];
+                    if (lane >= lp && lane < kk) Gs[lp * kk + lane] -= r1 * rjl;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            // R^-1: lane a computes row a, left to right
+            if (lane < kk) {
+                const int a = lane;
+                const double ra = 1.0 / Gs[a * kk + a];
+                rdi[a] = ra;
+                for (int b = a + 1; b < kk; ++b) {
+                    double sum = ra * Gs[a * kk + b];
+                    for (int p2 = a + 1; p2 < b; ++p2) sum = fma(Gs[p2 * kk + a], Gs[p2 * kk + b], sum);
+                    Gs[b * kk + a] = -sum / Gs[b * kk + b];
+                }
+            }
+            if (lane == 0) sh_done = good;
+        }
+        __syncthreads();
+        chol_ok = sh_done != 0;
+        if (!chol_ok) break;
+        for (int i = tid; i < c; i += NTH) {
+            double *zr = Z + (int64_t)i * kk;
+            for (int b0 = ((kk - 1) / 16) * 16; b0 >= 0; b0 -= 16) {
+                double acc[16];
+#pragma unroll
+                for (int y = 0; y < 16; ++y) acc[y] = 0.0;
+                const int amax = min(b0 + 16, kk);
+                for (int a = 0; a < amax; ++a) {
+                    const double za = zr[a];
+#pragma unroll
+                    for (int y = 0; y < 16; ++y) {
+                        const int b = b0 + y;
+                        if (b < kk && a <= b) acc[y] = fma(za, a == b ? rdi[a] : Gs[b * kk + a], acc[y]);
+                    }
+                }
+#pragma unroll
+                for (int y = 0; y < 16; ++y)
+                    if (b0 + y < kk) zr[b0 + y] = acc[y];
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+    // ---- 6b. classical Gram-Schmidt, twice (when Cholesky QR stopped) -----------------
+    for (int g = 0; g < (chol_ok ? 0 : kk); ++g) {
         int attempt = 0;
         for (int pass = 0; pass < 2; ++pass) {
             for (int h = wave; h < g; h += kWaves) {
