@@ -94,27 +94,31 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void e
     double *LU = Z + (int64_t)c * kMaxK;            // 4 arrays of c per solver thread
     double *out = Vk + (int64_t)blockIdx.x * c * kMaxK;
 
-    // ---- 1. W ------------------------------------------------------------------
+    // ---- 1. W (its lower triangle, the only part phase 2 reads) ------------------
     //      Each thread sums kWU entries at a time (independent loads in flight),
-    //      each entry in the fixed term order.
-    const int64_t cc = (int64_t)c * c;
-    for (int64_t q0 = tid; q0 < cc; q0 += (int64_t)NTH * kWU) {
+    //      each entry in the fixed term order.  Entries run over the packed
+    //      lower triangle, row by row: q = i (i + 1) / 2 + l, l <= i.
+    const int64_t cl = (int64_t)c * (c + 1) / 2;
+    for (int64_t q0 = tid; q0 < cl; q0 += (int64_t)NTH * kWU) {
         double s[kWU];
+        int64_t at[kWU];
 #pragma unroll
-        for (int x = 0; x < kWU; ++x) s[x] = 0.0;
+        for (int x = 0; x < kWU; ++x) {
+            s[x] = 0.0;
+            const int64_t q = min(q0 + (int64_t)x * NTH, cl - 1);
+            int64_t i = (int64_t)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+            while (i * (i + 1) / 2 > q) --i;
+            while ((i + 1) * (i + 2) / 2 <= q) ++i;
+            at[x] = i * c + (q - i * (i + 1) / 2);
+        }
         for (int g = 0; g < P.ng; ++g) {
             const double *src = gsrc[P.g0 + g];
 #pragma unroll
-            for (int x = 0; x < kWU; ++x) {
-                const int64_t q = q0 + (int64_t)x * NTH;
-                if (q < cc) s[x] += src[q];
-            }
+            for (int x = 0; x < kWU; ++x) s[x] += src[at[x]];
         }
 #pragma unroll
-        for (int x = 0; x < kWU; ++x) {
-            const int64_t q = q0 + (int64_t)x * NTH;
-            if (q < cc) W[q] = s[x];
-        }
+        for (int x = 0; x < kWU; ++x)
+            if (q0 + (int64_t)x * NTH < cl) W[at[x]] = s[x];
     }
     __syncthreads();
     // Grams of the Partial-SVD rows: W += R^T R, R k x c.  Each thread owns
@@ -127,6 +131,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void e
             const double *R = msrc[P.m0 + m];                   // k x c rows
             for (int tt = tid; tt < nti * ntj; tt += NTH) {
                 const int i0 = (tt / ntj) * TI, j0 = (tt % ntj) * TJ;
+                if (j0 > i0 + TI - 1) continue;           // no entry on or below the diagonal
                 double acc[TI][TJ];
 #pragma unroll
                 for (int a = 0; a < TI; ++a)
@@ -323,38 +328,70 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4))) void e
             }
             __syncthreads();                       // the panel's columns are complete
         }
-        // (5) W(m0:c, m0:c) -= [V Wp] [Wp V]^T: strips of 16 rows x 64 columns,
-        // 4 blocks of 16 x 16, on the FP64 16x16x4 shape.  A(i, s) =
-        // Lc(s, i) in lane i + 16 s, B(s, jj) = Lc(s ^ NB, jj) in lane jj + 16 s,
-        // D(i, jj) in register i / 4 of lane jj + 16 (i mod 4).
+        // (5) W(m0:c, m0:c) -= [V Wp] [Wp V]^T on its lower triangle, on the
+        // FP64 16x16x4 shape: a wave takes a strip of 16 rows (its A
+        // fragments A(i, s) = Lc(s, i) in lane i + 16 s stay in registers)
+        // and walks its 16 x 16 blocks up to the diagonal;
+        // B(s, jj) = Lc(s ^ NB, jj) in lane jj + 16 s, D(i, jj) in register
+        // i / 4 of lane jj + 16 (i mod 4).
         {
-            const int m0 = j0 + nbp, nt = c - m0;
-            const int nrs = (nt + 15) / 16, ncs = (nt + 63) / 64;
-            for (int st = wave; st < nrs * ncs; st += kWaves) {
-                const int i0 = m0 + 16 * (st / ncs), k0 = m0 + 64 * (st % ncs);
-                if (k0 > i0 + 15) continue;             // above the diagonal: not kept
-                v4d acc[4];
-#pragma unroll
-                for (int cb = 0; cb < 4; ++cb) acc[cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+            const int m0 = j0 + nbp;
+            const int nrs = (c - m0 + 15) / 16;
+            constexpr int QS = 2 * NB / 4;             // MFMA steps over the 2 NB columns
+            for (int r = wave; r < nrs; r += kWaves) {
+                const int i0 = m0 + 16 * r;
                 const int ia = i0 + lane % 16;
-#pragma unroll 2
-                for (int q = 0; q < 2 * NB / 4; ++q) {
-                    const int sa = 4 * q + lane / 16;
-                    const double a = ia < c ? Lc[(int64_t)sa * c + ia] : 0.0;
+                double af[QS];
 #pragma unroll
-                    for (int cb = 0; cb < 4; ++cb) {
-                        const int kb = k0 + 16 * cb + lane % 16;
-                        const double bv = kb < c ? Lc[(int64_t)(sa ^ NB) * c + kb] : 0.0;
-                        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[cb], 0, 0, 0);
+                for (int q = 0; q < QS; ++q) {
+                    const int sa = 4 * q + lane / 16;
+                    if constexpr (LCL) {
+                        af[q] = ia < c ? Lc[(int64_t)sa * c + ia] : 0.0;
+                    } else {
+                        const double ar = Lc[(int64_t)sa * c + min(ia, c - 1)];
+                        af[q] = ia < c ? ar : 0.0;
                     }
                 }
+                const int nblk = r + 1;                // blocks from column m0 to the diagonal
+                for (int b0 = 0; b0 < nblk; ++b0) {
+                    v4d acc = (v4d){0.0, 0.0, 0.0, 0.0};
+                    const int kb = m0 + 16 * b0 + lane % 16, kc = min(kb, c - 1);
+                    if constexpr (LCL) {
+                        // panel columns in LDS: loads as needed
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
+                        for (int q = 0; q < QS; ++q) {
+                            const int sb = (4 * q + lane / 16) ^ NB;
+                            const double bv = kb < c ? Lc[(int64_t)sb * c + kb] : 0.0;
+                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af[q], bv, acc, 0, 0, 0);
+                        }
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int i = i0 + 4 * v + lane / 16, kx = k0 + 16 * cb + lane % 16;
-                        if (i < c && kx < c) W[(int64_t)i * c + kx] -= acc[cb][v];
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = i0 + 4 * v + lane / 16;
+                            if (i < c && kb < c) W[(int64_t)i * c + kb] -= acc[v];
+                        }
+                    } else {
+                        // panel columns and W from cache: every load issued
+                        // (clamped) before the first use
+                        double bv[QS], wv[4];
+#pragma unroll
+                        for (int q = 0; q < QS; ++q) {
+                            const int sb = (4 * q + lane / 16) ^ NB;
+                            const double br = Lc[(int64_t)sb * c + kc];
+                            bv[q] = kb < c ? br : 0.0;
+                        }
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            wv[v] = W[(int64_t)min(i0 + 4 * v + lane / 16, c - 1) * c + kc];
+#pragma unroll
+                        for (int q = 0; q < QS; ++q)
+                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af[q], bv[q], acc, 0, 0, 0);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = i0 + 4 * v + lane / 16;
+                            if (i < c && kb < c) W[(int64_t)i * c + kb] = wv[v] - acc[v];
+                        }
                     }
+                }
             }
         }
         __syncthreads();                           // the trailing block is updated
