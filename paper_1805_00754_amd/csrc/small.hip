@@ -279,7 +279,10 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, int k, const 
     }
 }
 
-constexpr int kPartialRows = 16;   // rows of P staged in LDS at a time
+// Rows of P staged in LDS at a time: 16, or 8 above k = 32 so that two
+// blocks share a CU's LDS at k = 64.  The Gram sums run over the rows in
+// order either way.
+__host__ __device__ inline int partial_rows(int k) { return k > 32 ? 8 : 16; }
 
 // Up to two Gram entries per thread the kernel is held to 64 registers, so
 // that eight blocks (32 waves) share a CU and a batch's boundary blocks run in
@@ -295,14 +298,13 @@ void partial_kernel(StoreView st,
                                                            double *__restrict__ T, double rank_tol,
                                                            double xi, int *__restrict__ conv_flag)
 {
-    constexpr int RB = kPartialRows;
     extern __shared__ __align__(16) double smem[];
     const int k = st.k;
+    const int RB = partial_rows(k);
     const int ld = k + 1;                     // leading dimension of the k x k matrices
     double *G = smem;                         // k x k (G_P, then G_Y)
-    double *W1 = G + k * ld;                  // first-stage eigenvectors
-    double *W2 = W1 + k * ld;                 // second-stage rotation
-    double *Us = W2 + k * ld;                 // RB x k staged rows of P = X U Sigma
+    double *W1 = G + k * ld;                  // eigenvectors: first stage, then V~
+    double *Us = W1 + k * ld;                 // RB x k staged rows of P = X U Sigma
     double *Ys = Us + RB * k;                 // RB x k rows of Y = P W1
     __shared__ double cs_sh[kMaxK / 2], sn_sh[kMaxK / 2], dp_sh[kMaxK / 2], dq_sh[kMaxK / 2];
     __shared__ double sig[kMaxK], sblk[kMaxK];
@@ -357,30 +359,23 @@ void partial_kernel(StoreView st,
             }
         }
         __syncthreads();
-        double *Wp = pass == 0 ? W1 : W2;
+        // pass 0 starts W1 at the identity; pass 1 applies its rotations to
+        // W1 itself, which leaves V~ = W1 J there
 #pragma unroll
         for (int x = 0; x < EPT; ++x) {
             const int e = tid + x * kThreads;
             if (e < k * k) {
                 const int a = e / k, b = e % k;
                 G[a * ld + b] = acc[x];
-                Wp[a * ld + b] = (a == b) ? 1.0 : 0.0;
+                if (pass == 0) W1[a * ld + b] = (a == b) ? 1.0 : 0.0;
             }
         }
         __syncthreads();
-        const int sweeps = sym_jacobi(G, Wp, k, ld, cs_sh, sn_sh, dp_sh, dq_sh, &flag_sh, &tr_sh);
+        const int sweeps = sym_jacobi(G, W1, k, ld, cs_sh, sn_sh, dp_sh, dq_sh, &flag_sh, &tr_sh);
         if (sweeps < 0 && tid == 0) atomicOr(conv_flag, 1);
     }
     for (int j = tid; j < k; j += kThreads) sig[j] = sqrt(fmax(G[j * ld + j], 0.0));
-    __syncthreads();                          // sig holds G's diagonal
-    // V~ = W1 W2, written over G (no longer needed)
-    for (int e = tid; e < k * k; e += kThreads) {
-        const int a = e / k, j = e % k;
-        double s = 0.0;
-        for (int l = 0; l < k; ++l) s = fma(W1[a * ld + l], W2[l * ld + j], s);
-        G[a * ld + j] = s;
-    }
-    __syncthreads();
+    __syncthreads();                          // sig holds G's diagonal; V~ is in W1
     double smax = 0.0;
     for (int j = 0; j < k; ++j) smax = fmax(smax, sig[j]);
     // kept triplets: numerically non-zero and within the xi rank of Eq. (1)
@@ -413,14 +408,14 @@ void partial_kernel(StoreView st,
     for (int e = tid; e < k * c; e += kThreads) {
         const int j = e / c, col = e % c;
         double s = 0.0;
-        for (int l = 0; l < k; ++l) s = fma(G[l * ld + j], (double)Vt[(int64_t)l * c + col], s);
+        for (int l = 0; l < k; ++l) s = fma(W1[l * ld + j], (double)Vt[(int64_t)l * c + col], s);
         Mrows[e] = pkeep[j] ? sig[j] * s : 0.0;
     }
     // T = Sigma_(i) V~ Sigma~^+  (k x k, row-major)
     double *Tp = T + (int64_t)pc.t_idx * k * k;
     for (int e = tid; e < k * k; e += kThreads) {
         const int a = e / k, j = e % k;
-        Tp[e] = pkeep[j] ? sblk[a] * G[a * ld + j] / sig[j] : 0.0;
+        Tp[e] = pkeep[j] ? sblk[a] * W1[a * ld + j] / sig[j] : 0.0;
     }
 }
 
@@ -481,7 +476,7 @@ hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx
     if (npartial <= 0) return hipSuccess;
     if (st.k < 1 || st.k > kMaxK) return hipErrorInvalidValue;
     timing_begin("partial", stream);
-    const size_t lds = (size_t)(3 * st.k * (st.k + 1) + 2 * kPartialRows * st.k) * sizeof(double);
+    const size_t lds = (size_t)(2 * st.k * (st.k + 1) + 2 * partial_rows(st.k) * st.k) * sizeof(double);
     const int need = (st.k * st.k + kThreads - 1) / kThreads;
     hipError_t e;
     if (need <= 1) e = run_partial<1>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
