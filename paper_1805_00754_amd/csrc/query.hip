@@ -201,7 +201,8 @@ __device__ __forceinline__ double buf_elem(__amdgpu_buffer_rsrc_t r, int e)
 // runs on the matrix cores (FP64 MFMA 16x16x4): C_i stays in registers for
 // the whole piece as B fragments, so the tile loop reads no coefficients.
 //   1. the tile's rows of U_(i) (contiguous in HBM) are loaded with coalesced
-//      8-byte buffer loads one tile ahead and copied to LDS unchanged;
+//      8-byte buffer loads one tile ahead and copied to LDS (from 32
+//      columns on with the row stride padded to KM + 1, below);
 //   2. A fragments (16 rows x 4 columns) come from LDS; four row blocks times
 //      ceil(k_q / 16) column blocks of 16 x 16 accumulators, KM / 4 steps;
 //   3. the accumulators go back through LDS (row stride k_q) and are written
@@ -244,7 +245,15 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
     constexpr bool TAIL = KM % 16 == 4;
     constexpr int NF = TAIL ? NCB - 1 : NCB;       // full 16-column blocks
     constexpr int NFA = NF > 0 ? NF : 1;
-    extern __shared__ __align__(16) double tile[];    // 64 x KM
+    // From 32 columns on the U tile is stored in LDS at the padded row stride
+    // KM + 1 (at a stride of 32 or 64 doubles the 16 rows of an A fragment
+    // would share one bank pair); below, at the row stride k of HBM, where
+    // the padded form measured slower on the 20-column benchmark batch
+    // (12.2 against 10.8 ms: the lower register count gives a third wave per
+    // SIMD, which slows the store stream).
+    constexpr bool PAD = KM >= 32;
+    constexpr int LDT = KM + 1;                    // row stride of the padded U tile
+    extern __shared__ __align__(16) double tile[];    // U tile, then the output tile
     const int per = (npieces + kXcds - 1) / kXcds;
     const int pos = xcd ? (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds) : (int)blockIdx.x;
     if (pos >= npieces) return;
@@ -277,17 +286,26 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
         const int nr = max(0, min(kProdRows, nrows - row0));
         return buf(Ub + (int64_t)row0 * k, nr * k * (int)sizeof(TU));
     };
+    // Element e = lane + 64 i of a lane's share of the tile sits in row e / KM
+    // and column e mod KM: at e - (e / KM)(KM - k) in HBM (columns past k
+    // read past the range, zero) and at e + e / KM in LDS (stride KM + 1).
+    const int dk = KM - k;
+    auto uoff = [&](int e, int row) { return e - row * KM < k ? e - row * dk : 1 << 27; };
 
     double pre[KM];
     {
         const __amdgpu_buffer_rsrc_t r = urange(0);
 #pragma unroll
-        for (int i = 0; i < KM; ++i) pre[i] = buf_elem<TU, false>(r, lane + i * kProdRows);
+        for (int i = 0; i < KM; ++i) {
+            const int e = lane + i * kProdRows;
+            pre[i] = buf_elem<TU, false>(r, PAD ? uoff(e, e / KM) : e);
+        }
         // dropped stores, as many as a tile issues (below)
         const __amdgpu_buffer_rsrc_t none = buf(out, 0);
-        if constexpr (CONTIG && sizeof(TU) == 8) {
+        if constexpr (CONTIG) {
 #pragma unroll
-            for (int i = 0; i < KM / 2; ++i) buf_store2(none, (lane + i * kProdRows) * 16, 0.0, 0.0);
+            for (int i = 0; i < KM / (sizeof(TU) == 8 ? 2 : 4); ++i)
+                buf_store2(none, (lane + i * kProdRows) * 16, 0.0, 0.0);
         } else {
 #pragma unroll
             for (int i = 0; i < KM; ++i) buf_store(none, (lane + i * kProdRows) * (int)sizeof(TU), (TU)0);
@@ -297,9 +315,21 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
         const int row0 = t * kProdRows;
         const int nr = min(kProdRows, nrows - row0);
         wave_sync();                               // the previous tile's outputs are read
+        if constexpr (PAD) {
+            // the element positions are recomputed per tile (kept out of
+            // registers across tiles)
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            const __amdgpu_buffer_rsrc_t r = urange(row0 + kProdRows);   // empty after the last
 #pragma unroll
-        for (int i = 0; i < KM; ++i) tile[lane + i * kProdRows] = pre[i];
-        {
+            for (int i = 0; i < KM; ++i) {
+                const int e = ln + i * kProdRows, row = e / KM;
+                tile[e + row] = pre[i];
+                pre[i] = buf_elem<TU, true>(r, uoff(e, row));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < KM; ++i) tile[lane + i * kProdRows] = pre[i];
             const __amdgpu_buffer_rsrc_t r = urange(row0 + kProdRows);   // empty after the last
 #pragma unroll
             for (int i = 0; i < KM; ++i) pre[i] = buf_elem<TU, true>(r, lane + i * kProdRows);
@@ -315,8 +345,13 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
 #pragma unroll
             for (int s2 = 0; s2 < KS; ++s2) {
                 const int col = 4 * s2 + lane / 16;
-                const double x = tile[(16 * rb + lane % 16) * k + col];
-                const double a = col < k ? x : 0.0;
+                double a;
+                if constexpr (PAD) {
+                    a = tile[(16 * rb + lane % 16) * LDT + col];   // zero past k
+                } else {
+                    const double x = tile[(16 * rb + lane % 16) * k + col];
+                    a = col < k ? x : 0.0;
+                }
 #pragma unroll
                 for (int cb = 0; cb < NF; ++cb)
                     acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[cb][s2], acc[rb][cb], 0, 0, 0);
@@ -356,9 +391,18 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
                 const int n = nr * kq;
                 if (n & 1) buf_store(r, (n - 1) * 8, tile[n - 1]);
             } else {
+                // FP32 outputs in 16-byte quads, a straddling quad again
+                // element by element
+                typedef float f4 __attribute__((ext_vector_type(4)));
+                typedef unsigned u4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-                for (int i = 0; i < KM; ++i)
-                    buf_store(r, (lane + i * kProdRows) * (int)sizeof(TU), (TU)tile[lane + i * kProdRows]);
+                for (int i = 0; i < KM / 4; ++i) {
+                    const int e = 4 * (lane + i * kProdRows);
+                    const f4 q = {(float)tile[e], (float)tile[e + 1], (float)tile[e + 2], (float)tile[e + 3]};
+                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, q), r, e * 4, 0, 0);
+                }
+                const int n = nr * kq;
+                for (int e = n & ~3; e < n; ++e) buf_store(r, e * 4, (float)tile[e]);
             }
         } else {
             const int n = nr * kq;
@@ -409,7 +453,7 @@ template <int KM, typename TU>
 hipError_t run_blockprod(StoreView st, const Piece *pieces, const int32_t *perm, int npieces,
                          const double *C, void *U, bool contiguous, hipStream_t stream)
 {
-    const size_t lds = (size_t)kProdRows * KM * sizeof(double);
+    const size_t lds = (size_t)kProdRows * (KM >= 32 ? KM + 1 : KM) * sizeof(double);
     const unsigned grid = (unsigned)(kXcds * ((npieces + kXcds - 1) / kXcds));
     TU *out = static_cast<TU *>(U);
     char key[80];
