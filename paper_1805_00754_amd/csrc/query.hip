@@ -197,14 +197,16 @@ __device__ __forceinline__ double buf_elem(__amdgpu_buffer_rsrc_t r, int e)
         return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, e * 4, 0, aux));
 }
 
-// One wave per piece, rows in tiles of 64.  The product of a tile with C_i
+// One wave per piece, rows in tiles of 64 (16 from 48 columns on).  The
+// product of a tile with C_i
 // runs on the matrix cores (FP64 MFMA 16x16x4): C_i stays in registers for
 // the whole piece as B fragments, so the tile loop reads no coefficients.
 //   1. the tile's rows of U_(i) (contiguous in HBM) are loaded with coalesced
 //      8-byte buffer loads one tile ahead and copied to LDS (from 32
 //      columns on with the row stride padded to KM + 1, below);
-//   2. A fragments (16 rows x 4 columns) come from LDS; four row blocks times
-//      ceil(k_q / 16) column blocks of 16 x 16 accumulators, KM / 4 steps;
+//   2. A fragments (16 rows x 4 columns) come from LDS; the tile's row
+//      blocks times ceil(k_q / 16) column blocks of 16 x 16 accumulators,
+//      KM / 4 steps;
 //   3. the accumulators go back through LDS (row stride k_q) and are written
 //      with coalesced 16-byte stores.
 // Operand layout of v_mfma_f64_16x16x4f64 (wave of 64 lanes): A(i, s) in lane
@@ -214,12 +216,13 @@ __device__ __forceinline__ double buf_elem(__amdgpu_buffer_rsrc_t r, int e)
 // range does the bounds check), so the number of memory operations between
 // a tile's prefetch and its use is fixed and the wait for the prefetch does
 // not also wait for the previous tile's stores.  The prologue issues as many
-// dropped stores as a tile does (KM, or KM / 2 16-byte stores for FP64
-// output) to give the first iteration the same count; only a tile of odd
-// length adds one store.
+// dropped 16-byte stores as a tile does to give the first iteration the same
+// count; only a tile whose length is not a whole number of 16-byte groups
+// adds stores.
 // Every output is sum_l U(r, l) C(l, j) over l in order, four terms per
 // step; the padding adds exact zeros.
 constexpr int kProdRows = 64;
+template <int KM> struct ProdRowBlocks { static constexpr int value = KM >= 48 ? 1 : 4; };
 
 // Work-groups are dispatched to the eight XCDs round-robin; work-group w
 // takes position (w mod 8) * per + w / 8 of the block-major order, so each
@@ -253,6 +256,11 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
     // SIMD, which slows the store stream).
     constexpr bool PAD = KM >= 32;
     constexpr int LDT = KM + 1;                    // row stride of the padded U tile
+    // Tiles of 64 rows, or of 16 from 48 columns on, where a 64-row tile's
+    // prefetch and accumulators would leave one wave per SIMD.
+    constexpr int RB = ProdRowBlocks<KM>::value;   // 16-row blocks per tile
+    constexpr int TR = 16 * RB;                    // rows per tile
+    constexpr int PT = TR * KM / kProdRows;        // tile elements per lane
     extern __shared__ __align__(16) double tile[];    // U tile, then the output tile
     const int per = (npieces + kXcds - 1) / kXcds;
     const int pos = xcd ? (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds) : (int)blockIdx.x;
@@ -281,9 +289,9 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
     TU *out = Uout + pc.out_off;
     const int64_t ldu = pc.ldu;
     const int nrows = pc.r1 - pc.r0;
-    const int ntiles = (nrows + kProdRows - 1) / kProdRows;
+    const int ntiles = (nrows + TR - 1) / TR;
     auto urange = [&](int row0) {
-        const int nr = max(0, min(kProdRows, nrows - row0));
+        const int nr = max(0, min(TR, nrows - row0));
         return buf(Ub + (int64_t)row0 * k, nr * k * (int)sizeof(TU));
     };
     // Element e = lane + 64 i of a lane's share of the tile sits in row e / KM
@@ -292,11 +300,11 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
     const int dk = KM - k;
     auto uoff = [&](int e, int row) { return e - row * KM < k ? e - row * dk : 1 << 27; };
 
-    double pre[KM];
+    double pre[PT];
     {
         const __amdgpu_buffer_rsrc_t r = urange(0);
 #pragma unroll
-        for (int i = 0; i < KM; ++i) {
+        for (int i = 0; i < PT; ++i) {
             const int e = lane + i * kProdRows;
             pre[i] = buf_elem<TU, false>(r, PAD ? uoff(e, e / KM) : e);
         }
@@ -304,41 +312,41 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
         const __amdgpu_buffer_rsrc_t none = buf(out, 0);
         if constexpr (CONTIG) {
 #pragma unroll
-            for (int i = 0; i < KM / (sizeof(TU) == 8 ? 2 : 4); ++i)
+            for (int i = 0; i < PT / (sizeof(TU) == 8 ? 2 : 4); ++i)
                 buf_store2(none, (lane + i * kProdRows) * 16, 0.0, 0.0);
         } else {
 #pragma unroll
-            for (int i = 0; i < KM; ++i) buf_store(none, (lane + i * kProdRows) * (int)sizeof(TU), (TU)0);
+            for (int i = 0; i < PT; ++i) buf_store(none, (lane + i * kProdRows) * (int)sizeof(TU), (TU)0);
         }
     }
     for (int t = 0; t < ntiles; ++t) {
-        const int row0 = t * kProdRows;
-        const int nr = min(kProdRows, nrows - row0);
+        const int row0 = t * TR;
+        const int nr = min(TR, nrows - row0);
         wave_sync();                               // the previous tile's outputs are read
         if constexpr (PAD) {
             // the element positions are recomputed per tile (kept out of
             // registers across tiles)
             int ln = lane;
             asm volatile("" : "+v"(ln));
-            const __amdgpu_buffer_rsrc_t r = urange(row0 + kProdRows);   // empty after the last
+            const __amdgpu_buffer_rsrc_t r = urange(row0 + TR);   // empty after the last
 #pragma unroll
-            for (int i = 0; i < KM; ++i) {
+            for (int i = 0; i < PT; ++i) {
                 const int e = ln + i * kProdRows, row = e / KM;
                 tile[e + row] = pre[i];
                 pre[i] = buf_elem<TU, true>(r, uoff(e, row));
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < KM; ++i) tile[lane + i * kProdRows] = pre[i];
-            const __amdgpu_buffer_rsrc_t r = urange(row0 + kProdRows);   // empty after the last
+            for (int i = 0; i < PT; ++i) tile[lane + i * kProdRows] = pre[i];
+            const __amdgpu_buffer_rsrc_t r = urange(row0 + TR);   // empty after the last
 #pragma unroll
-            for (int i = 0; i < KM; ++i) pre[i] = buf_elem<TU, true>(r, lane + i * kProdRows);
+            for (int i = 0; i < PT; ++i) pre[i] = buf_elem<TU, true>(r, lane + i * kProdRows);
         }
         wave_sync();
-        v4d acc[4][NFA];
-        double acct[4];
+        v4d acc[RB][NFA];
+        double acct[RB];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
+        for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
             for (int cb = 0; cb < NF; ++cb) acc[rb][cb] = (v4d){0.0, 0.0, 0.0, 0.0};
             acct[rb] = 0.0;
@@ -361,7 +369,7 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
         }
         wave_sync();                               // every lane has read its A fragments
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
+        for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
             for (int cb = 0; cb < NF; ++cb)
 #pragma unroll
@@ -384,7 +392,7 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
                 // its in-range element, whatever the range check does with
                 // the half past the end.
 #pragma unroll
-                for (int i = 0; i < KM / 2; ++i) {
+                for (int i = 0; i < PT / 2; ++i) {
                     const int e = 2 * (lane + i * kProdRows);
                     buf_store2(r, e * 8, tile[e], tile[e + 1]);
                 }
@@ -396,7 +404,7 @@ __global__ __launch_bounds__(kProdRows) void blockprod_kernel(StoreView st, cons
                 typedef float f4 __attribute__((ext_vector_type(4)));
                 typedef unsigned u4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-                for (int i = 0; i < KM / 4; ++i) {
+                for (int i = 0; i < PT / 4; ++i) {
                     const int e = 4 * (lane + i * kProdRows);
                     const f4 q = {(float)tile[e], (float)tile[e + 1], (float)tile[e + 2], (float)tile[e + 3]};
                     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, q), r, e * 4, 0, 0);
@@ -453,7 +461,7 @@ template <int KM, typename TU>
 hipError_t run_blockprod(StoreView st, const Piece *pieces, const int32_t *perm, int npieces,
                          const double *C, void *U, bool contiguous, hipStream_t stream)
 {
-    const size_t lds = (size_t)kProdRows * (KM >= 32 ? KM + 1 : KM) * sizeof(double);
+    const size_t lds = (size_t)16 * ProdRowBlocks<KM>::value * (KM >= 32 ? KM + 1 : KM) * sizeof(double);
     const unsigned grid = (unsigned)(kXcds * ((npieces + kXcds - 1) / kXcds));
     TU *out = static_cast<TU *>(U);
     char key[80];
