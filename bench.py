@@ -76,7 +76,7 @@ def main():
                          "and 1e5 (the paper's block-size study), one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: there is no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, flush=True)
         sys.exit(2)
 

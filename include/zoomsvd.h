@@ -46,7 +46,7 @@ typedef enum {
     ZS_ENOMEM = -3,    /* device allocation failed, or the arrays exceed the device memory  */
     ZS_ENOCONV = -4,   /* a Jacobi eigen-solve hit its sweep cap (reported by zs_sync_status) */
     ZS_EDEVICE = -5,   /* a HIP runtime call failed                                         */
-    ZS_EUNSUPPORTED = -6 /* a size this build does not handle (c or k above the limits)    */
+    ZS_EUNSUPPORTED = -6 /* a size the library does not handle (c or k above the limits)  */
 } zs_status;
 
 typedef enum { ZS_F64 = 0, ZS_F32 = 1, ZS_BF16 = 2 } zs_dtype;          /* element type of A */
@@ -54,7 +54,7 @@ typedef enum { ZS_MODE_FP64 = 0, ZS_MODE_FP32 = 1, ZS_MODE_BF16 = 2 } zs_mode; /
 
 typedef struct zs_store zs_store;   /* opaque; owns the device-resident U_(i), Sigma_(i), V_(i) */
 
-/* Limits of this build: c <= ZS_MAX_C columns and k <= ZS_MAX_K. */
+/* Limits of the library: c <= ZS_MAX_C columns and k <= ZS_MAX_K. */
 #define ZS_MAX_C 1024
 #define ZS_MAX_K 64
 
