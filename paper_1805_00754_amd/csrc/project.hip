@@ -12,6 +12,8 @@
 //
 // project and stack_project share one tile body (one wave per chunk, tiles of
 // 32 or 64 rows), described at tile_project.
+#include <cstdio>
+
 #include "zs_internal.h"
 
 namespace zs {
@@ -321,16 +323,26 @@ __device__ __forceinline__ void tile_project(const RowFn &row, int rows, int c, 
 
 // stack_project: rows are Sigma_(i) V_(i)^T rows of the store (its element
 // type) for whole blocks, FP64 Partial-SVD rows (scale 1) for boundary blocks.
+constexpr int kStackXcds = 8;
 template <int KQM>
 __device__ __forceinline__ void stack_project_body(StoreView st, const Piece *__restrict__ pieces,
                                                    const double *__restrict__ Mp,
                                                    const StackChunk *__restrict__ chunks,
                                                    const double *__restrict__ Vk,
                                                    double *__restrict__ Y,
-                                                   double *__restrict__ GYpart)
+                                                   double *__restrict__ GYpart, int nchunks,
+                                                   int xcd)
 {
     extern __shared__ __align__(16) double sm[];
-    const StackChunk ch = chunks[blockIdx.x];
+    // Work-groups go to the eight XCDs round-robin.  With xcd set, work-group
+    // w takes chunk (w mod 8) per + w / 8: the chunks are in the order of
+    // their first block, so each XCD works through its own range of blocks
+    // and keeps their stack rows in its L2.  Without, chunk w.
+    const int per = (nchunks + kStackXcds - 1) / kStackXcds;
+    const int pos = xcd ? (int)(blockIdx.x % kStackXcds) * per + (int)(blockIdx.x / kStackXcds)
+                        : (int)blockIdx.x;
+    if (pos >= nchunks) return;
+    const StackChunk ch = chunks[pos];
     const int c = (int)st.c, k = st.k;
     const int vt_type = st.f32 ? kElemF32 : kElemF64;
     const size_t vt_es = st.f32 ? sizeof(float) : sizeof(double);
@@ -377,18 +389,18 @@ template <int KQM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KQM <= 32 ? 2 : 1))) void stack_project_kernel(
     StoreView st, const Piece *__restrict__ pieces, const double *__restrict__ Mp,
     const StackChunk *__restrict__ chunks, const double *__restrict__ Vk, double *__restrict__ Y,
-    double *__restrict__ GYpart)
+    double *__restrict__ GYpart, int nchunks, int xcd)
 {
-    stack_project_body<KQM>(st, pieces, Mp, chunks, Vk, Y, GYpart);
+    stack_project_body<KQM>(st, pieces, Mp, chunks, Vk, Y, GYpart, nchunks, xcd);
 }
 
 template <int KQM>
 __global__ __launch_bounds__(64) void stack_project_wide_kernel(
     StoreView st, const Piece *__restrict__ pieces, const double *__restrict__ Mp,
     const StackChunk *__restrict__ chunks, const double *__restrict__ Vk, double *__restrict__ Y,
-    double *__restrict__ GYpart)
+    double *__restrict__ GYpart, int nchunks, int xcd)
 {
-    stack_project_body<KQM>(st, pieces, Mp, chunks, Vk, Y, GYpart);
+    stack_project_body<KQM>(st, pieces, Mp, chunks, Vk, Y, GYpart, nchunks, xcd);
 }
 
 template <typename TU>
@@ -473,11 +485,20 @@ hipError_t run_stack_project(StoreView st, const Piece *pieces, const double *Mp
     // panel (64 x 17) or Y tile (64 x (kq + 1))
     const int w = kq_max + 1 > kPanel + 1 ? kq_max + 1 : kPanel + 1;
     const size_t lds = (size_t)(64 * w) * sizeof(double);
-    if constexpr (KQM <= 32)
-        stack_project_kernel<KQM><<<nchunks, 64, lds, stream>>>(st, pieces, Mp, chunks, Vk, Y, GYpart);
-    else
-        stack_project_wide_kernel<KQM><<<nchunks, 64, lds, stream>>>(st, pieces, Mp, chunks, Vk, Y, GYpart);
-    return hipGetLastError();
+    char key[64];
+    snprintf(key, sizeof key, "kq=%d c=%d n=%d", kq_max, (int)st.c, tune_bucket(nchunks));
+    return tuned_launch("stack_order", key, 2, 0, stream, [&](int v) {
+        const int xcd = v;
+        const unsigned grid = xcd ? (unsigned)(kStackXcds * ((nchunks + kStackXcds - 1) / kStackXcds))
+                                  : (unsigned)nchunks;
+        if constexpr (KQM <= 32)
+            stack_project_kernel<KQM><<<grid, 64, lds, stream>>>(st, pieces, Mp, chunks, Vk, Y, GYpart,
+                                                                 nchunks, xcd);
+        else
+            stack_project_wide_kernel<KQM><<<grid, 64, lds, stream>>>(st, pieces, Mp, chunks, Vk, Y,
+                                                                      GYpart, nchunks, xcd);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_stack_project(StoreView st, const Piece *pieces, const double *Mp,

@@ -18,7 +18,7 @@ from tests.gpu_common import download_store, say, to_dev
 pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SITES = {"gram_lp_tile": 2, "eig_tri_threads": 2, "blockprod_order": 2}
+SITES = {"gram_lp_tile": 2, "eig_tri_threads": 2, "blockprod_order": 2, "stack_order": 2}
 
 
 def _run(A, tdtype, b, k, mode, ts, te, kq):
