@@ -120,7 +120,10 @@ def test_query_parity_other_widths(t, c, b, k):
 LARGE_C = [(3_000, 200, 600, 24), (4_000, 256, 1000, 32), (2_600, 512, 1300, 48),
            (2_100, 1024, 1050, 64),
            # short last blocks (300 rows) at c = 256 and c = 1024
-           (3_300, 256, 1000, 32), (2_300, 1024, 1000, 64)]
+           (3_300, 256, 1000, 32), (2_300, 1024, 1000, 64),
+           # the first width of each form of the solver (c = 129, 257, 513):
+           # trailing blocks of one element past a 64-column chunk
+           (2_100, 129, 700, 16), (2_200, 257, 900, 40), (2_200, 513, 1100, 20)]
 
 
 @pytest.mark.parametrize("t,c,b,k", LARGE_C)
