@@ -260,3 +260,45 @@ def test_bad_query_raises(sinmix64):
         with pytest.raises(zs.ZSError) as ei:
             zs.zs_query(st, ts, te, kq)
         assert ei.value.status == zs.ZS_ERANGE
+
+
+def test_stores_share_a_stream_workspace():
+    """The query scratch belongs to the (device, stream) pair, not to a store:
+    batches on two stores of different shapes issued back to back on one
+    stream, with no synchronisation between them, and a batch on a store built
+    after the first was freed, give the same bits as each batch run alone."""
+    a = synth.sinusoid_mixture(6_000, 64, sources=6, seed=21, noise="iid", noise_sigma=0.1).A
+    b = synth.sinusoid_mixture(12_000, 128, sources=9, seed=22, noise="iid", noise_sigma=0.1).A
+    da, db = to_dev(a), to_dev(b)
+    sa, sb = zs.zs_store_blocks(da, 500, 10), zs.zs_store_blocks(db, 1_000, 20)
+    rng = synth.rng_for(23)
+    qa = synth.queries_uniform(rng, 6_000, 24, 100, 5_000)
+    qb = synth.queries_uniform(rng, 12_000, 48, 100, 11_000)
+    ka = rng.integers(1, 11, size=24).astype(np.int32)
+    kb = rng.integers(1, 21, size=48).astype(np.int32)
+
+    def host(batch):
+        return [x.cpu().numpy() for x in (batch.U, batch.S, batch.V, batch.k_out)]
+
+    say("alone: store a, then store b")
+    ref_a = host(zs.zs_query_batch(sa, *qa, ka))
+    torch.cuda.synchronize()
+    ref_b = host(zs.zs_query_batch(sb, *qb, kb))
+    torch.cuda.synchronize()
+    say("interleaved on one stream")
+    outs = []
+    for _ in range(2):
+        outs.append((zs.zs_query_batch(sa, *qa, ka), zs.zs_query_batch(sb, *qb, kb)))
+    torch.cuda.synchronize()
+    for oa, ob in outs:
+        for x, y in zip(host(oa), ref_a):
+            np.testing.assert_array_equal(x, y)
+        for x, y in zip(host(ob), ref_b):
+            np.testing.assert_array_equal(x, y)
+    say("a store built after the first is freed")
+    sa.free()
+    sa2 = zs.zs_store_blocks(da, 500, 10)
+    for x, y in zip(host(zs.zs_query_batch(sa2, *qa, ka)), ref_a):
+        np.testing.assert_array_equal(x, y)
+    sa2.free()
+    sb.free()
