@@ -284,13 +284,19 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, int k, const 
 // order either way.
 __host__ __device__ inline int partial_rows(int k) { return k > 32 ? 8 : 16; }
 
-// Up to two Gram entries per thread the kernel is held to 64 registers, so
-// that eight blocks (32 waves) share a CU and a batch's boundary blocks run in
-// one round.
-template <int EPT> struct PartialOcc { static constexpr int waves = EPT <= 2 ? 8 : 1; };
+// From k = 17 on the Gram sums run over 2 x 2 tiles on or below the
+// diagonal, TPT tiles per thread (one up to k = 44): four loads from LDS feed
+// four FMAs, where one entry per thread takes two loads per FMA.  Up to
+// k = 16 (TPT = 0) each thread sums one entry, which keeps more threads busy
+// when the loads are few.  Either way every entry is summed by one thread
+// over the rows in order, so the two forms give the same bits.  With at most
+// one tile per thread the kernel is held to 64 registers, so that eight
+// blocks (32 waves) share a CU and a batch's boundary blocks run in one round.
+template <int TPT> struct PartialOcc { static constexpr int waves = TPT <= 1 ? 8 : 1; };
+constexpr int kPartialTileK = 17;
 
-template <typename TU, int EPT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PartialOcc<EPT>::waves)))
+template <typename TU, int TPT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PartialOcc<TPT>::waves)))
 void partial_kernel(StoreView st,
                                                            const Piece *__restrict__ pieces,
                                                            const int32_t *__restrict__ pidx,
@@ -319,15 +325,31 @@ void partial_kernel(StoreView st,
     const int m = pc.r1 - pc.r0;
     for (int j = tid; j < k; j += kThreads) sblk[j] = st.S[pc.blk * k + j];
 
-    // EPT >= ceil(k^2 / kThreads) Gram entries per thread (a template
-    // parameter, so small k keeps few registers and many blocks per CU)
-    double acc[EPT];
+    // Tile x of this thread: rows 2A, 2A + 1 and columns 2B, 2B + 1 of the
+    // Gram, B <= A, tile number A (A + 1) / 2 + B (an index past k is read
+    // clamped and not written).  Every entry is summed by one thread over
+    // the rows in order, as sum_r fma(P(r, a), P(r, b), s); its mirror has
+    // the same bits.
+    const int kh = (k + 1) / 2;
+    const int ntile = kh * (kh + 1) / 2;
+    // first row and column of tile ti (recomputed where used: fewer live
+    // registers through the eigen-solves)
+    auto tile_a = [](int ti) {
+        int A = (int)((sqrt(8.0 * ti + 1.0) - 1.0) * 0.5);
+        while ((A + 1) * (A + 2) / 2 <= ti) ++A;
+        while (A * (A + 1) / 2 > ti) --A;
+        return A;
+    };
+    constexpr int NT = TPT > 0 ? TPT : 1;
+    double acc[NT][4];
     // Two passes over the kept rows.  Pass 0: G_P = P^T P.  Pass 1, after the
     // first eigen-solve: G_Y = Y^T Y with Y = P W1 recomputed from the rows,
     // so the singular values of P come out with relative accuracy.
     for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
-        for (int x = 0; x < EPT; ++x) acc[x] = 0.0;
+        for (int x = 0; x < NT; ++x)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[x][v] = 0.0;
         for (int r0 = 0; r0 < m; r0 += RB) {
             const int nr = min(RB, m - r0);
             __syncthreads();
@@ -338,38 +360,96 @@ void partial_kernel(StoreView st,
             __syncthreads();
             const double *R = Us;
             if (pass == 1) {
-                for (int e = tid; e < nr * k; e += kThreads) {
-                    const int rr = e / k, j = e % k;
-                    double s = 0.0;
-                    for (int a = 0; a < k; ++a) s = fma(Us[rr * k + a], W1[a * ld + j], s);
-                    Ys[e] = s;
+                if constexpr (TPT == 0) {
+                    for (int e = tid; e < nr * k; e += kThreads) {
+                        const int rr = e / k, j = e % k;
+                        double s = 0.0;
+                        for (int a = 0; a < k; ++a) s = fma(Us[rr * k + a], W1[a * ld + j], s);
+                        Ys[e] = s;
+                    }
+                } else {
+                    // Y = P W1 in 2 x 2 tiles (rows i0, i0 + 1; columns j0, j0 + 1),
+                    // each output summed over a in order
+                    const int ntc = (k + 1) / 2;
+                    for (int t = tid; t < ((nr + 1) / 2) * ntc; t += kThreads) {
+                        const int i0 = 2 * (t / ntc), j0 = 2 * (t % ntc);
+                        const int i1 = min(i0 + 1, nr - 1), j1 = min(j0 + 1, k - 1);
+                        double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+                        for (int a = 0; a < k; ++a) {
+                            const double u0 = Us[i0 * k + a], u1 = Us[i1 * k + a];
+                            const double w0 = W1[a * ld + j0], w1 = W1[a * ld + j1];
+                            s00 = fma(u0, w0, s00);
+                            s01 = fma(u0, w1, s01);
+                            s10 = fma(u1, w0, s10);
+                            s11 = fma(u1, w1, s11);
+                        }
+                        Ys[i0 * k + j0] = s00;
+                        if (j0 + 1 < k) Ys[i0 * k + j0 + 1] = s01;
+                        if (i0 + 1 < nr) {
+                            Ys[(i0 + 1) * k + j0] = s10;
+                            if (j0 + 1 < k) Ys[(i0 + 1) * k + j0 + 1] = s11;
+                        }
+                    }
                 }
                 __syncthreads();
                 R = Ys;
             }
-#pragma unroll
-            for (int x = 0; x < EPT; ++x) {
-                const int e = tid + x * kThreads;
-                if (e < k * k) {
-                    const int a = e / k, b = e % k;
-                    double s = acc[x];
+            if constexpr (TPT == 0) {
+                if (tid < k * k) {
+                    const int a = tid / k, b = tid % k;
+                    double s = acc[0][0];
                     for (int rr = 0; rr < nr; ++rr) s = fma(R[rr * k + a], R[rr * k + b], s);
-                    acc[x] = s;
+                    acc[0][0] = s;
+                }
+            } else {
+#pragma unroll
+                for (int x = 0; x < TPT; ++x) {
+                    const int ti = tid + x * kThreads;
+                    if (ti < ntile) {
+                        const int A = tile_a(ti);
+                        const int a0 = 2 * A, a1 = min(a0 + 1, k - 1);
+                        const int b0 = 2 * (ti - A * (A + 1) / 2), b1 = min(b0 + 1, k - 1);
+                        double s00 = acc[x][0], s01 = acc[x][1], s10 = acc[x][2], s11 = acc[x][3];
+                        for (int rr = 0; rr < nr; ++rr) {
+                            const double *row = R + rr * k;
+                            const double p0 = row[a0], p1 = row[a1], q0 = row[b0], q1 = row[b1];
+                            s00 = fma(p0, q0, s00);
+                            s01 = fma(p0, q1, s01);
+                            s10 = fma(p1, q0, s10);
+                            s11 = fma(p1, q1, s11);
+                        }
+                        acc[x][0] = s00;
+                        acc[x][1] = s01;
+                        acc[x][2] = s10;
+                        acc[x][3] = s11;
+                    }
                 }
             }
         }
         __syncthreads();
         // pass 0 starts W1 at the identity; pass 1 applies its rotations to
         // W1 itself, which leaves V~ = W1 J there
+        if constexpr (TPT == 0) {
+            if (tid < k * k) G[(tid / k) * ld + tid % k] = acc[0][0];
+        } else {
 #pragma unroll
-        for (int x = 0; x < EPT; ++x) {
-            const int e = tid + x * kThreads;
-            if (e < k * k) {
-                const int a = e / k, b = e % k;
-                G[a * ld + b] = acc[x];
-                if (pass == 0) W1[a * ld + b] = (a == b) ? 1.0 : 0.0;
+            for (int x = 0; x < TPT; ++x) {
+                const int ti = tid + x * kThreads;
+                if (ti < ntile) {
+                    const int A = tile_a(ti);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int a = 2 * A + v / 2, b = 2 * (ti - A * (A + 1) / 2) + v % 2;
+                        if (a < k && b < k) {
+                            G[a * ld + b] = acc[x][v];
+                            G[b * ld + a] = acc[x][v];
+                        }
+                    }
+                }
             }
         }
+        if (pass == 0)
+            for (int e = tid; e < k * k; e += kThreads) W1[(e / k) * ld + e % k] = (e / k == e % k) ? 1.0 : 0.0;
         __syncthreads();
         const int sweeps = sym_jacobi(G, W1, k, ld, cs_sh, sn_sh, dp_sh, dq_sh, &flag_sh, &tr_sh);
         if (sweeps < 0 && tid == 0) atomicOr(conv_flag, 1);
@@ -449,20 +529,20 @@ hipError_t launch_finalize(int c, int k, const Prob *probs, int nprob, int kk_ma
 
 namespace {
 
-template <int EPT>
+template <int TPT>
 hipError_t run_partial(StoreView st, const Piece *pieces, const int32_t *pidx, int npartial,
                        double *Mp, double *T, double rank_tol, double xi, int *conv_flag,
                        size_t lds, hipStream_t stream)
 {
     static size_t cur_f = 0, cur_d = 0;   // one limit per instantiation
-    hipError_t e = st.f32 ? ensure_lds((const void *)partial_kernel<float, EPT>, lds, cur_f)
-                          : ensure_lds((const void *)partial_kernel<double, EPT>, lds, cur_d);
+    hipError_t e = st.f32 ? ensure_lds((const void *)partial_kernel<float, TPT>, lds, cur_f)
+                          : ensure_lds((const void *)partial_kernel<double, TPT>, lds, cur_d);
     if (e != hipSuccess) return e;
     if (st.f32)
-        partial_kernel<float, EPT><<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T,
+        partial_kernel<float, TPT><<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T,
                                                                         rank_tol, xi, conv_flag);
     else
-        partial_kernel<double, EPT><<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T,
+        partial_kernel<double, TPT><<<npartial, kThreads, lds, stream>>>(st, pieces, pidx, Mp, T,
                                                                          rank_tol, xi, conv_flag);
     return hipGetLastError();
 }
@@ -477,13 +557,13 @@ hipError_t launch_partial(StoreView st, const Piece *pieces, const int32_t *pidx
     if (st.k < 1 || st.k > kMaxK) return hipErrorInvalidValue;
     timing_begin("partial", stream);
     const size_t lds = (size_t)(2 * st.k * (st.k + 1) + 2 * partial_rows(st.k) * st.k) * sizeof(double);
-    const int need = (st.k * st.k + kThreads - 1) / kThreads;
+    const int kh = (st.k + 1) / 2;
+    const int need = (kh * (kh + 1) / 2 + kThreads - 1) / kThreads;   // 2 x 2 tiles per thread
     hipError_t e;
-    if (need <= 1) e = run_partial<1>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
+    if (st.k < kPartialTileK) e = run_partial<0>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
+    else if (need <= 1) e = run_partial<1>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
     else if (need <= 2) e = run_partial<2>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
-    else if (need <= 4) e = run_partial<4>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
-    else if (need <= 8) e = run_partial<8>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
-    else e = run_partial<16>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
+    else e = run_partial<3>(st, pieces, pidx, npartial, Mp, T, rank_tol, xi, conv_flag, lds, stream);
     timing_end("partial", stream);
     return e;
 }
