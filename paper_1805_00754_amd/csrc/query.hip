@@ -121,11 +121,38 @@ __global__ __launch_bounds__(kThreads) void coef_kernel(int k, const Piece *__re
         }
         if (p + 1 < ch.npieces) fetch(p + 1);   // consumed after this piece's products
         __syncthreads();
-        for (int e = tid; e < k * kq; e += kThreads) {
-            const int l = e / kq, j = e % kq;
-            double s = 0.0;
-            for (int m = 0; m < kq; ++m) s = fma(Ys[l * kq + m], Fs[m * kq + j], s);
-            Ur[e] = s;
+        // U_r(i) = Y_i F.  From k_q = 17 on in 2 x 2 tiles (rows l0, l0 + 1;
+        // columns j0, j0 + 1), where four LDS loads feed four FMAs; below, one
+        // output per thread keeps more threads busy.  Either way each output
+        // is summed over m in order by one thread (the same bits).
+        if (kq < 17) {
+            for (int e = tid; e < k * kq; e += kThreads) {
+                const int l = e / kq, j = e % kq;
+                double s = 0.0;
+                for (int m = 0; m < kq; ++m) s = fma(Ys[l * kq + m], Fs[m * kq + j], s);
+                Ur[e] = s;
+            }
+        } else {
+            const int ntc = (kq + 1) / 2;
+            for (int t = tid; t < ((k + 1) / 2) * ntc; t += kThreads) {
+                const int l0 = 2 * (t / ntc), j0 = 2 * (t % ntc);
+                const int l1 = min(l0 + 1, k - 1), j1 = min(j0 + 1, kq - 1);
+                double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+                for (int m = 0; m < kq; ++m) {
+                    const double y0 = Ys[l0 * kq + m], y1 = Ys[l1 * kq + m];
+                    const double f0 = Fs[m * kq + j0], f1 = Fs[m * kq + j1];
+                    s00 = fma(y0, f0, s00);
+                    s01 = fma(y0, f1, s01);
+                    s10 = fma(y1, f0, s10);
+                    s11 = fma(y1, f1, s11);
+                }
+                Ur[l0 * kq + j0] = s00;
+                if (j0 + 1 < kq) Ur[l0 * kq + j0 + 1] = s01;
+                if (l0 + 1 < k) {
+                    Ur[(l0 + 1) * kq + j0] = s10;
+                    if (j0 + 1 < kq) Ur[(l0 + 1) * kq + j0 + 1] = s11;
+                }
+            }
         }
         __syncthreads();
         double *Cp = C + pc.c_off;
