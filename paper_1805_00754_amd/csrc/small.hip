@@ -294,6 +294,8 @@ __host__ __device__ inline int partial_rows(int k) { return k > 32 ? 8 : 16; }
 // blocks (32 waves) share a CU and a batch's boundary blocks run in one round.
 template <int TPT> struct PartialOcc { static constexpr int waves = TPT <= 1 ? 8 : 1; };
 constexpr int kPartialTileK = 17;
+static_assert((kPartialTileK - 1) * (kPartialTileK - 1) <= kThreads,
+              "one Gram entry per thread below the tile threshold");
 
 template <typename TU, int TPT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PartialOcc<TPT>::waves)))
@@ -332,8 +334,8 @@ void partial_kernel(StoreView st,
     // the same bits.
     const int kh = (k + 1) / 2;
     const int ntile = kh * (kh + 1) / 2;
-    // first row and column of tile ti (recomputed where used: fewer live
-    // registers through the eigen-solves)
+    // tile row A of tile ti, whose tile column is ti - A (A + 1) / 2
+    // (recomputed where used: fewer live registers through the eigen-solves)
     auto tile_a = [](int ti) {
         int A = (int)((sqrt(8.0 * ti + 1.0) - 1.0) * 0.5);
         while ((A + 1) * (A + 2) / 2 <= ti) ++A;
