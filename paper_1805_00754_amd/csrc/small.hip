@@ -10,6 +10,8 @@
 //  * partial: Partial-SVD of a boundary block (Alg. 3, Eqs. (5)-(6)):
 //    P = X U_(i) Sigma_(i),  P^T P = V~ Sigma~^2 V~^T, the block's stack rows
 //    Sigma~ V~^T V_(i)^T, and T = Sigma_(i) V~ Sigma~^+ so that U' = X U_(i) T.
+#include <climits>
+
 #include "zs_internal.h"
 
 namespace zs {
@@ -183,6 +185,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, int k, const 
     __shared__ int flag_sh;
     __shared__ double tr_sh;
     __shared__ double red[kThreads];
+    __shared__ int pidx_sh[kThreads];
 
     const Prob P = probs[blockIdx.x];
     const int kk = P.kk;
@@ -242,15 +245,36 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int c, int k, const 
     }
     __threadfence_block();
     __syncthreads();
-    // sign rule: largest |v| entry (lowest index on ties) made positive
-    for (int j = tid; j < kk; j += kThreads) {
-        int am = 0;
-        double vm = -1.0;
-        for (int a = 0; a < c; ++a) {
-            const double v = fabs(Vn[(int64_t)a * kk + j]);
-            if (v > vm) { vm = v; am = a; }
+    // sign rule: largest |v| entry (lowest index on ties) made positive.
+    // nsub (at most 16) threads per column each scan the rows a = sub mod
+    // nsub in order (the first of equal maxima kept), then one thread per
+    // column combines the partial maxima, equal values going to the lower
+    // row: the entry a single scan over all rows would pick.
+    {
+        const int nsub = kk > 0 ? min(kThreads / kk, 16) : 1;
+        if (tid < nsub * kk) {
+            const int j = tid % kk, sub = tid / kk;
+            int am = INT_MAX;
+            double vm = -1.0;
+            for (int a = sub; a < c; a += nsub) {
+                const double v = fabs(Vn[(int64_t)a * kk + j]);
+                if (v > vm) { vm = v; am = a; }
+            }
+            red[tid] = vm;
+            pidx_sh[tid] = am;
         }
-        flip[j] = Vn[(int64_t)am * kk + j] < 0.0 ? -1.0 : 1.0;
+        __syncthreads();
+        for (int j = tid; j < kk; j += kThreads) {
+            int am = INT_MAX;
+            double vm = -1.0;
+            for (int sub = 0; sub < nsub; ++sub) {
+                const double v = red[sub * kk + j];
+                const int a = pidx_sh[sub * kk + j];
+                if (v > vm || (v == vm && a < am)) { vm = v; am = a; }
+            }
+            if (am == INT_MAX) am = 0;        // no entry above -1 (all NaN)
+            flip[j] = Vn[(int64_t)am * kk + j] < 0.0 ? -1.0 : 1.0;
+        }
     }
     __syncthreads();
     for (int e = tid; e < c * kk; e += kThreads) {
