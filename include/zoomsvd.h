@@ -283,6 +283,18 @@ void zs_store_graph_free(zs_store_graph *g);
  * a no-op. */
 void zs_store_free(zs_store *st);
 
+/*
+ * zs_release_workspaces -- returns the scratch the library keeps for `stream`
+ * on the current device: the storage phase's and the queries' workspaces,
+ * which otherwise grow to the largest call the stream has run and stay for
+ * the life of the process.  Waits for `stream` first.  For callers that
+ * retire a stream, or that need the memory back between phases.  The next
+ * call on the stream allocates again; captured graphs keep their own
+ * scratch and are not affected.  ZS_OK when nothing was kept; ZS_EDEVICE if
+ * the stream cannot be synchronised.
+ */
+zs_status zs_release_workspaces(hipStream_t stream);
+
 /* Device bytes held by the store: the block factors (8 or 4 bytes per element
  * by mode) and the Gram tree of the
  * blocks (2 n2 c x c FP64 matrices, n2 = smallest power of two >= nb), not the

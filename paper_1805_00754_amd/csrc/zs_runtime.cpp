@@ -102,6 +102,7 @@ struct Workspace {
         if (host) (void)hipHostFree(host);
         if (copied) (void)hipEventDestroy(copied);
         host = nullptr;
+        host_bytes = 0;
         copied = nullptr;
     }
 };
@@ -139,6 +140,16 @@ struct StoreWork {
     void *host = nullptr;        // pinned staging of the descriptors
     size_t host_bytes = 0;
     hipEvent_t copied = nullptr; // the last upload from `host` has completed
+    void release()
+    {
+        Gpart.release(); Vk.release(); GY.release(); F.release(); Ysc.release(); Big.release();
+        Rows.release(); desc.release();
+        if (host) (void)hipHostFree(host);
+        if (copied) (void)hipEventDestroy(copied);
+        host = nullptr;
+        host_bytes = 0;
+        copied = nullptr;
+    }
 };
 std::mutex g_swmu;
 std::map<std::pair<int, hipStream_t>, StoreWork *> g_sw;
@@ -1299,6 +1310,38 @@ zs_status zs_store_graph_launch(zs_store_graph *g, hipStream_t stream)
 {
     if (!g || !g->exec) return fail(ZS_EINVAL, "graph is null");
     HIP_TRY(hipGraphLaunch(g->exec, stream));
+    return ZS_OK;
+}
+
+zs_status zs_release_workspaces(hipStream_t stream)
+{
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    StoreWork *sw = nullptr;
+    QueryWork *qw = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_swmu);
+        auto it = g_sw.find({device, stream});
+        if (it != g_sw.end()) sw = it->second;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_qwmu);
+        auto it = g_qw.find({device, stream});
+        if (it != g_qw.end()) qw = it->second;
+    }
+    // The entries stay in their maps (a call that has already looked one up
+    // may be waiting on its lock); only their memory is returned, and it
+    // grows again on the next call on the stream.
+    if (sw) {
+        std::lock_guard<std::mutex> lk(sw->mu);
+        HIP_TRY(hipStreamSynchronize(stream));
+        sw->release();
+    }
+    if (qw) {
+        std::lock_guard<std::recursive_mutex> lk(qw->mu);
+        HIP_TRY(hipStreamSynchronize(stream));
+        qw->w.release();
+    }
     return ZS_OK;
 }
 

@@ -33,7 +33,8 @@ EXPORTED = ["zs_store_blocks", "zs_store_blocks_xi", "zs_store_append", "zs_wind
             "zs_query", "zs_query_noalloc", "zs_query_scratch_bytes", "zs_query_batch",
             "zs_query_batch_graph",
             "zs_batch_graph_launch", "zs_batch_graph_free", "zs_store_graph_create",
-            "zs_store_graph_launch", "zs_store_graph_free", "zs_store_free", "zs_store_bytes",
+            "zs_store_graph_launch", "zs_store_graph_free", "zs_store_free", "zs_release_workspaces",
+            "zs_store_bytes",
             "zs_store_info", "zs_store_get_block", "zs_sync_status", "zs_last_error", "zs_version",
             "zs_timing_enable", "zs_timing_reset", "zs_timing_get", "zs_set_sweep_cap", "zs_autotune",
             "zs_autotune_force", "zs_autotune_table"]
@@ -93,6 +94,7 @@ def load(path: str | None = None):
         lib.zs_store_info.argtypes = [_vp] + [_vp] * 6
         lib.zs_store_get_block.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp, _vp]
         lib.zs_sync_status.argtypes = [_vp, _vp]
+        lib.zs_release_workspaces.argtypes = [_vp]
         lib.zs_last_error.restype = ctypes.c_char_p
         lib.zs_version.restype = ctypes.c_char_p
         lib.zs_timing_enable.argtypes = [ctypes.c_int]
@@ -111,7 +113,7 @@ def load(path: str | None = None):
                      "zs_store_info",
                      "zs_store_get_block", "zs_sync_status", "zs_timing_get",
                      "zs_query_batch_graph", "zs_batch_graph_launch", "zs_store_graph_create",
-                     "zs_store_graph_launch"):
+                     "zs_store_graph_launch", "zs_release_workspaces"):
             getattr(lib, name).restype = ctypes.c_int
         if path is None:
             _lib = lib
@@ -417,6 +419,12 @@ def zs_store_bytes(st: Store) -> int:
 
 def zs_sync_status(st: Store, stream=None):
     _check(load().zs_sync_status(_vp(st.handle), _vp(_stream(stream))))
+
+
+def zs_release_workspaces(stream=None):
+    """Return the scratch the library keeps for a stream (storage phase and
+    queries); the next call on the stream allocates again."""
+    _check(load().zs_release_workspaces(_vp(_stream(stream))))
 
 
 def zs_timing_enable(on: bool = True):

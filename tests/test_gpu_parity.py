@@ -302,3 +302,33 @@ def test_stores_share_a_stream_workspace():
         np.testing.assert_array_equal(x, y)
     sa2.free()
     sb.free()
+
+
+def test_release_workspaces_then_reuse():
+    """zs_release_workspaces returns a stream's scratch; stores and batches run
+    on the stream afterwards give the same bits as before, and releasing a
+    stream that has nothing kept (or releasing twice) is a no-op."""
+    a = synth.sinusoid_mixture(8_000, 96, sources=7, seed=24, noise="iid", noise_sigma=0.1).A
+    da = to_dev(a)
+    rng = synth.rng_for(25)
+    ts, te = synth.queries_uniform(rng, 8_000, 32, 100, 7_000)
+    kq = rng.integers(1, 13, size=32).astype(np.int32)
+
+    def run():
+        st = zs.zs_store_blocks(da, 700, 12)
+        out = zs.zs_query_batch(st, ts, te, kq)
+        torch.cuda.synchronize()
+        blk = [x.cpu().numpy() for x in zs.zs_store_get_block(st, 5)]
+        res = [x.cpu().numpy() for x in (out.U, out.S, out.V, out.k_out)] + blk
+        st.free()
+        return res
+
+    say("before release")
+    ref = run()
+    zs.zs_release_workspaces()
+    zs.zs_release_workspaces()
+    say("after release")
+    for x, y in zip(run(), ref):
+        np.testing.assert_array_equal(x, y)
+    side = torch.cuda.Stream()
+    zs.zs_release_workspaces(side)            # nothing kept for this stream
