@@ -174,7 +174,7 @@ zs_status zs_query_noalloc(const zs_store *st, int64_t t_s, int64_t t_e, int32_t
  * descriptors): with the outputs, what an admission policy must budget per
  * query.  There is one workspace per device and stream, shared by every
  * store queried on that stream; it grows to the largest batch the stream has
- * run and is kept for the life of the process.  Returns -1 for a null store or a
+ * run and is kept until zs_release_workspaces.  Returns -1 for a null store or a
  * range or rank that zs_query would reject.
  */
 int64_t zs_query_scratch_bytes(const zs_store *st, int64_t t_s, int64_t t_e, int32_t k_q);
