@@ -110,7 +110,7 @@ struct Workspace {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Scratch of the query pipeline, one per (device, stream), grow-only and kept
-// for the life of the process like the storage phase's, so that queries on a
+// until zs_release_workspaces like the storage phase's, so that queries on a
 // new store do not allocate again (a batch of the 10^6 x 128 workload on a
 // fresh store spent about 0.5 ms in the allocations of its own workspace).
 // Calls on one stream are ordered on the device; the lock orders the host
@@ -132,7 +132,7 @@ QueryWork *query_work(int device, hipStream_t stream)
 }
 
 // Scratch of the storage phase, one per (device, stream), grow-only and kept
-// for the life of the process, so that repeated stores do not allocate.  A
+// until zs_release_workspaces, so that repeated stores do not allocate.  A
 // store call holds its entry's lock until the stream has synchronised.
 struct StoreWork {
     std::mutex mu;
