@@ -28,7 +28,8 @@ _lock = threading.Lock()
 _lib = None
 
 # Numerical-rank threshold, relative to sigma_1 of the matrix being
-# decomposed (the paper is silent; see the readings in the design doc).
+# decomposed.  The paper does not fix one; singular values below this
+# fraction of sigma_1 are taken as numerically zero.
 RANK_TOL = 1e-11
 
 CFLAGS = ["-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared"]
