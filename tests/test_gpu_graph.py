@@ -102,3 +102,29 @@ def test_store_graph_replays_equal_eager_store(name, mode, tdtype):
             assert torch.equal(x, y)
     g.free()
     g.st.free()
+
+
+def test_graph_replays_after_workspaces_released():
+    """A captured batch owns its scratch: releasing the stream's workspaces
+    (zs_release_workspaces) leaves its replays bitwise equal to the eager
+    batch, and eager calls afterwards allocate again."""
+    zs.load()
+    ser, cfg = synth.workload("sinmix_10k_x64_f64")
+    st = zs.zs_store_blocks(to_dev(ser.A), cfg["b"], cfg["k"])
+    rng = synth.rng_for(93)
+    ts, te = synth.queries_uniform(rng, st.t, 16, 50, 6_000)
+    kq = np.full(16, cfg["k"], np.int32)
+    ref = _outputs(zs.zs_query_batch(st, ts, te, kq))
+    g = zs.zs_query_batch_graph(st, ts, te, kq)
+    zs.zs_release_workspaces()
+    say("replay after release")
+    for x in (g.out.U, g.out.S, g.out.V):
+        x.zero_()
+    torch.cuda.synchronize()
+    g.launch()
+    for a, b in zip(_outputs(g.out), ref):
+        np.testing.assert_array_equal(a, b)
+    for a, b in zip(_outputs(zs.zs_query_batch(st, ts, te, kq)), ref):
+        np.testing.assert_array_equal(a, b)
+    g.free()
+    st.free()
