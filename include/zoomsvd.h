@@ -24,7 +24,10 @@
  *   - Every call enqueues its GPU work on `stream` and returns without waiting
  *     for it, except where noted.  Outputs are valid once the stream has
  *     reached that point.  The store is immutable after zs_store_blocks, so
- *     queries on different streams may run concurrently.
+ *     queries on different streams may run concurrently.  The library keeps
+ *     scratch per device and stream; calls on one stream from several host
+ *     threads take turns in the library's host part, and calls on different
+ *     streams do not wait for each other.
  *   - Calls return a zs_status and never throw or abort.  On error nothing is
  *     written to the outputs; zs_last_error() gives a message for the calling
  *     thread.
@@ -207,7 +210,7 @@ zs_status zs_query_batch(const zs_store *st, int32_t nq, const int64_t *t_s, con
  *   sim         device, n_windows doubles: sim[w - 1] = <u_base, u_w> /
  *               (|u_base| |u_w|), 0 when either range has rank 0.  Signs
  *               follow the sign rule of the query outputs.
- *   The windows' factors go to scratch of the store for this stream (n
+ *   The windows' factors go to the library's scratch for this stream (n
  *   rows per window), not to the caller.  Asynchronous on `stream`.  Errors as
  *   in zs_query_batch, plus ZS_EINVAL for stride < 1 or n_windows < 1.
  */
